@@ -1,0 +1,165 @@
+/*
+ * libdda — the CG-FFT discrete dipole approximation on one MI355X (gfx950).
+ *
+ * The library solves the DDA system of the paper's Eq. 1,
+ *
+ *     alpha_n^{-1} P_n - sum_{m != n} G(r_n - r_m) P_m = E_inc,n ,
+ *
+ * written in Gaussian units with lattice spacing d = 1 (the paper's
+ * normalisation k^2/eps0 * A differs by a global constant; cross sections are
+ * identical), for dipoles on the occupied sites of a K x J x P cubic lattice.
+ * The off-diagonal part is applied as a convolution: the block-Toeplitz tensor
+ * is embedded in a zero-padded level-three circulant (Sec. 3, Appendix A) and
+ * every 3D DFT runs as ensembles of 1D transforms that skip the all-zero lines
+ * and planes (Sec. 3, Table 2).
+ *
+ * Conventions
+ *  - Lattice index: site (i, j, k) has linear index n = k*J*K + j*K + i
+ *    (Appendix A).  Dipoles are the occupied sites in increasing n.
+ *  - Vectors are component-major [nrhs][3][N_d] of interleaved complex
+ *    (re, im): complex128 for DDA_FP64, complex64 for DDA_FP32 (the x0/x1/x2
+ *    split of Sec. 3).  Compatible with torch.complex128/complex64.
+ *  - Pointers named *_dev are device pointers on the library's device; all
+ *    other pointers are host pointers.  The caller owns every buffer passed in;
+ *    the library owns the handles' internal storage and frees it in
+ *    *_destroy / dda_close.
+ *  - Device work is enqueued on the caller's HIP stream (NULL = the default
+ *    stream).  Calls that return host results synchronise that stream.
+ *  - Errors: every int-returning call returns DDA_OK or a negative code and
+ *    sets a thread-local message readable with dda_last_error().  No call
+ *    throws.  One target must not be used from two threads at once.
+ */
+#ifndef DDA_H
+#define DDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DDA_OK = 0,
+  DDA_EINVAL = -1,   /* invalid argument (sizes, poles of alpha, NULL buffers) */
+  DDA_ENOMEM = -2,   /* device allocation failed                               */
+  DDA_EDEVICE = -3,  /* HIP runtime error                                      */
+  DDA_ENOTCONV = -4, /* a right-hand side missed the tolerance                 */
+  DDA_ESTATE = -5    /* call out of order (e.g. matvec before the spectrum)    */
+};
+
+enum { DDA_FP64 = 0, DDA_FP32 = 1 };                       /* vector precision   */
+enum { DDA_POL_CM = 0, DDA_POL_RR = 1, DDA_POL_LDR = 2 };  /* polarisability     */
+enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1 };                /* Krylov solver      */
+enum { DDA_SOLVE_FP64 = 0, DDA_SOLVE_MIXED = 1 };          /* solve precision    */
+
+typedef struct dda_lib dda_lib;
+typedef struct dda_target dda_target;
+
+/* Open the library on HIP device `hip_device`.  `tune_cache_path` (nullable)
+ * names a text file where the FFT-schedule autotuner keeps its choices. */
+int dda_open(int hip_device, const char *tune_cache_path, dda_lib **out);
+void dda_close(dda_lib *lib);
+
+/* A target on a K x J x P lattice (K, J, P >= 1) with wavenumber kd > 0 in
+ * units of the lattice spacing.  Chooses the padded FFT sizes
+ * K'' >= 2K-1, J'' >= 2J-1, P'' >= 2P-1 (Sec. 3: any size >= 2n-1 embeds the
+ * Toeplitz matrix in a circulant; the smallest 2^a 3^b 5^c length is used). */
+int dda_target_create(dda_lib *lib, int K, int J, int P, double kd, dda_target **out);
+void dda_target_destroy(dda_target *t);
+
+/* Occupancy: occ[K*J*P] (0/1, linear index order).  Returns N_d >= 1 in
+ * *nd_out.  Invalidates polarisabilities. */
+int dda_set_occupancy(dda_target *t, const uint8_t *occ, int64_t *nd_out);
+
+/* Per-dipole permittivity eps[2*N_d] (re, im) and a polarisability
+ * prescription.  The paper names the radiative-reaction correction and the
+ * lattice dispersion relation (Sec. 1) without formulas; the published ones are
+ * used (d = 1):
+ *   CM : alpha^{-1} = (4 pi / 3)(eps + 2)/(eps - 1)
+ *   RR : CM - (2/3) i kd^3
+ *   LDR: CM + (b1 + b2 eps + b3 S eps) kd^2 - (2/3) i kd^3,  S = sum_a (khat_a ehat_a)^2
+ * (S is per right-hand side and passed with each call).  DDA_EINVAL for
+ * eps = 1 or a non-finite alpha^{-1}.  Enables dda_grad_cabs_eps. */
+int dda_set_permittivity(dda_target *t, const double *eps, int prescription);
+
+/* Per-dipole polarisability alpha[2*N_d] (re, im), used as given. */
+int dda_set_polarizability(dda_target *t, const double *alpha);
+
+/* Interaction spectrum (Sec. 3): the six tensor components' first columns
+ * t = -G on [0,K)x[0,J)x[0,P), implicit Toeplitz-to-circulant conversion with
+ * the Table 1 signs, 1D DFTs along x (J*P lines), y (K_h*P) and z (K_h*J_h),
+ * keeping the unique octant of n_h = n''/2 + 1 entries per axis.  Built in
+ * FP64; the FP32 copy is the FP64 one rounded to nearest even. */
+int dda_build_spectrum(dda_target *t, void *hip_stream);
+
+/* y = A x (Eq. 1) for nrhs right-hand sides, FP64 or FP32 vectors.
+ * S: host [nrhs] LDR orientation factors (NULL = 0).
+ * jacobi != 0 applies the symmetric Point-Jacobi form D^{-1/2} A D^{-1/2},
+ * D = diag(alpha^{-1}). */
+int dda_matvec(dda_target *t, int precision, int nrhs, const double *S, int jacobi, const void *x_dev,
+               void *y_dev, void *hip_stream);
+
+typedef struct {
+  int solver;        /* DDA_BICGSTAB or DDA_QMR_SYM                               */
+  int precision;     /* DDA_SOLVE_FP64, or DDA_SOLVE_MIXED (FP32 inner, FP64 outer) */
+  int max_iter;      /* total inner iterations per right-hand side (<= 0: 10000)  */
+  int max_outer;     /* refinement steps (<= 0: 20)                               */
+  double tol;        /* ||E - A P|| / ||E|| target, true FP64 residual             */
+  double inner_tol;  /* relative tolerance of each FP32 inner solve (<= 0: 1e-3)   */
+  int jacobi;        /* Point-Jacobi preconditioning (symmetric form)             */
+  int check_every;   /* iterations between convergence read-backs (<= 0: 8)        */
+  int use_graph;     /* capture the inner iteration in a HIP graph                */
+} dda_solve_opts;
+
+typedef struct {
+  int converged;        /* true FP64 residual <= tol                      */
+  int iterations;       /* inner Krylov iterations (all refinement steps) */
+  int outer_iterations; /* refinement steps                               */
+  int matvecs;          /* matrix-vector products (both precisions)       */
+  double rel_residual;  /* ||E - A P|| / ||E|| in FP64 at exit             */
+} dda_solve_info;
+
+/* Solve A P = E_inc for nrhs right-hand sides with a zero initial guess.
+ * E_inc is einc_dev ([nrhs][3][N_d] complex128) or, if NULL, plane waves
+ * ehat exp(i kd khat . r) built from khat[3*nrhs] and ehat[6*nrhs] (re, im).
+ * S (nullable) as for dda_matvec; when NULL and the prescription is LDR, S is
+ * computed from khat/ehat.  p_dev: out [nrhs][3][N_d] complex128.
+ * info: host [nrhs].  DDA_ENOTCONV if a right-hand side missed tol. */
+int dda_solve(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *khat, const double *ehat,
+              const double *S, const void *einc_dev, void *p_dev, dda_solve_info *info, void *hip_stream);
+
+/* Incident plane waves at the dipoles, E[r][c][n] = ehat_r[c] exp(i kd khat_r . r_n)
+ * (Sec. 1; |E0| = 1): khat[3*nrhs] real unit vectors, ehat[6*nrhs] (re, im).
+ * e_dev: out [nrhs][3][N_d] complex128. */
+int dda_incident_field(dda_target *t, int nrhs, const double *khat, const double *ehat, void *e_dev,
+                       void *hip_stream);
+
+/* C_ext = 4 pi k sum Im(E^* . P), C_abs = 4 pi k sum |P|^2 (-Im alpha^{-1} - 2k^3/3)
+ * (Draine 1988, |E0| = 1) and C_sca = C_ext - C_abs, per right-hand side
+ * (host outputs, nrhs each; any may be NULL). */
+int dda_cross_sections(dda_target *t, int nrhs, const double *S, const void *einc_dev, const void *p_dev,
+                       double *cext, double *cabs, double *csca, void *hip_stream);
+
+/* dC_abs/d eps_n for every dipole and right-hand side by one adjoint solve
+ * with the same matrix (A is complex symmetric: A mu = W conj(P)).
+ * grad_dev: out [nrhs][N_d] complex128 = dC/dRe eps + i dC/dIm eps.
+ * Requires dda_set_permittivity. */
+int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *S, const void *p_dev,
+                      void *grad_dev, void *hip_stream);
+
+/* Sizes of the embedding, for inspection:
+ * dims[0..8] = K'', J'', P'', K_h, J_h, P_h, N_d, and the 1D transform counts
+ * of one matrix-vector product per right-hand side (forward + inverse) and of
+ * the spectrum build (Table 2). */
+int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
+
+/* Copy the spectrum [6][P_h][J_h][K_h] (complex128 or complex64) to out_dev. */
+int dda_get_spectrum(dda_target *t, int precision, void *out_dev, void *hip_stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDA_H */

@@ -1,0 +1,1027 @@
+// libdda host driver: the C ABI of include/dda.h.
+//
+// Every step of the DDA matrix-vector product, the spectrum build, the Krylov
+// solvers, the refinement loop, the cross sections and the gradient runs in
+// the HIP kernels of kernels_fft.hpp / kernels_solver.hpp; this file only
+// plans sizes, owns device memory and enqueues launches on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dda.h"
+#include "common.hpp"
+#include "kernels_fft.hpp"
+#include "kernels_solver.hpp"
+
+using namespace dda;
+
+// ----------------------------------------------------------------------------
+// errors
+// ----------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) return fail(DDA_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+#define CHK(x)              \
+  do {                      \
+    int rc_ = (x);          \
+    if (rc_ != DDA_OK) return rc_; \
+  } while (0)
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+// ----------------------------------------------------------------------------
+// device buffers
+// ----------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t b) {
+    if (b <= bytes && p) return DDA_OK;
+    release();
+    if (b == 0) return DDA_OK;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      bytes = 0;
+      (void)hipGetLastError();
+      return fail(DDA_ENOMEM, "hipMalloc(%zu) failed", b);
+    }
+    bytes = b;
+    return DDA_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+  ~DevBuf() { release(); }
+};
+
+// ----------------------------------------------------------------------------
+// FFT planning
+// ----------------------------------------------------------------------------
+static bool smooth235(int n) {
+  for (int f : {2, 3, 5})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+
+// smallest 2^a 3^b 5^c >= m (m >= 1)
+static int fft_size_at_least(int m) {
+  int n = std::max(1, m);
+  while (!smooth235(n)) ++n;
+  return n;
+}
+
+static FftDesc make_desc(int n) {
+  FftDesc d;
+  d.n = n;
+  d.nst = 0;
+  int r = n;
+  int twos = 0;
+  while (r % 2 == 0) { r /= 2; ++twos; }
+  while (twos >= 3) { d.radix[d.nst++] = 8; twos -= 3; }
+  if (twos == 2) d.radix[d.nst++] = 4;
+  if (twos == 1) d.radix[d.nst++] = 2;
+  while (r % 5 == 0) { r /= 5; d.radix[d.nst++] = 5; }
+  while (r % 3 == 0) { r /= 3; d.radix[d.nst++] = 3; }
+  return d;
+}
+
+static int pow2_floor(long v) {
+  int p = 1;
+  while ((long)p * 2 <= v) p *= 2;
+  return p;
+}
+
+// ----------------------------------------------------------------------------
+// handles
+// ----------------------------------------------------------------------------
+struct dda_lib {
+  int device = 0;
+  std::string tune_path;
+};
+
+template <typename R>
+struct PrecBufs {
+  DevBuf Y;                 // spectrum [6][Ph][Jh][Kh]
+  DevBuf tw[3];             // twiddles for K'', J'', P''
+  DevBuf a0, a1;            // diagonal alpha^{-1} = a0 + S a1
+  DevBuf G1, G2;            // matvec workspaces
+  int cap = 0;              // right-hand sides the workspaces hold
+  DevBuf vec;               // solver vectors: 10 x [cap][3][nd]
+  int vec_cap = 0;
+};
+
+struct dda_target {
+  dda_lib* lib = nullptr;
+  int K = 0, J = 0, P = 0;
+  double kd = 0;
+  int Kpp = 0, Jpp = 0, Ppp = 0, Kh = 0, Jh = 0, Ph = 0;
+  FftDesc fx{}, fy{}, fz{};
+  int64_t nd = 0;
+  DevBuf map;    // int [P][J][K], -1 where empty
+  DevBuf sites;  // int [nd] linear index
+  bool have_alpha = false, have_eps = false, has_a1 = false;
+  int prescription = -1;
+  DevBuf d0, d1;  // d alpha^{-1} / d eps = d0 + S d1 (FP64)
+  PrecBufs<double> p64;
+  PrecBufs<float> p32;
+  bool spec_ready = false;
+  // per-solve scratch
+  DevBuf S;       // double [cap]
+  DevBuf active;  // int [cap]
+  DevBuf active_outer;
+  DevBuf state;   // solver states
+  DevBuf part;    // reduction partials
+  DevBuf scal;    // double [cap] scale factors
+  DevBuf outer;   // FP64 outer vectors: E, r, y  (3 x [cap][3][nd])
+  DevBuf khat, ehat;
+  int scap = 0;
+  std::vector<int> h_active;
+  int matvecs = 0;
+};
+
+template <typename R>
+static PrecBufs<R>& bufs(dda_target* t);
+template <>
+PrecBufs<double>& bufs<double>(dda_target* t) { return t->p64; }
+template <>
+PrecBufs<float>& bufs<float>(dda_target* t) { return t->p32; }
+
+// ----------------------------------------------------------------------------
+// launch helpers
+// ----------------------------------------------------------------------------
+static const int kThreads = 256;
+static const size_t kLdsBudget = 64 * 1024;
+
+template <typename R>
+static int launch_contig(const cx<R>* in, cx<R>* out, long nlines, long lin_stride, long lout_stride, int Lin,
+                         int Lout, const FftDesc& d, const cx<R>* tw, bool inv, bool mirror, long lines_per_comp,
+                         int axis, long lines_per_rhs, const int* active, double scale, hipStream_t st) {
+  ContigArgs a;
+  a.nlines = nlines;
+  a.lin_stride = lin_stride;
+  a.lout_stride = lout_stride;
+  a.Lin = Lin;
+  a.Lout = Lout;
+  a.ls = d.n;
+  a.lines_per_comp = lines_per_comp > 0 ? lines_per_comp : 1;
+  a.axis = axis;
+  a.lines_per_rhs = active ? lines_per_rhs : 0;
+  a.scale = scale;
+  const size_t per = 2 * (size_t)d.n * sizeof(cx<R>);
+  int rows = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / per));
+  if (a.lines_per_rhs) {
+    while (rows > 1 && a.lines_per_rhs % rows != 0) --rows;
+  }
+  a.rows = rows;
+  const size_t lds = rows * per;
+  dim3 grid((unsigned)((nlines + rows - 1) / rows));
+  if (inv) {
+    if (mirror) hipLaunchKernelGGL((k_lines_contig<R, true, true>), grid, dim3(kThreads), lds, st, in, out, a, d, tw, active);
+    else hipLaunchKernelGGL((k_lines_contig<R, true, false>), grid, dim3(kThreads), lds, st, in, out, a, d, tw, active);
+  } else {
+    if (mirror) hipLaunchKernelGGL((k_lines_contig<R, false, true>), grid, dim3(kThreads), lds, st, in, out, a, d, tw, active);
+    else hipLaunchKernelGGL((k_lines_contig<R, false, false>), grid, dim3(kThreads), lds, st, in, out, a, d, tw, active);
+  }
+  LAUNCHCHK();
+  return DDA_OK;
+}
+
+template <typename R>
+static int tile_width(int NX, int n, int nbuf) {
+  const size_t per = (size_t)nbuf * n * sizeof(cx<R>);
+  int tx = (int)std::min<size_t>(64, std::max<size_t>(1, kLdsBudget / per));
+  tx = pow2_floor(tx);
+  while (tx > 1 && tx / 2 >= NX) tx /= 2;
+  return tx;
+}
+
+template <typename R>
+static int launch_strided_mirror(const cx<R>* in, cx<R>* out, StridedArgs a, int NO, int NB, const FftDesc& d,
+                                 const cx<R>* tw, hipStream_t st) {
+  a.TX = tile_width<R>(a.NX, d.n, 2);
+  const size_t lds = 2 * (size_t)d.n * a.TX * sizeof(cx<R>);
+  dim3 grid((a.NX + a.TX - 1) / a.TX, NO, NB);
+  hipLaunchKernelGGL((k_lines_strided<R, false, true>), grid, dim3(kThreads), lds, st, in, out, a, d, tw);
+  LAUNCHCHK();
+  return DDA_OK;
+}
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+const char* dda_last_error(void) { return g_err.c_str(); }
+
+int dda_open(int hip_device, const char* tune_cache_path, dda_lib** out) {
+  if (!out) return fail(DDA_EINVAL, "dda_open: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) return fail(DDA_EINVAL, "dda_open: device %d of %d", hip_device, n);
+  HIPCHK(hipSetDevice(hip_device));
+  dda_lib* l = new dda_lib();
+  l->device = hip_device;
+  if (tune_cache_path) l->tune_path = tune_cache_path;
+  *out = l;
+  return DDA_OK;
+}
+
+void dda_close(dda_lib* lib) { delete lib; }
+
+int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target** out) {
+  if (!lib || !out) return fail(DDA_EINVAL, "dda_target_create: NULL argument");
+  *out = nullptr;
+  if (K < 1 || J < 1 || P < 1) return fail(DDA_EINVAL, "dda_target_create: lattice %dx%dx%d", K, J, P);
+  if (!(kd > 0.0) || !std::isfinite(kd)) return fail(DDA_EINVAL, "dda_target_create: kd = %g", kd);
+  if ((long)K * J * P > (1L << 30)) return fail(DDA_EINVAL, "dda_target_create: lattice too large");
+  HIPCHK(hipSetDevice(lib->device));
+  dda_target* t = new dda_target();
+  t->lib = lib;
+  t->K = K;
+  t->J = J;
+  t->P = P;
+  t->kd = kd;
+  t->Kpp = fft_size_at_least(2 * K - 1);
+  t->Jpp = fft_size_at_least(2 * J - 1);
+  t->Ppp = fft_size_at_least(2 * P - 1);
+  t->Kh = t->Kpp / 2 + 1;
+  t->Jh = t->Jpp / 2 + 1;
+  t->Ph = t->Ppp / 2 + 1;
+  t->fx = make_desc(t->Kpp);
+  t->fy = make_desc(t->Jpp);
+  t->fz = make_desc(t->Ppp);
+  // twiddle tables exp(-2 pi i m / n), from host libm in FP64; FP32 by rounding
+  const int ns[3] = {t->Kpp, t->Jpp, t->Ppp};
+  for (int a = 0; a < 3; ++a) {
+    const int n = ns[a];
+    std::vector<c64> w(n);
+    std::vector<c32> wf(n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = 2.0 * M_PI * (double)m / (double)n;
+      w[m] = mk(std::cos(ang), -std::sin(ang));
+      wf[m] = mk((float)w[m].x, (float)w[m].y);
+    }
+    int rc = t->p64.tw[a].ensure(n * sizeof(c64));
+    if (rc == DDA_OK) rc = t->p32.tw[a].ensure(n * sizeof(c32));
+    if (rc != DDA_OK) {
+      delete t;
+      return rc;
+    }
+    if (hipMemcpy(t->p64.tw[a].p, w.data(), n * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->p32.tw[a].p, wf.data(), n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess) {
+      delete t;
+      return fail(DDA_EDEVICE, "dda_target_create: twiddle upload failed");
+    }
+  }
+  *out = t;
+  return DDA_OK;
+}
+
+void dda_target_destroy(dda_target* t) {
+  if (!t) return;
+  (void)hipSetDevice(t->lib->device);
+  delete t;
+}
+
+int dda_target_info(const dda_target* t, int64_t* dims) {
+  if (!t || !dims) return fail(DDA_EINVAL, "dda_target_info: NULL argument");
+  dims[0] = t->Kpp;
+  dims[1] = t->Jpp;
+  dims[2] = t->Ppp;
+  dims[3] = t->Kh;
+  dims[4] = t->Jh;
+  dims[5] = t->Ph;
+  dims[6] = t->nd;
+  // 1D transforms per matrix-vector product and right-hand side, forward and
+  // inverse (Sec. 3): y on K*P lines, x on J''*P lines, z on K''*J'' lines,
+  // for each of the 3 components, both directions.
+  dims[7] = 2L * 3 * ((long)t->K * t->P + (long)t->Jpp * t->P + (long)t->Kpp * t->Jpp);
+  // spectrum build: x on J*P, y on K_h*P, z on K_h*J_h lines, 6 components
+  dims[8] = 6L * ((long)t->J * t->P + (long)t->Kh * t->P + (long)t->Kh * t->Jh);
+  return DDA_OK;
+}
+
+int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
+  if (!t || !occ) return fail(DDA_EINVAL, "dda_set_occupancy: NULL argument");
+  HIPCHK(hipSetDevice(t->lib->device));
+  const long N = (long)t->K * t->J * t->P;
+  std::vector<int> map(N), sites;
+  for (long s = 0; s < N; ++s) {
+    if (occ[s]) {
+      map[s] = (int)sites.size();
+      sites.push_back((int)s);
+    } else {
+      map[s] = -1;
+    }
+  }
+  if (sites.empty()) return fail(DDA_EINVAL, "dda_set_occupancy: no occupied site");
+  CHK(t->map.ensure(N * sizeof(int)));
+  CHK(t->sites.ensure(sites.size() * sizeof(int)));
+  HIPCHK(hipMemcpy(t->map.p, map.data(), N * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t->sites.p, sites.data(), sites.size() * sizeof(int), hipMemcpyHostToDevice));
+  t->nd = (int64_t)sites.size();
+  t->have_alpha = t->have_eps = false;
+  if (nd_out) *nd_out = t->nd;
+  return DDA_OK;
+}
+
+static int upload_diag(dda_target* t, const std::vector<c64>& a0, const std::vector<c64>* a1) {
+  const size_t nd = (size_t)t->nd;
+  CHK(t->p64.a0.ensure(nd * sizeof(c64)));
+  CHK(t->p32.a0.ensure(nd * sizeof(c32)));
+  std::vector<c32> f(nd);
+  for (size_t n = 0; n < nd; ++n) f[n] = mk((float)a0[n].x, (float)a0[n].y);
+  HIPCHK(hipMemcpy(t->p64.a0.p, a0.data(), nd * sizeof(c64), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t->p32.a0.p, f.data(), nd * sizeof(c32), hipMemcpyHostToDevice));
+  t->has_a1 = a1 != nullptr;
+  if (a1) {
+    CHK(t->p64.a1.ensure(nd * sizeof(c64)));
+    CHK(t->p32.a1.ensure(nd * sizeof(c32)));
+    for (size_t n = 0; n < nd; ++n) f[n] = mk((float)(*a1)[n].x, (float)(*a1)[n].y);
+    HIPCHK(hipMemcpy(t->p64.a1.p, a1->data(), nd * sizeof(c64), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(t->p32.a1.p, f.data(), nd * sizeof(c32), hipMemcpyHostToDevice));
+  }
+  return DDA_OK;
+}
+
+int dda_set_permittivity(dda_target* t, const double* eps, int prescription) {
+  if (!t || !eps) return fail(DDA_EINVAL, "dda_set_permittivity: NULL argument");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_set_permittivity: occupancy not set");
+  if (prescription < DDA_POL_CM || prescription > DDA_POL_LDR)
+    return fail(DDA_EINVAL, "dda_set_permittivity: prescription %d", prescription);
+  HIPCHK(hipSetDevice(t->lib->device));
+  // Published prescriptions (CM; Draine 1988 radiative reaction; Draine &
+  // Goodman 1993 lattice dispersion relation), d = 1.
+  const double b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004;
+  const double kd = t->kd, kd2 = kd * kd, kd3 = kd2 * kd;
+  const size_t nd = (size_t)t->nd;
+  std::vector<c64> a0(nd), a1(nd), d0(nd), d1(nd);
+  for (size_t n = 0; n < nd; ++n) {
+    const c64 e = mk(eps[2 * n], eps[2 * n + 1]);
+    const c64 em1 = e - mk(1.0, 0.0);
+    if (!(abs2(em1) > 0.0)) return fail(DDA_EINVAL, "dda_set_permittivity: eps = 1 at dipole %zu", n);
+    c64 cm = (4.0 * M_PI / 3.0) * cdiv(e + mk(2.0, 0.0), em1);
+    c64 v = cm;
+    c64 dv = (-4.0 * M_PI) * cdiv(mk(1.0, 0.0), em1 * em1);
+    c64 s1 = mk(0.0, 0.0), ds1 = mk(0.0, 0.0);
+    if (prescription >= DDA_POL_RR) v = v + mk(0.0, -(2.0 / 3.0) * kd3);
+    if (prescription == DDA_POL_LDR) {
+      v = v + kd2 * (mk(b1, 0.0) + b2 * e);
+      dv = dv + mk(b2 * kd2, 0.0);
+      s1 = (b3 * kd2) * e;
+      ds1 = mk(b3 * kd2, 0.0);
+    }
+    if (!std::isfinite(v.x) || !std::isfinite(v.y) || !(abs2(v) > 0.0))
+      return fail(DDA_EINVAL, "dda_set_permittivity: alpha^-1 not finite at dipole %zu", n);
+    a0[n] = v;
+    a1[n] = s1;
+    d0[n] = dv;
+    d1[n] = ds1;
+  }
+  const bool ldr = prescription == DDA_POL_LDR;
+  CHK(upload_diag(t, a0, ldr ? &a1 : nullptr));
+  CHK(t->d0.ensure(nd * sizeof(c64)));
+  HIPCHK(hipMemcpy(t->d0.p, d0.data(), nd * sizeof(c64), hipMemcpyHostToDevice));
+  if (ldr) {
+    CHK(t->d1.ensure(nd * sizeof(c64)));
+    HIPCHK(hipMemcpy(t->d1.p, d1.data(), nd * sizeof(c64), hipMemcpyHostToDevice));
+  }
+  t->prescription = prescription;
+  t->have_alpha = t->have_eps = true;
+  return DDA_OK;
+}
+
+int dda_set_polarizability(dda_target* t, const double* alpha) {
+  if (!t || !alpha) return fail(DDA_EINVAL, "dda_set_polarizability: NULL argument");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_set_polarizability: occupancy not set");
+  HIPCHK(hipSetDevice(t->lib->device));
+  const size_t nd = (size_t)t->nd;
+  std::vector<c64> a0(nd);
+  for (size_t n = 0; n < nd; ++n) {
+    const c64 a = mk(alpha[2 * n], alpha[2 * n + 1]);
+    if (!(abs2(a) > 0.0)) return fail(DDA_EINVAL, "dda_set_polarizability: alpha = 0 at dipole %zu", n);
+    a0[n] = cdiv(mk(1.0, 0.0), a);
+    if (!std::isfinite(a0[n].x) || !std::isfinite(a0[n].y))
+      return fail(DDA_EINVAL, "dda_set_polarizability: alpha^-1 not finite at dipole %zu", n);
+  }
+  CHK(upload_diag(t, a0, nullptr));
+  t->prescription = -1;
+  t->have_alpha = true;
+  t->have_eps = false;
+  return DDA_OK;
+}
+
+int dda_build_spectrum(dda_target* t, void* hip_stream) {
+  if (!t) return fail(DDA_EINVAL, "dda_build_spectrum: NULL target");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int K = t->K, J = t->J, P = t->P, Kh = t->Kh, Jh = t->Jh, Ph = t->Ph;
+  DevBuf T, S1, S2;
+  CHK(T.ensure(6L * K * J * P * sizeof(c64)));
+  CHK(S1.ensure(6L * P * J * Kh * sizeof(c64)));
+  CHK(S2.ensure(6L * P * Jh * Kh * sizeof(c64)));
+  CHK(t->p64.Y.ensure(6L * Ph * Jh * Kh * sizeof(c64)));
+  CHK(t->p32.Y.ensure(6L * Ph * Jh * Kh * sizeof(c32)));
+  const long N = (long)K * J * P;
+  hipLaunchKernelGGL(k_tensor_column, dim3((unsigned)std::min<long>((N + 255) / 256, 65535)), dim3(256), 0, st,
+                     T.as<c64>(), K, J, P, t->kd);
+  LAUNCHCHK();
+  // x: 6*J*P lines of K -> K'' (mirrored with Table 1 signs), keep K_h
+  CHK(launch_contig<double>(T.as<c64>(), S1.as<c64>(), 6L * J * P, K, Kh, K, Kh, t->fx, t->p64.tw[0].as<c64>(),
+                            false, true, (long)J * P, 0, 0, nullptr, 1.0, st));
+  // y: lines along y of [6][P][J][K_h] -> [6][P][J_h][K_h]
+  StridedArgs ya;
+  ya.sb = (long)P * J * Kh;
+  ya.so = (long)J * Kh;
+  ya.se = Kh;
+  ya.tb = (long)P * Jh * Kh;
+  ya.to = (long)Jh * Kh;
+  ya.te = Kh;
+  ya.NX = Kh;
+  ya.Lin = J;
+  ya.Lout = Jh;
+  ya.axis = 1;
+  CHK(launch_strided_mirror<double>(S1.as<c64>(), S2.as<c64>(), ya, P, 6, t->fy, t->p64.tw[1].as<c64>(), st));
+  // z: lines along z of [6][P][J_h][K_h] -> [6][P_h][J_h][K_h]
+  StridedArgs za;
+  za.sb = (long)P * Jh * Kh;
+  za.so = Kh;
+  za.se = (long)Jh * Kh;
+  za.tb = (long)Ph * Jh * Kh;
+  za.to = Kh;
+  za.te = (long)Jh * Kh;
+  za.NX = Kh;
+  za.Lin = P;
+  za.Lout = Ph;
+  za.axis = 2;
+  CHK(launch_strided_mirror<double>(S2.as<c64>(), t->p64.Y.as<c64>(), za, Jh, 6, t->fz, t->p64.tw[2].as<c64>(),
+                                    st));
+  const long ny = 6L * Ph * Jh * Kh;
+  hipLaunchKernelGGL(k_round_to_f32, dim3((unsigned)std::min<long>((ny + 255) / 256, 65535)), dim3(256), 0, st,
+                     t->p64.Y.as<c64>(), t->p32.Y.as<c32>(), ny);
+  LAUNCHCHK();
+  // temporaries are freed on return: wait for the kernels that use them
+  HIPCHK(hipStreamSynchronize(st));
+  t->spec_ready = true;
+  return DDA_OK;
+}
+
+int dda_get_spectrum(dda_target* t, int precision, void* out_dev, void* hip_stream) {
+  if (!t || !out_dev) return fail(DDA_EINVAL, "dda_get_spectrum: NULL argument");
+  if (!t->spec_ready) return fail(DDA_ESTATE, "dda_get_spectrum: spectrum not built");
+  HIPCHK(hipSetDevice(t->lib->device));
+  const long ny = 6L * t->Ph * t->Jh * t->Kh;
+  if (precision == DDA_FP64)
+    HIPCHK(hipMemcpyAsync(out_dev, t->p64.Y.p, ny * sizeof(c64), hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
+  else
+    HIPCHK(hipMemcpyAsync(out_dev, t->p32.Y.p, ny * sizeof(c32), hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
+  return DDA_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// matrix-vector product
+// ----------------------------------------------------------------------------
+static int ensure_scratch(dda_target* t, int nrhs) {
+  if (nrhs <= t->scap) return DDA_OK;
+  const int cap = nrhs;
+  CHK(t->S.ensure(cap * sizeof(double)));
+  CHK(t->active.ensure(cap * sizeof(int)));
+  CHK(t->active_outer.ensure(cap * sizeof(int)));
+  CHK(t->scal.ensure(cap * sizeof(double)));
+  CHK(t->state.ensure(cap * std::max(sizeof(BcgState), sizeof(QmrState))));
+  CHK(t->khat.ensure(cap * 3 * sizeof(double)));
+  CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
+  t->h_active.resize(cap);
+  t->scap = cap;
+  return DDA_OK;
+}
+
+template <typename R>
+static int ensure_matvec_ws(dda_target* t, int nrhs) {
+  PrecBufs<R>& b = bufs<R>(t);
+  if (nrhs <= b.cap) return DDA_OK;
+  CHK(b.G1.ensure((size_t)nrhs * 3 * t->P * t->Jpp * t->K * sizeof(cx<R>)));
+  CHK(b.G2.ensure((size_t)nrhs * 3 * t->P * t->Jpp * t->Kpp * sizeof(cx<R>)));
+  b.cap = nrhs;
+  return DDA_OK;
+}
+
+// y = A x (jacobi = 0) or D^{-1/2} A D^{-1/2} x (jacobi = 1); S and active are
+// device arrays [nrhs] (nullable).
+template <typename R>
+static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
+                    const int* active, hipStream_t st) {
+  CHK(ensure_matvec_ws<R>(t, nrhs));
+  PrecBufs<R>& b = bufs<R>(t);
+  const int K = t->K, J = t->J, P = t->P, Jpp = t->Jpp, Kpp = t->Kpp, Ppp = t->Ppp;
+  cx<R>* G1 = b.G1.template as<cx<R>>();
+  cx<R>* G2 = b.G2.template as<cx<R>>();
+  const cx<R>* a0 = b.a0.template as<cx<R>>();
+  const cx<R>* a1 = t->has_a1 ? b.a1.template as<cx<R>>() : nullptr;
+  VecArgs va;
+  va.K = K;
+  va.J = J;
+  va.P = P;
+  va.Jpp = Jpp;
+  va.Kpp = Kpp;
+  va.Ppp = Ppp;
+  va.nd = t->nd;
+  va.jacobi = jacobi;
+  va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
+  va.TX = tile_width<R>(K, Jpp, 2);
+  {
+    const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
+    dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
+    hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, t->map.as<int>(), a0, a1, dS,
+                       active, va, t->fy, b.tw[1].template as<cx<R>>());
+    LAUNCHCHK();
+  }
+  const long rows = (long)nrhs * 3 * P * Jpp;
+  CHK(launch_contig<R>(G1, G2, rows, K, Kpp, K, Kpp, t->fx, b.tw[0].template as<cx<R>>(), false, false, 0, 0,
+                       3L * P * Jpp, active, 1.0, st));
+  {
+    ZArgs za;
+    za.Kpp = Kpp;
+    za.Jpp = Jpp;
+    za.P = P;
+    za.Ppp = Ppp;
+    za.Kh = t->Kh;
+    za.Jh = t->Jh;
+    za.Ph = t->Ph;
+    za.TX = tile_width<R>(Kpp, Ppp, 4);
+    const size_t lds = 4 * (size_t)Ppp * za.TX * sizeof(cx<R>);
+    dim3 grid((Kpp + za.TX - 1) / za.TX, Jpp, nrhs);
+    hipLaunchKernelGGL((k_vec_zmul<R>), grid, dim3(kThreads), lds, st, G2, b.Y.template as<cx<R>>(), active, za,
+                       t->fz, b.tw[2].template as<cx<R>>());
+    LAUNCHCHK();
+  }
+  CHK(launch_contig<R>(G2, G1, rows, Kpp, K, Kpp, K, t->fx, b.tw[0].template as<cx<R>>(), true, false, 0, 0, 3L * P * Jpp,
+                       active, 1.0, st));
+  {
+    const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
+    dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
+    hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, t->map.as<int>(), a0, a1, dS,
+                       active, va, t->fy, b.tw[1].template as<cx<R>>());
+    LAUNCHCHK();
+  }
+  t->matvecs += 1;
+  return DDA_OK;
+}
+
+static int check_ready(dda_target* t, const char* who) {
+  if (!t) return fail(DDA_EINVAL, "%s: NULL target", who);
+  if (t->nd <= 0) return fail(DDA_ESTATE, "%s: occupancy not set", who);
+  if (!t->have_alpha) return fail(DDA_ESTATE, "%s: polarisability not set", who);
+  if (!t->spec_ready) return fail(DDA_ESTATE, "%s: spectrum not built", who);
+  return DDA_OK;
+}
+
+extern "C" int dda_matvec(dda_target* t, int precision, int nrhs, const double* S, int jacobi, const void* x_dev,
+                          void* y_dev, void* hip_stream) {
+  CHK(check_ready(t, "dda_matvec"));
+  if (nrhs < 1) return fail(DDA_EINVAL, "dda_matvec: nrhs = %d", nrhs);
+  if (!x_dev || !y_dev) return fail(DDA_EINVAL, "dda_matvec: NULL vector");
+  if (x_dev == y_dev) return fail(DDA_EINVAL, "dda_matvec: x and y must not alias");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(ensure_scratch(t, nrhs));
+  std::vector<double> hs(nrhs, 0.0);
+  if (S)
+    for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
+  HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (precision == DDA_FP64)
+    return matvec_T<double>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c64*)x_dev, (c64*)y_dev, nullptr, st);
+  if (precision == DDA_FP32)
+    return matvec_T<float>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, nullptr, st);
+  return fail(DDA_EINVAL, "dda_matvec: precision %d", precision);
+}
+
+// ----------------------------------------------------------------------------
+// Krylov solvers
+// ----------------------------------------------------------------------------
+struct InnerResult {
+  std::vector<int> iters, converged, breakdown;
+  std::vector<double> rnorm2, bnorm2;
+};
+
+static int nblocks_for(long n3) {
+  long b = (n3 + 4L * kRedThreads - 1) / (4L * kRedThreads);
+  return (int)std::max(1L, std::min(b, 256L));
+}
+
+template <typename R>
+static int ensure_solver_ws(dda_target* t, int nrhs) {
+  PrecBufs<R>& b = bufs<R>(t);
+  if (nrhs <= b.vec_cap) return DDA_OK;
+  CHK(b.vec.ensure((size_t)10 * nrhs * 3 * t->nd * sizeof(cx<R>)));
+  b.vec_cap = nrhs;
+  return DDA_OK;
+}
+
+// Read the device `active` flags; returns the number still active.
+static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
+  HIPCHK(hipMemcpyAsync(t->h_active.data(), t->active.p, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  n_active = 0;
+  for (int r = 0; r < nrhs; ++r) n_active += t->h_active[r] != 0;
+  return DDA_OK;
+}
+
+// Solve (jacobi-scaled) A u = b for the right-hand sides flagged in
+// t->active; b and u are slots 0 and 1 of the solver vectors.
+template <typename R>
+static int inner_solve(dda_target* t, int solver, int nrhs, double tol, int max_iter, int jacobi, int check_every,
+                       hipStream_t st, InnerResult& res) {
+  PrecBufs<R>& B = bufs<R>(t);
+  const long n3 = 3 * t->nd;
+  const size_t vsz = (size_t)nrhs * n3;
+  cx<R>* V = B.vec.template as<cx<R>>();
+  auto slot = [&](int k) { return V + k * vsz; };
+  cx<R>* b = slot(0);
+  cx<R>* u = slot(1);
+  SolverDims dm;
+  dm.n3 = n3;
+  dm.nblk = nblocks_for(n3);
+  CHK(t->part.ensure((size_t)nrhs * dm.nblk * 2 * sizeof(c64)));
+  c64* part = t->part.as<c64>();
+  int* act = t->active.as<int>();
+  const double* dS = t->S.as<double>();
+  dim3 vg(dm.nblk, nrhs), fg(nrhs);
+  const int check = check_every > 0 ? check_every : 8;
+  int n_active = 0;
+  if (solver == DDA_BICGSTAB) {
+    BcgState* stt = t->state.as<BcgState>();
+    cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
+    hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(256), 0, st, b, r, rhat, p, v, u, act, dm, part);
+    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tol);
+    LAUNCHCHK();
+    for (int it = 0; it < max_iter; ++it) {
+      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, st, r, p, v, stt, act, dm);
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, st));
+      hipLaunchKernelGGL((k_dots<R, 1>), vg, dim3(256), 0, st, rhat, v, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_alpha, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, st, r, v, stt, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_s, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, st));
+      hipLaunchKernelGGL((k_dots<R, 2>), vg, dim3(256), 0, st, tt, r, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_omega, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, st, u, r, p, tt, rhat, stt, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_iter, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      LAUNCHCHK();
+      if ((it + 1) % check == 0 || it + 1 == max_iter) {
+        CHK(read_active(t, nrhs, st, n_active));
+        if (n_active == 0) break;
+      }
+    }
+    std::vector<BcgState> hs(nrhs);
+    HIPCHK(hipMemcpyAsync(hs.data(), stt, nrhs * sizeof(BcgState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < nrhs; ++q) {
+      res.iters[q] = hs[q].iters;
+      res.converged[q] = hs[q].converged;
+      res.breakdown[q] = hs[q].breakdown;
+      res.rnorm2[q] = hs[q].rnorm2;
+      res.bnorm2[q] = hs[q].bnorm2;
+    }
+  } else {
+    QmrState* stt = t->state.as<QmrState>();
+    cx<R>*r = slot(2), *va = slot(3), *vb = slot(4), *w = slot(5), *pa = slot(6), *pb = slot(7), *qa = slot(8),
+          *qb = slot(9);
+    // va = v_{n-1} (initially 0), vb = v_n
+    hipLaunchKernelGGL((k_qmr_init_a<R>), vg, dim3(256), 0, st, b, r, u, va, pa, pb, qa, qb, act, dm, part);
+    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tol);
+    hipLaunchKernelGGL((k_qmr_init_b<R>), vg, dim3(256), 0, st, b, vb, stt, act, dm);
+    LAUNCHCHK();
+    cx<R>*vprev = va, *vcur = vb, *p1 = pa, *p2 = pb, *q1 = qa, *q2 = qb;
+    for (int it = 0; it < max_iter; ++it) {
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, vcur, w, act, st));
+      hipLaunchKernelGGL((k_bil_dot<R>), vg, dim3(256), 0, st, vcur, w, act, dm, part);
+      hipLaunchKernelGGL(k_qmr_fin_alpha, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_qmr_vt<R>), vg, dim3(256), 0, st, w, vcur, vprev, stt, act, dm, part);
+      hipLaunchKernelGGL(k_qmr_fin_givens, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_qmr_update<R>), vg, dim3(256), 0, st, vprev, vcur, w, p1, p2, q1, q2, u, r, stt, act, dm,
+                         part);
+      hipLaunchKernelGGL(k_qmr_fin_conv, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
+      LAUNCHCHK();
+      std::swap(vprev, vcur);  // v_{n+1} now in vcur
+      std::swap(p1, p2);       // p_n now in p1
+      std::swap(q1, q2);
+      if ((it + 1) % check == 0 || it + 1 == max_iter) {
+        CHK(read_active(t, nrhs, st, n_active));
+        if (n_active == 0) break;
+      }
+    }
+    std::vector<QmrState> hs(nrhs);
+    HIPCHK(hipMemcpyAsync(hs.data(), stt, nrhs * sizeof(QmrState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < nrhs; ++q) {
+      res.iters[q] = hs[q].iters;
+      res.converged[q] = hs[q].converged;
+      res.breakdown[q] = hs[q].breakdown;
+      res.rnorm2[q] = hs[q].rnorm2;
+      res.bnorm2[q] = hs[q].bnorm2;
+    }
+  }
+  return DDA_OK;
+}
+
+// FP64 true residual r = E - A P for all right-hand sides; returns |r|^2 and
+// |E|^2 per right-hand side on the host.
+static int true_residual(dda_target* t, int nrhs, const c64* E, const c64* Pv, c64* r, c64* y, hipStream_t st,
+                         std::vector<double>& rn2, std::vector<double>& en2) {
+  CHK(matvec_T<double>(t, nrhs, t->S.as<double>(), 0, Pv, y, nullptr, st));
+  SolverDims dm;
+  dm.n3 = 3 * t->nd;
+  dm.nblk = nblocks_for(dm.n3);
+  CHK(t->part.ensure((size_t)nrhs * dm.nblk * 2 * sizeof(c64)));
+  hipLaunchKernelGGL(k_residual, dim3(dm.nblk, nrhs), dim3(256), 0, st, E, y, r, dm, t->part.as<c64>());
+  LAUNCHCHK();
+  std::vector<c64> hp((size_t)nrhs * dm.nblk * 2);
+  HIPCHK(hipMemcpyAsync(hp.data(), t->part.p, hp.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  rn2.assign(nrhs, 0.0);
+  en2.assign(nrhs, 0.0);
+  for (int q = 0; q < nrhs; ++q)
+    for (int bk = 0; bk < dm.nblk; ++bk) {
+      rn2[q] += hp[((size_t)q * dm.nblk + bk) * 2].x;
+      en2[q] += hp[((size_t)q * dm.nblk + bk) * 2 + 1].x;
+    }
+  return DDA_OK;
+}
+
+static int ensure_outer(dda_target* t, int nrhs) {
+  return t->outer.ensure((size_t)3 * nrhs * 3 * t->nd * sizeof(c64));
+}
+
+static void orientation_S(dda_target* t, int nrhs, const double* khat, const double* ehat, const double* S,
+                          std::vector<double>& hs) {
+  hs.assign(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r) {
+    if (S) {
+      hs[r] = S[r];
+    } else if (t->prescription == DDA_POL_LDR && khat && ehat) {
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        // (khat_a ehat_a)^2 for a complex ehat: real part of the square
+        const double kr = khat[3 * r + a];
+        const double er = ehat[6 * r + 2 * a], ei = ehat[6 * r + 2 * a + 1];
+        s += kr * kr * (er * er - ei * ei);
+      }
+      hs[r] = s;
+    }
+  }
+}
+
+// Refinement loop around the inner solves: P += D^{-1/2} u |r| where
+// (D^{-1/2} A D^{-1/2}) u = D^{-1/2} r / |r|, until the FP64 true residual
+// meets tol.  Inner precision FP64 (tol_in = tol) or FP32 (tol_in = inner_tol).
+static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c64* E, c64* Pv, dda_solve_info* info,
+                      hipStream_t st) {
+  CHK(ensure_outer(t, nrhs));
+  const long n3 = 3 * t->nd;
+  c64* r64 = t->outer.as<c64>() + (size_t)nrhs * n3;
+  c64* y64 = r64 + (size_t)nrhs * n3;
+  const bool mixed = o.precision == DDA_SOLVE_MIXED;
+  if (mixed) CHK(ensure_solver_ws<float>(t, nrhs));
+  else CHK(ensure_solver_ws<double>(t, nrhs));
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
+  const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+  const double tol = o.tol > 0 ? o.tol : 1e-6;
+  const double tol_in = mixed ? (o.inner_tol > 0 ? o.inner_tol : 1e-3) : tol;
+  const int mv0 = t->matvecs;
+  HIPCHK(hipMemsetAsync(Pv, 0, (size_t)nrhs * n3 * sizeof(c64), st));
+  std::vector<double> rn2, en2;
+  // P = 0: the residual is E
+  HIPCHK(hipMemcpyAsync(r64, E, (size_t)nrhs * n3 * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  {
+    CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
+  }
+  std::vector<int> iters(nrhs, 0), outer(nrhs, 0), done(nrhs, 0);
+  InnerResult ir;
+  ir.iters.resize(nrhs);
+  ir.converged.resize(nrhs);
+  ir.breakdown.resize(nrhs);
+  ir.rnorm2.resize(nrhs);
+  ir.bnorm2.resize(nrhs);
+  std::vector<int> hact(nrhs);
+  std::vector<double> hsc(nrhs);
+  for (int step = 0; step < max_outer; ++step) {
+    int n_left = 0;
+    for (int q = 0; q < nrhs; ++q) {
+      done[q] = !(rn2[q] > tol * tol * en2[q]) || iters[q] >= max_iter;
+      hact[q] = !done[q];
+      n_left += hact[q];
+      hsc[q] = rn2[q] > 0 ? 1.0 / std::sqrt(rn2[q]) : 0.0;
+    }
+    if (n_left == 0) break;
+    int budget = 0;
+    for (int q = 0; q < nrhs; ++q)
+      if (hact[q]) budget = std::max(budget, max_iter - iters[q]);
+    HIPCHK(hipMemcpyAsync(t->active.p, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(t->active_outer.p, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(t->scal.p, hsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    const unsigned gx = (unsigned)std::min<long>((n3 + 255) / 256, 4096);
+    const c64* a0 = t->p64.a0.as<c64>();
+    const c64* a1 = t->has_a1 ? t->p64.a1.as<c64>() : nullptr;
+    if (mixed) {
+      hipLaunchKernelGGL((k_scale_rhs<float>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p32.vec.as<c32>(), a0, a1,
+                         t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
+      LAUNCHCHK();
+      CHK(inner_solve<float>(t, o.solver, nrhs, tol_in, budget, o.jacobi ? 1 : 0, o.check_every, st, ir));
+    } else {
+      hipLaunchKernelGGL((k_scale_rhs<double>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p64.vec.as<c64>(), a0, a1,
+                         t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
+      LAUNCHCHK();
+      CHK(inner_solve<double>(t, o.solver, nrhs, tol_in, budget, o.jacobi ? 1 : 0, o.check_every, st, ir));
+    }
+    // P += |r| D^{-1/2} u
+    for (int q = 0; q < nrhs; ++q) hsc[q] = std::sqrt(rn2[q]);
+    HIPCHK(hipMemcpyAsync(t->scal.p, hsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    if (mixed) {
+      const size_t vsz = (size_t)nrhs * n3;
+      hipLaunchKernelGGL((k_accumulate<float>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p32.vec.as<c32>() + vsz, a0,
+                         a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
+                         o.jacobi ? 1 : 0);
+    } else {
+      const size_t vsz = (size_t)nrhs * n3;
+      hipLaunchKernelGGL((k_accumulate<double>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p64.vec.as<c64>() + vsz, a0,
+                         a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
+                         o.jacobi ? 1 : 0);
+    }
+    LAUNCHCHK();
+    for (int q = 0; q < nrhs; ++q)
+      if (hact[q]) {
+        iters[q] += ir.iters[q];
+        outer[q] += 1;
+      }
+    CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
+  }
+  bool all = true;
+  for (int q = 0; q < nrhs; ++q) {
+    const double rel = en2[q] > 0 ? std::sqrt(rn2[q] / en2[q]) : 0.0;
+    const int conv = rel <= tol;
+    all = all && conv;
+    if (info) {
+      info[q].converged = conv;
+      info[q].iterations = iters[q];
+      info[q].outer_iterations = outer[q];
+      info[q].rel_residual = rel;
+      info[q].matvecs = t->matvecs - mv0;
+    }
+  }
+  if (!all) return fail(DDA_ENOTCONV, "dda_solve: a right-hand side missed tol %g", tol);
+  return DDA_OK;
+}
+
+static int check_opts(const dda_solve_opts* opts, const char* who) {
+  if (!opts) return fail(DDA_EINVAL, "%s: opts is NULL", who);
+  if (opts->solver != DDA_BICGSTAB && opts->solver != DDA_QMR_SYM)
+    return fail(DDA_EINVAL, "%s: solver %d", who, opts->solver);
+  if (opts->precision != DDA_SOLVE_FP64 && opts->precision != DDA_SOLVE_MIXED)
+    return fail(DDA_EINVAL, "%s: precision %d", who, opts->precision);
+  if (!(opts->tol > 0.0) || !(opts->tol < 1.0)) return fail(DDA_EINVAL, "%s: tol %g", who, opts->tol);
+  return DDA_OK;
+}
+
+extern "C" int dda_solve(dda_target* t, const dda_solve_opts* opts, int nrhs, const double* khat, const double* ehat,
+                         const double* S, const void* einc_dev, void* p_dev, dda_solve_info* info, void* hip_stream) {
+  CHK(check_ready(t, "dda_solve"));
+  CHK(check_opts(opts, "dda_solve"));
+  if (nrhs < 1) return fail(DDA_EINVAL, "dda_solve: nrhs = %d", nrhs);
+  if (!p_dev) return fail(DDA_EINVAL, "dda_solve: p_dev is NULL");
+  if (!einc_dev && (!khat || !ehat)) return fail(DDA_EINVAL, "dda_solve: need einc_dev or khat and ehat");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(ensure_scratch(t, nrhs));
+  CHK(ensure_outer(t, nrhs));
+  std::vector<double> hs;
+  orientation_S(t, nrhs, khat, ehat, S, hs);
+  HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  const c64* E = (const c64*)einc_dev;
+  if (!E) {
+    c64* Eg = t->outer.as<c64>();
+    HIPCHK(hipMemcpyAsync(t->khat.p, khat, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(t->ehat.p, ehat, nrhs * 6 * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_einc, dim3((unsigned)std::min<long>((t->nd + 255) / 256, 4096), nrhs), dim3(256), 0, st, Eg,
+                       t->sites.as<int>(), (long)t->nd, t->K, t->J, t->kd, t->khat.as<double>(), t->ehat.as<double>());
+    LAUNCHCHK();
+    E = Eg;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return solve_core(t, *opts, nrhs, E, (c64*)p_dev, info, st);
+}
+
+extern "C" int dda_incident_field(dda_target* t, int nrhs, const double* khat, const double* ehat, void* e_dev,
+                                  void* hip_stream) {
+  if (!t || !khat || !ehat || !e_dev || nrhs < 1) return fail(DDA_EINVAL, "dda_incident_field: bad arguments");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_incident_field: occupancy not set");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(ensure_scratch(t, nrhs));
+  HIPCHK(hipMemcpyAsync(t->khat.p, khat, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(t->ehat.p, ehat, nrhs * 6 * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_einc, dim3((unsigned)std::min<long>((t->nd + 255) / 256, 4096), nrhs), dim3(256), 0, st,
+                     (c64*)e_dev, t->sites.as<int>(), (long)t->nd, t->K, t->J, t->kd, t->khat.as<double>(),
+                     t->ehat.as<double>());
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  return DDA_OK;
+}
+
+extern "C" int dda_cross_sections(dda_target* t, int nrhs, const double* S, const void* einc_dev, const void* p_dev,
+                                  double* cext, double* cabs, double* csca, void* hip_stream) {
+  CHK(check_ready(t, "dda_cross_sections"));
+  if (nrhs < 1 || !einc_dev || !p_dev) return fail(DDA_EINVAL, "dda_cross_sections: bad arguments");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(ensure_scratch(t, nrhs));
+  std::vector<double> hs(nrhs, 0.0);
+  if (S)
+    for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
+  HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  SolverDims dm;
+  dm.n3 = 3 * t->nd;
+  dm.nblk = nblocks_for(dm.n3);
+  CHK(t->part.ensure((size_t)nrhs * dm.nblk * 2 * sizeof(c64)));
+  hipLaunchKernelGGL(k_cross_sums, dim3(dm.nblk, nrhs), dim3(256), 0, st, (const c64*)einc_dev, (const c64*)p_dev,
+                     t->p64.a0.as<c64>(), t->has_a1 ? t->p64.a1.as<c64>() : nullptr, t->S.as<double>(), (long)t->nd,
+                     t->kd, dm, t->part.as<c64>());
+  LAUNCHCHK();
+  std::vector<c64> hp((size_t)nrhs * dm.nblk * 2);
+  HIPCHK(hipMemcpyAsync(hp.data(), t->part.p, hp.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double fk = 4.0 * M_PI * t->kd;
+  for (int q = 0; q < nrhs; ++q) {
+    double se = 0, sa = 0;
+    for (int bk = 0; bk < dm.nblk; ++bk) {
+      se += hp[((size_t)q * dm.nblk + bk) * 2].x;
+      sa += hp[((size_t)q * dm.nblk + bk) * 2 + 1].x;
+    }
+    if (cext) cext[q] = fk * se;
+    if (cabs) cabs[q] = fk * sa;
+    if (csca) csca[q] = fk * (se - sa);
+  }
+  return DDA_OK;
+}
+
+extern "C" int dda_grad_cabs_eps(dda_target* t, const dda_solve_opts* opts, int nrhs, const double* S,
+                                 const void* p_dev, void* grad_dev, void* hip_stream) {
+  CHK(check_ready(t, "dda_grad_cabs_eps"));
+  CHK(check_opts(opts, "dda_grad_cabs_eps"));
+  if (!t->have_eps) return fail(DDA_ESTATE, "dda_grad_cabs_eps: needs dda_set_permittivity");
+  if (nrhs < 1 || !p_dev || !grad_dev) return fail(DDA_EINVAL, "dda_grad_cabs_eps: bad arguments");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(ensure_scratch(t, nrhs));
+  CHK(ensure_outer(t, nrhs));
+  std::vector<double> hs(nrhs, 0.0);
+  if (S)
+    for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
+  HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  const long n3 = 3 * t->nd;
+  // adjoint right-hand side W conj(P) into a separate buffer (the outer slot 0
+  // holds E for plane-wave solves; the adjoint uses its own allocation)
+  DevBuf rhs, mu;
+  CHK(rhs.ensure((size_t)nrhs * n3 * sizeof(c64)));
+  CHK(mu.ensure((size_t)nrhs * n3 * sizeof(c64)));
+  const c64* a1 = t->has_a1 ? t->p64.a1.as<c64>() : nullptr;
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)std::min<long>((nrhs * n3 + 255) / 256, 65535)), dim3(256), 0, st,
+                     (const c64*)p_dev, rhs.as<c64>(), t->p64.a0.as<c64>(), a1, t->S.as<double>(), (long)t->nd, t->kd,
+                     nrhs);
+  LAUNCHCHK();
+  int rc = solve_core(t, *opts, nrhs, rhs.as<c64>(), mu.as<c64>(), nullptr, st);
+  if (rc != DDA_OK && rc != DDA_ENOTCONV) return rc;
+  hipLaunchKernelGGL(k_gradient, dim3((unsigned)std::min<long>((nrhs * t->nd + 255) / 256, 65535)), dim3(256), 0, st,
+                     (const c64*)p_dev, mu.as<c64>(), t->d0.as<c64>(), t->has_a1 ? t->d1.as<c64>() : nullptr,
+                     t->S.as<double>(), (long)t->nd, t->kd, nrhs, (c64*)grad_dev);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  return rc;
+}

@@ -1,0 +1,363 @@
+// Device kernels of the interaction spectrum and of the pruned FFT
+// matrix-vector product.
+//
+// Grid layouts (x fastest, as the linear site index n = k*J*K + j*K + i of
+// Appendix A):
+//   tensor first column   t  [6][P][J][K]            complex FP64
+//   spectrum              Y  [6][P_h][J_h][K_h]      unique octant, n_h = n''/2 + 1
+//   y-transformed vector  G1 [rhs][3][P][J''][K]     (Sec. 3: K x J'' x P array)
+//   xy-transformed vector G2 [rhs][3][P][J''][K'']   (the x-transformed rows of the
+//                                                     xz-planes of Sec. 3)
+//   compressed vectors    x, y [rhs][3][N_d]         occupied sites only (Sec. 4)
+#pragma once
+#include "fft_core.hpp"
+
+namespace dda {
+
+// Table 1 of the paper: parity of each tensor component (xx xy xz yy yz zz)
+// under reflection of the x, y and z displacement; the Toeplitz-to-circulant
+// mirror multiplies mirrored entries by it.
+__constant__ int8_t c_sign[3][6] = {
+    {+1, -1, -1, +1, +1, +1},
+    {+1, -1, +1, +1, -1, +1},
+    {+1, +1, -1, +1, -1, +1},
+};
+
+// ---------------------------------------------------------------------------
+// Tensor first column (Eq. 1): t(d) = -G(d) for d in [0,K)x[0,J)x[0,P), with
+// t(0) = 0 (the diagonal is excluded from the convolution, Sec. 3).
+// ---------------------------------------------------------------------------
+__global__ void k_tensor_column(c64* __restrict__ t, int K, int J, int P, double k) {
+  const long N = (long)K * J * P;
+  for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < N; s += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(s % K);
+    const int j = (int)((s / K) % J);
+    const int l = (int)(s / ((long)K * J));
+    double g[6] = {0, 0, 0, 0, 0, 0}, gi[6] = {0, 0, 0, 0, 0, 0};
+    if (s != 0) {
+      const double rx = i, ry = j, rz = l;
+      const double r2 = rx * rx + ry * ry + rz * rz;
+      const double r = sqrt(r2);
+      const double u[3] = {rx / r, ry / r, rz / r};
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      const double inv3 = 1.0 / (r2 * r);
+      // e^{ikr}/r^3 [k^2 r^2 (I - uu) + (1 - ikr)(3uu - I)]
+      const double pr = cs * inv3, pi = sn * inv3;
+      const double a = k * k * r2;
+      const int pq[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double d = (pq[c][0] == pq[c][1]) ? 1.0 : 0.0;
+        const double uu = u[pq[c][0]] * u[pq[c][1]];
+        const double br = 3.0 * uu - d;                  // (1 - ikr)(3uu - I): real part br, imag -kr br
+        const double mr = a * (d - uu) + br;             // real part of the bracket
+        const double mi = -k * r * br;                   // imaginary part of the bracket
+        g[c] = -(pr * mr - pi * mi);
+        gi[c] = -(pr * mi + pi * mr);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t[c * N + s] = mk(g[c], gi[c]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lines along the contiguous axis.  Line `ln` reads in[ln*lin_stride + e] for
+// e < Lin and writes out[ln*lout_stride + e] for e < Lout.
+// MIRROR: the implicit Toeplitz-to-circulant conversion of a tensor line
+// (Sec. 3): entry e > n - Lin holds sign * in[n - e] (Table 1), the rest of the
+// padded line is zero.
+// ---------------------------------------------------------------------------
+struct ContigArgs {
+  long nlines;
+  long lin_stride, lout_stride;
+  int Lin, Lout;
+  int rows;           // lines per workgroup
+  int ls;             // LDS line stride (>= n)
+  long lines_per_comp;  // for the mirror sign: component = (ln / lines_per_comp) % 6
+  int axis;           // which row of Table 1
+  long lines_per_rhs;   // for masking converged right-hand sides (0: none)
+  double scale;
+};
+
+template <typename R, bool INV, bool MIRROR>
+__global__ void __launch_bounds__(256) k_lines_contig(const cx<R>* __restrict__ in, cx<R>* __restrict__ out,
+                                                      ContigArgs a, FftDesc d, const cx<R>* __restrict__ tw,
+                                                      const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<R>* A = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* B = A + a.rows * a.ls;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long l0 = (long)blockIdx.x * a.rows;
+  const int nl = (int)min((long)a.rows, a.nlines - l0);
+  if (active && a.lines_per_rhs) {
+    // workgroups never straddle right-hand sides (rows divides lines_per_rhs)
+    if (!active[l0 / a.lines_per_rhs]) return;
+  }
+  const int n = d.n;
+  for (int idx = tid; idx < nl * n; idx += nthr) {
+    const int l = idx / n, e = idx - l * n;
+    const long ln = l0 + l;
+    const cx<R>* src = in + ln * a.lin_stride;
+    cx<R> v = mk((R)0, (R)0);
+    if (e < a.Lin) {
+      v = src[e];
+    } else if (MIRROR && e > n - a.Lin) {
+      v = src[n - e];
+      if (c_sign[a.axis][(ln / a.lines_per_comp) % 6] < 0) v = mk(-v.x, -v.y);
+    }
+    A[l * a.ls + e] = v;
+  }
+  __syncthreads();
+  cx<R>* res = lds_fft<R, INV>(A, B, d, tw, nl, a.ls, 1, tid, nthr);
+  const R sc = (R)a.scale;
+  for (int idx = tid; idx < nl * a.Lout; idx += nthr) {
+    const int l = idx / a.Lout, e = idx - l * a.Lout;
+    out[(l0 + l) * a.lout_stride + e] = sc * res[l * a.ls + e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lines along a strided axis, processed in tiles of TX adjacent x positions so
+// that every global row access is contiguous.  Element e of line (b, o, x) is
+// in[b*sb + o*so + e*se + x]; outputs go to out[b*tb + o*to + e*te + x].
+// grid = (ceil(NX/TX), NO, NB).
+// ---------------------------------------------------------------------------
+struct StridedArgs {
+  long sb, so, se, tb, to, te;
+  int NX, Lin, Lout, TX;
+  int axis;  // row of Table 1 for MIRROR
+};
+
+template <typename R, bool INV, bool MIRROR>
+__global__ void __launch_bounds__(256) k_lines_strided(const cx<R>* __restrict__ in, cx<R>* __restrict__ out,
+                                                       StridedArgs a, FftDesc d, const cx<R>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<R>* A = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* B = A + d.n * a.TX;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int x0 = blockIdx.x * a.TX;
+  const long o = blockIdx.y, b = blockIdx.z;
+  const int n = d.n, TX = a.TX;
+  const cx<R>* src = in + b * a.sb + o * a.so + x0;
+  const bool neg = MIRROR && c_sign[a.axis][b % 6] < 0;
+  for (int idx = tid; idx < n * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX;
+    cx<R> v = mk((R)0, (R)0);
+    if (x0 + l < a.NX) {
+      if (e < a.Lin) {
+        v = src[e * a.se + l];
+      } else if (MIRROR && e > n - a.Lin) {
+        v = src[(n - e) * a.se + l];
+        if (neg) v = mk(-v.x, -v.y);
+      }
+    }
+    A[e * TX + l] = v;
+  }
+  __syncthreads();
+  cx<R>* res = lds_fft<R, INV>(A, B, d, tw, TX, 1, TX, tid, nthr);
+  cx<R>* dst = out + b * a.tb + o * a.to + x0;
+  for (int idx = tid; idx < a.Lout * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX;
+    if (x0 + l < a.NX) dst[e * a.te + l] = res[e * TX + l];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal alpha_n^{-1} of right-hand side r: a0[n] + S[r] a1[n] (the LDR term
+// b3 S eps (kd)^2 depends on the incident direction and polarisation).
+// Point-Jacobi in symmetric form uses s_n = (alpha_n^{-1})^{-1/2}.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ cx<R> diag_of(const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1, R S, long n) {
+  cx<R> v = a0[n];
+  if (a1) v = v + S * a1[n];
+  return v;
+}
+template <typename R>
+__device__ __forceinline__ cx<R> jacobi_scale(cx<R> a) {
+  cx<R> q = csqrt(a);
+  return cdiv(mk((R)1, (R)0), q);
+}
+
+struct VecArgs {
+  int K, J, P, Jpp, Kpp, Ppp;
+  long nd;
+  int TX;
+  int jacobi;  // 0: y = A x;  1: y = D^{-1/2} A D^{-1/2} x with D = diag(alpha^{-1})
+  double scale;  // 1/(K''J''P'') for the inverse pass
+};
+
+// Expansion (Sec. 4) of the compressed vector into the zero-padded
+// [K x J'' x P] array fused with the forward DFT along y on the K*P lines that
+// hold data (Sec. 3).  grid = (ceil(K/TX), P, nrhs*3).
+template <typename R>
+__global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, cx<R>* __restrict__ G1,
+                                                  const int* __restrict__ map, const cx<R>* __restrict__ a0,
+                                                  const cx<R>* __restrict__ a1, const double* __restrict__ S,
+                                                  const int* __restrict__ active, VecArgs a, FftDesc d,
+                                                  const cx<R>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int rc = blockIdx.z, rhs = rc / 3;
+  if (active && !active[rhs]) return;
+  cx<R>* A = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* B = A + d.n * a.TX;
+  const int tid = threadIdx.x, nthr = blockDim.x, TX = a.TX;
+  const int i0 = blockIdx.x * TX, k = blockIdx.y;
+  const R Sr = S ? (R)S[rhs] : (R)0;
+  const cx<R>* xv = x + (long)rc * a.nd;
+  for (int idx = tid; idx < d.n * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX, i = i0 + l;
+    cx<R> v = mk((R)0, (R)0);
+    if (e < a.J && i < a.K) {
+      const int m = map[((long)k * a.J + e) * a.K + i];
+      if (m >= 0) {
+        v = xv[m];
+        if (a.jacobi) v = jacobi_scale(diag_of(a0, a1, Sr, m)) * v;
+      }
+    }
+    A[e * TX + l] = v;
+  }
+  __syncthreads();
+  cx<R>* res = lds_fft<R, false>(A, B, d, tw, TX, 1, TX, tid, nthr);
+  cx<R>* dst = G1 + ((long)rc * a.P + k) * a.Jpp * a.K + i0;
+  for (int idx = tid; idx < a.Jpp * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX;
+    if (i0 + l < a.K) dst[(long)e * a.K + l] = res[e * TX + l];
+  }
+}
+
+// Inverse DFT along y on the K*P lines that contribute, normalisation,
+// compression back to occupied sites (Sec. 4) and the diagonal term added back
+// (step 5 of the standard algorithm).  grid = (ceil(K/TX), P, nrhs*3).
+template <typename R>
+__global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x,
+                                                  cx<R>* __restrict__ y, const int* __restrict__ map,
+                                                  const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
+                                                  const double* __restrict__ S, const int* __restrict__ active,
+                                                  VecArgs a, FftDesc d, const cx<R>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int rc = blockIdx.z, rhs = rc / 3;
+  if (active && !active[rhs]) return;
+  cx<R>* A = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* B = A + d.n * a.TX;
+  const int tid = threadIdx.x, nthr = blockDim.x, TX = a.TX;
+  const int i0 = blockIdx.x * TX, k = blockIdx.y;
+  const cx<R>* src = G1 + ((long)rc * a.P + k) * a.Jpp * a.K + i0;
+  for (int idx = tid; idx < d.n * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX;
+    A[e * TX + l] = (i0 + l < a.K) ? src[(long)e * a.K + l] : mk((R)0, (R)0);
+  }
+  __syncthreads();
+  cx<R>* res = lds_fft<R, true>(A, B, d, tw, TX, 1, TX, tid, nthr);
+  const R Sr = S ? (R)S[rhs] : (R)0;
+  const R sc = (R)a.scale;
+  const cx<R>* xv = x + (long)rc * a.nd;
+  cx<R>* yv = y + (long)rc * a.nd;
+  for (int idx = tid; idx < a.J * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX, i = i0 + l;
+    if (i >= a.K) continue;
+    const int m = map[((long)k * a.J + e) * a.K + i];
+    if (m < 0) continue;
+    const cx<R> conv = sc * res[e * TX + l];
+    const cx<R> dg = diag_of(a0, a1, Sr, m);
+    if (a.jacobi) {
+      yv[m] = xv[m] + jacobi_scale(dg) * conv;
+    } else {
+      yv[m] = dg * xv[m] + conv;
+    }
+  }
+}
+
+// z direction: forward DFT of the three components on all K''*J'' lines, the
+// element-wise product with the 3x3 symmetric spectrum (Eqs. Q0-Q2) read from
+// the unique octant with mirrored indices and Table 1 signs, and the inverse
+// DFT keeping the first P entries (Sec. 3).  In place on G2.
+// grid = (ceil(K''/TX), J'', nrhs).
+struct ZArgs {
+  int Kpp, Jpp, P, Ppp, Kh, Jh, Ph, TX;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_vec_zmul(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y,
+                                                  const int* __restrict__ active, ZArgs a, FftDesc d,
+                                                  const cx<R>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int rhs = blockIdx.z;
+  if (active && !active[rhs]) return;
+  const int tid = threadIdx.x, nthr = blockDim.x, TX = a.TX, n = d.n;
+  cx<R>* buf[4];
+  buf[0] = reinterpret_cast<cx<R>*>(smem);
+  for (int q = 1; q < 4; ++q) buf[q] = buf[q - 1] + n * TX;
+  const int i0 = blockIdx.x * TX, jj = blockIdx.y;
+  const long plane = (long)a.Jpp * a.Kpp;
+  for (int c = 0; c < 3; ++c) {
+    const cx<R>* src = G2 + ((long)(rhs * 3 + c) * a.P) * plane + (long)jj * a.Kpp + i0;
+    for (int idx = tid; idx < n * TX; idx += nthr) {
+      const int e = idx / TX, l = idx - e * TX;
+      buf[c][e * TX + l] = (e < a.P && i0 + l < a.Kpp) ? src[e * plane + l] : mk((R)0, (R)0);
+    }
+  }
+  __syncthreads();
+  int slot[3] = {0, 1, 2}, fr = 3;
+  for (int c = 0; c < 3; ++c) {
+    cx<R>* r = lds_fft<R, false>(buf[slot[c]], buf[fr], d, tw, TX, 1, TX, tid, nthr);
+    if (r == buf[fr]) {
+      const int t = slot[c];
+      slot[c] = fr;
+      fr = t;
+    }
+  }
+  // spectral product
+  const int jm = min(jj, a.Jpp - jj);
+  const bool my = jj > a.Jpp - jj;
+  for (int idx = tid; idx < n * TX; idx += nthr) {
+    const int e = idx / TX, l = idx - e * TX, i = i0 + l;
+    if (i >= a.Kpp) continue;
+    const int im = min(i, a.Kpp - i), km = min(e, n - e);
+    const bool mx = i > a.Kpp - i, mz = e > n - e;
+    const cx<R>* ys = Y + ((long)km * a.Jh + jm) * a.Kh + im;
+    const long cs = (long)a.Ph * a.Jh * a.Kh;
+    cx<R> yv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      int sg = 1;
+      if (mx) sg *= c_sign[0][c];
+      if (my) sg *= c_sign[1][c];
+      if (mz) sg *= c_sign[2][c];
+      cx<R> v = ys[c * cs];
+      yv[c] = sg < 0 ? mk(-v.x, -v.y) : v;
+    }
+    const int o = e * TX + l;
+    const cx<R> x0 = buf[slot[0]][o], x1 = buf[slot[1]][o], x2 = buf[slot[2]][o];
+    buf[slot[0]][o] = yv[0] * x0 + yv[1] * x1 + yv[2] * x2;
+    buf[slot[1]][o] = yv[1] * x0 + yv[3] * x1 + yv[4] * x2;
+    buf[slot[2]][o] = yv[2] * x0 + yv[4] * x1 + yv[5] * x2;
+  }
+  __syncthreads();
+  for (int c = 0; c < 3; ++c) {
+    cx<R>* r = lds_fft<R, true>(buf[slot[c]], buf[fr], d, tw, TX, 1, TX, tid, nthr);
+    if (r == buf[fr]) {
+      const int t = slot[c];
+      slot[c] = fr;
+      fr = t;
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    cx<R>* dst = G2 + ((long)(rhs * 3 + c) * a.P) * plane + (long)jj * a.Kpp + i0;
+    for (int idx = tid; idx < a.P * TX; idx += nthr) {
+      const int e = idx / TX, l = idx - e * TX;
+      if (i0 + l < a.Kpp) dst[e * plane + l] = buf[slot[c]][e * TX + l];
+    }
+  }
+}
+
+// FP64 -> FP32 copy with round-to-nearest-even (the FP32 spectrum is the FP64
+// spectrum rounded).
+__global__ void k_round_to_f32(const c64* __restrict__ in, c32* __restrict__ out, long n) {
+  for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < n; s += (long)gridDim.x * blockDim.x)
+    out[s] = mk((float)in[s].x, (float)in[s].y);
+}
+
+}  // namespace dda

@@ -1,0 +1,708 @@
+// Krylov-solver kernels: fused vector updates with wavefront reductions that
+// accumulate in FP64 whatever the vector precision, and one-block-per-RHS
+// finalisers that reduce the partial sums in a fixed order (deterministic) and
+// update the per-RHS solver scalars on the device, so the host never waits on
+// a scalar inside the iteration.
+//
+// Vectors are [nrhs][3][N_d]; each right-hand side has its own scalars and an
+// `active` flag (0 once converged or stopped) that masks every kernel.
+#pragma once
+#include "common.hpp"
+
+namespace dda {
+
+constexpr int kRedThreads = 256;
+
+// Sum of ND complex values over a 256-thread block, in a fixed order.
+// Result valid in thread 0.
+template <int ND>
+__device__ __forceinline__ void block_sum(c64 (&v)[ND]) {
+  __shared__ c64 sh[ND][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < ND; ++q) {
+    double a = v[q].x, b = v[q].y;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
+    }
+    if (lane == 0) sh[q][wv] = mk(a, b);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+      c64 s = sh[q][0];
+      for (int w = 1; w < kRedThreads / 64; ++w) s = s + sh[q][w];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Reduce nblk partial blocks of ND sums for right-hand side `rhs` (fixed
+// order); result valid in thread 0.
+template <int ND>
+__device__ __forceinline__ void reduce_partials(const c64* __restrict__ part, int nblk, int rhs, c64 (&v)[ND]) {
+#pragma unroll
+  for (int q = 0; q < ND; ++q) v[q] = mk(0.0, 0.0);
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const c64* p = part + ((long)rhs * nblk + b) * ND;
+#pragma unroll
+    for (int q = 0; q < ND; ++q) v[q] = v[q] + p[q];
+  }
+  block_sum<ND>(v);
+}
+
+// complex helpers in FP64 for mixed products
+template <typename R>
+__device__ __forceinline__ c64 up(cx<R> a) { return mk((double)a.x, (double)a.y); }
+__device__ __forceinline__ c64 cmulc(c64 a, c64 b) { return conjg(a) * b; }  // a^H b term
+
+struct SolverDims {
+  long n3;    // 3 * N_d elements per right-hand side
+  int nblk;   // blocks per right-hand side in the vector kernels
+};
+
+// Grid-stride range of this block inside one right-hand side's vector.
+#define DDA_RANGE(dims, i)                                                        \
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (dims).n3; \
+       i += (long)(dims).nblk * blockDim.x)
+
+// ============================================================================
+// BiCGSTAB (van der Vorst 1992), complex, Hermitian inner products
+// ============================================================================
+struct BcgState {
+  c64 rho, rho_old, alpha, omega, beta;
+  double bnorm2, rnorm2, tol2;
+  int s_conv, converged, breakdown, iters;
+};
+
+// r = b, rhat = b, p = v = u = 0; partials |b|^2
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
+                                                  cx<R>* __restrict__ rhat, cx<R>* __restrict__ p,
+                                                  cx<R>* __restrict__ v, cx<R>* __restrict__ u,
+                                                  const int* __restrict__ active, SolverDims dm,
+                                                  c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[1] = {mk(0.0, 0.0)};
+  if (active[rhs]) {
+    const long o = (long)rhs * dm.n3;
+    DDA_RANGE(dm, i) {
+      const cx<R> bv = b[o + i];
+      r[o + i] = bv;
+      rhat[o + i] = bv;
+      p[o + i] = mk((R)0, (R)0);
+      v[o + i] = mk((R)0, (R)0);
+      u[o + i] = mk((R)0, (R)0);
+      acc[0].x += abs2(up(bv));
+    }
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
+}
+
+__global__ void k_bcg_fin_init(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
+                               int* __restrict__ active, double tol) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[1];
+  reduce_partials<1>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    BcgState s;
+    s.bnorm2 = v[0].x;
+    s.rnorm2 = v[0].x;
+    s.tol2 = tol * tol * v[0].x;
+    s.rho = mk(v[0].x, 0.0);  // rhat = r = b
+    s.rho_old = mk(1.0, 0.0);
+    s.alpha = mk(1.0, 0.0);
+    s.omega = mk(1.0, 0.0);
+    s.beta = mk(0.0, 0.0);
+    s.s_conv = 0;
+    s.converged = v[0].x == 0.0;
+    s.breakdown = 0;
+    s.iters = 0;
+    st[rhs] = s;
+    if (s.converged) active[rhs] = 0;
+  }
+}
+
+// p = r + beta (p - omega v)
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R>* __restrict__ p,
+                                               const cx<R>* __restrict__ v, const BcgState* __restrict__ st,
+                                               const int* __restrict__ active, SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const cx<R> beta = cvt<R>(st[rhs].beta), om = cvt<R>(st[rhs].omega);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) { p[o + i] = r[o + i] + beta * (p[o + i] - om * v[o + i]); }
+}
+
+// partials of a^H b (ND = 1) or of a^H b and a^H a (ND = 2)
+template <typename R, int ND>
+__global__ void __launch_bounds__(256) k_dots(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
+                                              const int* __restrict__ active, SolverDims dm,
+                                              c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 acc[ND];
+#pragma unroll
+  for (int q = 0; q < ND; ++q) acc[q] = mk(0.0, 0.0);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const c64 av = up(a[o + i]);
+    acc[0] = acc[0] + cmulc(av, up(b[o + i]));
+    if (ND > 1) acc[1].x += abs2(av);
+  }
+  block_sum<ND>(acc);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < ND; ++q) part[((long)rhs * dm.nblk + blockIdx.x) * ND + q] = acc[q];
+}
+
+__device__ __forceinline__ bool tiny(c64 a, double scale) { return !(abs2(a) > 1e-300 * scale); }
+
+// alpha = rho / (rhat^H v)
+__global__ void k_bcg_fin_alpha(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
+                                int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[1];
+  reduce_partials<1>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    BcgState& s = st[rhs];
+    if (tiny(v[0], s.bnorm2 * s.bnorm2) || !isfinite(v[0].x)) {
+      s.breakdown = 1;
+      active[rhs] = 0;
+      return;
+    }
+    s.alpha = cdiv(s.rho, v[0]);
+  }
+}
+
+// s = r - alpha v (stored in r); partials |s|^2
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_s(cx<R>* __restrict__ r, const cx<R>* __restrict__ v,
+                                               const BcgState* __restrict__ st, const int* __restrict__ active,
+                                               SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const cx<R> al = cvt<R>(st[rhs].alpha);
+  c64 acc[1] = {mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> s = r[o + i] - al * v[o + i];
+    r[o + i] = s;
+    acc[0].x += abs2(up(s));
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
+}
+
+__global__ void k_bcg_fin_s(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
+                            const int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[1];
+  reduce_partials<1>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    BcgState& s = st[rhs];
+    s.s_conv = v[0].x <= s.tol2;
+    if (s.s_conv) s.rnorm2 = v[0].x;
+  }
+}
+
+// omega = t^H s / t^H t  (partials: [t^H s, t^H t])
+__global__ void k_bcg_fin_omega(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
+                                const int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    BcgState& s = st[rhs];
+    if (s.s_conv) return;
+    s.omega = (v[1].x > 0.0) ? mk(v[0].x / v[1].x, v[0].y / v[1].x) : mk(0.0, 0.0);
+  }
+}
+
+// u += alpha p + omega s;  r = s - omega t;  partials |r|^2, rhat^H r
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_update(cx<R>* __restrict__ u, cx<R>* __restrict__ r,
+                                                    const cx<R>* __restrict__ p, const cx<R>* __restrict__ t,
+                                                    const cx<R>* __restrict__ rhat,
+                                                    const BcgState* __restrict__ st,
+                                                    const int* __restrict__ active, SolverDims dm,
+                                                    c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const BcgState& s = st[rhs];
+  const cx<R> al = cvt<R>(s.alpha), om = cvt<R>(s.omega);
+  const bool sc = s.s_conv;
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> sv = r[o + i];
+    if (sc) {
+      u[o + i] = u[o + i] + al * p[o + i];
+    } else {
+      u[o + i] = u[o + i] + al * p[o + i] + om * sv;
+      const cx<R> rn = sv - om * t[o + i];
+      r[o + i] = rn;
+      const c64 rd = up(rn);
+      acc[0].x += abs2(rd);
+      acc[1] = acc[1] + cmulc(up(rhat[o + i]), rd);
+    }
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+__global__ void k_bcg_fin_iter(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
+                               int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    BcgState& s = st[rhs];
+    s.iters += 1;
+    if (s.s_conv) {
+      s.converged = 1;
+      active[rhs] = 0;
+      return;
+    }
+    s.rnorm2 = v[0].x;
+    s.rho_old = s.rho;
+    s.rho = v[1];
+    if (!isfinite(v[0].x)) {
+      s.breakdown = 1;
+      active[rhs] = 0;
+      return;
+    }
+    if (s.rnorm2 <= s.tol2) {
+      s.converged = 1;
+      active[rhs] = 0;
+      return;
+    }
+    if (tiny(s.omega, 1.0) || tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32)) {
+      s.breakdown = 1;  // restart from the current iterate (host)
+      active[rhs] = 0;
+      return;
+    }
+    s.beta = cdiv(s.rho, s.rho_old) * cdiv(s.alpha, s.omega);
+  }
+}
+
+// ============================================================================
+// QMR for complex-symmetric matrices (Freund 1992): Lanczos with the bilinear
+// form x^T y and Euclidean-normalised vectors, quasi-minimal residual by
+// Givens rotations, the residual carried alongside via q_n = A p_n.
+// ============================================================================
+struct QmrState {
+  c64 alpha, beta, delta, delta_prev;  // Lanczos scalars
+  double rho, rho_next;                // Euclidean norms of the unnormalised vectors
+  c64 s1, s2;                          // sines of rotations n-1, n-2
+  double c1, c2;                       // cosines of rotations n-1, n-2
+  c64 tau, coef, ep, fpp, rnn;         // quasi-residual, step, new column entries
+  double bnorm2, rnorm2, tol2;
+  int converged, breakdown, iters, n;
+};
+
+// r = b; u = 0; vprev = 0; v = b/|b|; p, pprev, q, qprev = 0; partials |b|^2, b^T b
+template <typename R>
+__global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
+                                                    cx<R>* __restrict__ u, cx<R>* __restrict__ vprev,
+                                                    cx<R>* __restrict__ pa, cx<R>* __restrict__ pb,
+                                                    cx<R>* __restrict__ qa, cx<R>* __restrict__ qb,
+                                                    const int* __restrict__ active, SolverDims dm,
+                                                    c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  if (active[rhs]) {
+    const long o = (long)rhs * dm.n3;
+    const cx<R> z = mk((R)0, (R)0);
+    DDA_RANGE(dm, i) {
+      const cx<R> bv = b[o + i];
+      r[o + i] = bv;
+      u[o + i] = z;
+      vprev[o + i] = z;
+      pa[o + i] = z;
+      pb[o + i] = z;
+      qa[o + i] = z;
+      qb[o + i] = z;
+      const c64 bd = up(bv);
+      acc[0].x += abs2(bd);
+      acc[1] = acc[1] + bd * bd;
+    }
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+__global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
+                               int* __restrict__ active, double tol) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    QmrState s;
+    const double nb2 = v[0].x;
+    s.bnorm2 = nb2;
+    s.rnorm2 = nb2;
+    s.tol2 = tol * tol * nb2;
+    s.rho = sqrt(nb2);
+    s.rho_next = 0.0;
+    s.delta = nb2 > 0 ? mk(v[1].x / nb2, v[1].y / nb2) : mk(1.0, 0.0);
+    s.delta_prev = mk(1.0, 0.0);
+    s.alpha = s.beta = mk(0.0, 0.0);
+    s.s1 = s.s2 = mk(0.0, 0.0);
+    s.c1 = s.c2 = 1.0;
+    s.tau = mk(s.rho, 0.0);
+    s.coef = s.ep = s.fpp = s.rnn = mk(0.0, 0.0);
+    s.converged = nb2 == 0.0;
+    s.breakdown = 0;
+    s.iters = 0;
+    s.n = 0;
+    st[rhs] = s;
+    if (s.converged) active[rhs] = 0;
+  }
+}
+
+// v = b / rho_1
+template <typename R>
+__global__ void __launch_bounds__(256) k_qmr_init_b(const cx<R>* __restrict__ b, cx<R>* __restrict__ v,
+                                                    const QmrState* __restrict__ st,
+                                                    const int* __restrict__ active, SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const R inv = (R)(1.0 / st[rhs].rho);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) { v[o + i] = inv * b[o + i]; }
+}
+
+// partials of v^T w (bilinear)
+template <typename R>
+__global__ void __launch_bounds__(256) k_bil_dot(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
+                                                 const int* __restrict__ active, SolverDims dm,
+                                                 c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 acc[1] = {mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) { acc[0] = acc[0] + up(a[o + i]) * up(b[o + i]); }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
+}
+
+// alpha_n = v_n^T A v_n / delta_n;  beta_n = rho_n delta_n / delta_{n-1} (0 for n = 1)
+__global__ void k_qmr_fin_alpha(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
+                                int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[1];
+  reduce_partials<1>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    QmrState& s = st[rhs];
+    s.n += 1;
+    s.alpha = cdiv(v[0], s.delta);
+    s.beta = (s.n == 1) ? mk(0.0, 0.0) : s.rho * cdiv(s.delta, s.delta_prev);
+  }
+}
+
+// vt = w - alpha v - beta vprev, written over vprev; partials |vt|^2, vt^T vt
+template <typename R>
+__global__ void __launch_bounds__(256) k_qmr_vt(const cx<R>* __restrict__ w, const cx<R>* __restrict__ v,
+                                                cx<R>* __restrict__ vprev, const QmrState* __restrict__ st,
+                                                const int* __restrict__ active, SolverDims dm,
+                                                c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const cx<R> al = cvt<R>(st[rhs].alpha), be = cvt<R>(st[rhs].beta);
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> t = w[o + i] - al * v[o + i] - be * vprev[o + i];
+    vprev[o + i] = t;
+    const c64 td = up(t);
+    acc[0].x += abs2(td);
+    acc[1] = acc[1] + td * td;
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+// rho_{n+1}, delta_{n+1}; the new column (beta_n, alpha_n, rho_{n+1}) of the
+// tridiagonal matrix is rotated by the two previous Givens rotations and a new
+// one annihilates rho_{n+1}.
+__global__ void k_qmr_fin_givens(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
+                                 int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    QmrState& s = st[rhs];
+    const double h = sqrt(v[0].x);
+    s.rho_next = h;
+    const c64 f = s.beta, g = s.alpha;
+    // rotation n-2 acts on rows (n-2, n-1): entry of row n-2 was 0
+    const c64 ep = s.s2 * f;
+    const c64 fp = s.c2 * f;
+    // rotation n-1 acts on rows (n-1, n)
+    const c64 fpp = s.c1 * fp + s.s1 * g;
+    const c64 gp = s.c1 * g - conjg(s.s1) * fp;
+    // new rotation: [c s; -conj(s) c] (gp, h)^T = (rnn, 0)^T
+    const double ag = sqrt(abs2(gp));
+    double c;
+    c64 sn, rnn;
+    if (ag == 0.0) {
+      c = 0.0;
+      sn = mk(1.0, 0.0);
+      rnn = mk(h, 0.0);
+    } else {
+      const double nrm = sqrt(ag * ag + h * h);
+      c = ag / nrm;
+      sn = (c * h) * cdiv(mk(1.0, 0.0), conjg(gp));
+      rnn = (nrm / ag) * gp;
+    }
+    s.ep = ep;
+    s.fpp = fpp;
+    s.rnn = rnn;
+    s.coef = c * s.tau;
+    s.tau = (-1.0) * (conjg(sn) * s.tau);
+    s.c2 = s.c1;
+    s.s2 = s.s1;
+    s.c1 = c;
+    s.s1 = sn;
+    // Lanczos normalisation for the next step
+    s.delta_prev = s.delta;
+    s.delta = (h > 0.0) ? mk(v[1].x / (h * h), v[1].y / (h * h)) : mk(0.0, 0.0);
+    if (!(abs2(rnn) > 0.0) || !isfinite(h)) {
+      s.breakdown = 1;
+      active[rhs] = 0;
+    }
+  }
+}
+
+// v_{n+1} = vt / rho_{n+1} (in place over vprev), p_n = (v_n - f'' p_{n-1} - e' p_{n-2}) / r_nn
+// written over p_{n-2}, q_n = A p_n likewise from w, u += coef p_n,
+// r -= coef q_n; partials |r|^2
+template <typename R>
+__global__ void __launch_bounds__(256) k_qmr_update(cx<R>* __restrict__ vnext, const cx<R>* __restrict__ v,
+                                                    const cx<R>* __restrict__ w, const cx<R>* __restrict__ p1,
+                                                    cx<R>* __restrict__ p2, const cx<R>* __restrict__ q1,
+                                                    cx<R>* __restrict__ q2, cx<R>* __restrict__ u,
+                                                    cx<R>* __restrict__ r, const QmrState* __restrict__ st,
+                                                    const int* __restrict__ active, SolverDims dm,
+                                                    c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const QmrState& s = st[rhs];
+  const R hinv = s.rho_next > 0.0 ? (R)(1.0 / s.rho_next) : (R)0;
+  const c64 ri = cdiv(mk(1.0, 0.0), s.rnn);
+  const cx<R> fpp = cvt<R>(s.fpp), ep = cvt<R>(s.ep), rinv = cvt<R>(ri), cf = cvt<R>(s.coef);
+  c64 acc[1] = {mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    vnext[o + i] = hinv * vnext[o + i];
+    const cx<R> pn = rinv * (v[o + i] - fpp * p1[o + i] - ep * p2[o + i]);
+    const cx<R> qn = rinv * (w[o + i] - fpp * q1[o + i] - ep * q2[o + i]);
+    p2[o + i] = pn;
+    q2[o + i] = qn;
+    u[o + i] = u[o + i] + cf * pn;
+    const cx<R> rn = r[o + i] - cf * qn;
+    r[o + i] = rn;
+    acc[0].x += abs2(up(rn));
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
+}
+
+__global__ void k_qmr_fin_conv(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
+                               int* __restrict__ active) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[1];
+  reduce_partials<1>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    QmrState& s = st[rhs];
+    s.iters += 1;
+    s.rho = s.rho_next;
+    s.rnorm2 = v[0].x;
+    if (!isfinite(v[0].x)) {
+      s.breakdown = 1;
+      active[rhs] = 0;
+    } else if (s.rnorm2 <= s.tol2) {
+      s.converged = 1;
+      active[rhs] = 0;
+    } else if (!(s.rho > 0.0) || !(abs2(s.delta) > 1e-300)) {
+      s.breakdown = 1;
+      active[rhs] = 0;
+    }
+  }
+}
+
+// ============================================================================
+// Outer (FP64) refinement, incident field, cross sections, gradient
+// ============================================================================
+
+// Incident plane wave E[r][c][n] = ehat_r[c] exp(i k khat_r . r_n) (Sec. 1),
+// site coordinates from the linear index n = k*J*K + j*K + i.
+__global__ void k_einc(c64* __restrict__ E, const int* __restrict__ sites, long nd, int K, int J, double k,
+                       const double* __restrict__ khat, const double* __restrict__ ehat) {
+  const int rhs = blockIdx.y;
+  const double* kh = khat + 3 * rhs;
+  const double* eh = ehat + 6 * rhs;
+  for (long n = blockIdx.x * (long)blockDim.x + threadIdx.x; n < nd; n += (long)gridDim.x * blockDim.x) {
+    const int s = sites[n];
+    const double x = s % K, y = (s / K) % J, z = s / (K * J);
+    double sn, cs;
+    sincos(k * (kh[0] * x + kh[1] * y + kh[2] * z), &sn, &cs);
+    const c64 ph = mk(cs, sn);
+    for (int c = 0; c < 3; ++c) E[((long)rhs * 3 + c) * nd + n] = mk(eh[2 * c], eh[2 * c + 1]) * ph;
+  }
+}
+
+// out[r] = (jacobi ? s_n : 1) * in[r] * scale_r  (FP64 -> precision R), the
+// right-hand side of an inner solve
+template <typename R>
+__global__ void k_scale_rhs(const c64* __restrict__ in, cx<R>* __restrict__ out, const c64* __restrict__ a0,
+                            const c64* __restrict__ a1, const double* __restrict__ S,
+                            const double* __restrict__ sc, const int* __restrict__ active, long nd,
+                            int jacobi) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const long n3 = 3 * nd;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x) {
+    const long n = i % nd;
+    c64 v = sc[rhs] * in[(long)rhs * n3 + i];
+    if (jacobi) {
+      c64 a = a0[n];
+      if (a1) a = a + S[rhs] * a1[n];
+      v = cdiv(mk(1.0, 0.0), csqrt(a)) * v;
+    }
+    out[(long)rhs * n3 + i] = cvt<R>(v);
+  }
+}
+
+// P += (jacobi ? s_n : 1) * d * scale_r   (d in precision R)
+template <typename R>
+__global__ void k_accumulate(c64* __restrict__ P, const cx<R>* __restrict__ d, const c64* __restrict__ a0,
+                             const c64* __restrict__ a1, const double* __restrict__ S,
+                             const double* __restrict__ sc, const int* __restrict__ active, long nd,
+                             int jacobi) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const long n3 = 3 * nd;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x) {
+    const long n = i % nd;
+    c64 v = sc[rhs] * up(d[(long)rhs * n3 + i]);
+    if (jacobi) {
+      c64 a = a0[n];
+      if (a1) a = a + S[rhs] * a1[n];
+      v = cdiv(mk(1.0, 0.0), csqrt(a)) * v;
+    }
+    P[(long)rhs * n3 + i] = P[(long)rhs * n3 + i] + v;
+  }
+}
+
+// r = E - y; partials |r|^2 and |E|^2
+__global__ void __launch_bounds__(256) k_residual(const c64* __restrict__ E, const c64* __restrict__ y,
+                                                  c64* __restrict__ r, SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const c64 e = E[o + i];
+    const c64 rv = e - y[o + i];
+    r[o + i] = rv;
+    acc[0].x += abs2(rv);
+    acc[1].x += abs2(e);
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+// Sums for the cross sections (Draine 1988, |E0| = 1):
+//   [0] sum Im(E^* . P)              -> C_ext = 4 pi k [0]
+//   [1] sum |P|^2 (-Im a_n - 2k^3/3)  -> C_abs = 4 pi k [1]
+__global__ void __launch_bounds__(256) k_cross_sums(const c64* __restrict__ E, const c64* __restrict__ P,
+                                                    const c64* __restrict__ a0, const c64* __restrict__ a1,
+                                                    const double* __restrict__ S, long nd, double k,
+                                                    SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  const double rad = (2.0 / 3.0) * k * k * k;
+  DDA_RANGE(dm, i) {
+    const long n = i % nd;
+    const c64 pv = P[o + i];
+    acc[0].x += (conjg(E[o + i]) * pv).y;
+    c64 a = a0[n];
+    if (a1) a = a + S[rhs] * a1[n];
+    acc[1].x += abs2(pv) * (-a.y - rad);
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+// Adjoint right-hand side W conj(P), w_n = 4 pi k (-Im alpha_n^{-1} - 2k^3/3)
+__global__ void k_adjoint_rhs(const c64* __restrict__ P, c64* __restrict__ out, const c64* __restrict__ a0,
+                              const c64* __restrict__ a1, const double* __restrict__ S, long nd, double k,
+                              int nrhs) {
+  const long n3 = 3 * nd;
+  const double rad = (2.0 / 3.0) * k * k * k, fk = 4.0 * M_PI * k;
+  for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < n3 * nrhs; g += (long)gridDim.x * blockDim.x) {
+    const int rhs = (int)(g / n3);
+    const long n = (g % n3) % nd;
+    c64 a = a0[n];
+    if (a1) a = a + S[rhs] * a1[n];
+    out[g] = (fk * (-a.y - rad)) * conjg(P[g]);
+  }
+}
+
+// dC_abs/d eps_n from the forward and adjoint solutions (A mu = W conj(P)):
+//   dC/dRe = -2 Re[(mu_n . P_n) a'] - 4 pi k Im[a'] |P_n|^2
+//   dC/dIm = +2 Im[(mu_n . P_n) a'] - 4 pi k Re[a'] |P_n|^2
+// with a' = d alpha_n^{-1} / d eps_n = d0[n] + S_r d1[n]; out = dRe + i dIm.
+__global__ void k_gradient(const c64* __restrict__ P, const c64* __restrict__ mu, const c64* __restrict__ d0,
+                           const c64* __restrict__ d1, const double* __restrict__ S, long nd, double k,
+                           int nrhs, c64* __restrict__ grad) {
+  const double fk = 4.0 * M_PI * k;
+  for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < nd * nrhs; g += (long)gridDim.x * blockDim.x) {
+    const int rhs = (int)(g / nd);
+    const long n = g % nd;
+    const long o = (long)rhs * 3 * nd + n;
+    c64 muP = mk(0.0, 0.0);
+    double p2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      muP = muP + mu[o + c * nd] * P[o + c * nd];
+      p2 += abs2(P[o + c * nd]);
+    }
+    c64 da = d0[n];
+    if (d1) da = da + S[rhs] * d1[n];
+    const c64 m = muP * da;
+    grad[g] = mk(-2.0 * m.x - fk * da.y * p2, 2.0 * m.y - fk * da.x * p2);
+  }
+}
+
+}  // namespace dda

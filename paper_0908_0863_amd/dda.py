@@ -1,0 +1,280 @@
+"""Thin ctypes binding of libdda (include/dda.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libdda.so.  Device memory and streams come from PyTorch (ROCm);
+vectors are torch tensors of shape [nrhs, 3, N_d], complex128 (FP64) or
+complex64 (FP32), on the library's device.
+
+Functions keep the C names (``dda_open``, ``dda_target_create``, ...);
+``Library`` and ``Target`` are small owners of the handles on top of them.
+If libdda.so is missing this module raises on load: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime that libdda binds to
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdda.so")
+
+DDA_OK, DDA_EINVAL, DDA_ENOMEM, DDA_EDEVICE, DDA_ENOTCONV, DDA_ESTATE = 0, -1, -2, -3, -4, -5
+DDA_FP64, DDA_FP32 = 0, 1
+DDA_POL_CM, DDA_POL_RR, DDA_POL_LDR = 0, 1, 2
+DDA_BICGSTAB, DDA_QMR_SYM = 0, 1
+DDA_SOLVE_FP64, DDA_SOLVE_MIXED = 0, 1
+
+_PRESC = {"cm": DDA_POL_CM, "rr": DDA_POL_RR, "ldr": DDA_POL_LDR}
+_SOLVER = {"bicgstab": DDA_BICGSTAB, "qmr": DDA_QMR_SYM, "qmr_sym": DDA_QMR_SYM}
+_SPREC = {"fp64": DDA_SOLVE_FP64, "mixed": DDA_SOLVE_MIXED}
+
+
+class DDAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdda error {code}: {msg}")
+        self.code = code
+
+
+class NotConverged(DDAError):
+    pass
+
+
+class dda_solve_opts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("jacobi", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class dda_solve_info(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int), ("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
+                ("matvecs", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+# Every symbol the header declares (tests check that the library exports them).
+EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
+           "dda_set_permittivity", "dda_set_polarizability", "dda_build_spectrum", "dda_matvec", "dda_solve",
+           "dda_incident_field", "dda_cross_sections", "dda_grad_cabs_eps", "dda_target_info",
+           "dda_get_spectrum", "dda_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Open libdda.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libdda.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "dda_open": (i, [i, ctypes.c_char_p, P(vp)]),
+        "dda_close": (None, [vp]),
+        "dda_target_create": (i, [vp, i, i, i, d, P(vp)]),
+        "dda_target_destroy": (None, [vp]),
+        "dda_set_occupancy": (i, [vp, vp, P(i64)]),
+        "dda_set_permittivity": (i, [vp, vp, i]),
+        "dda_set_polarizability": (i, [vp, vp]),
+        "dda_build_spectrum": (i, [vp, vp]),
+        "dda_matvec": (i, [vp, i, i, vp, i, vp, vp, vp]),
+        "dda_solve": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp, vp, vp, vp]),
+        "dda_incident_field": (i, [vp, i, vp, vp, vp, vp]),
+        "dda_cross_sections": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
+        "dda_grad_cabs_eps": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp]),
+        "dda_target_info": (i, [vp, vp]),
+        "dda_get_spectrum": (i, [vp, i, vp, vp]),
+        "dda_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != DDA_OK:
+        msg = load().dda_last_error().decode()
+        if rc == DDA_ENOTCONV:
+            raise NotConverged(rc, msg)
+        raise DDAError(rc, msg)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _opt_np(a, dtype, n):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=dtype).reshape(-1))
+    if arr.size != n:
+        raise ValueError(f"expected {n} values, got {arr.size}")
+    return arr, _np_ptr(arr)
+
+
+class Library:
+    """An opened libdda on one HIP device."""
+
+    def __init__(self, device: int | None = None, tune_cache: str | None = None):
+        lib = load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib.dda_open(device, tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().dda_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Target:
+    """A lattice target: occupancy, polarisabilities and the interaction spectrum."""
+
+    def __init__(self, lib: Library, K: int, J: int, P: int, kd: float):
+        self.lib = lib
+        self.K, self.J, self.P, self.kd = int(K), int(J), int(P), float(kd)
+        h = ctypes.c_void_p()
+        _check(load().dda_target_create(lib.h, self.K, self.J, self.P, self.kd, ctypes.byref(h)))
+        self.h = h
+        self.nd = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().dda_target_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dev(self):
+        return torch.device("cuda", self.lib.device)
+
+    def set_occupancy(self, occ) -> int:
+        occ = np.ascontiguousarray(np.asarray(occ, dtype=np.uint8).reshape(-1))
+        if occ.size != self.K * self.J * self.P:
+            raise ValueError("occupancy size")
+        nd = ctypes.c_int64()
+        _check(load().dda_set_occupancy(self.h, _np_ptr(occ), ctypes.byref(nd)))
+        self.nd = int(nd.value)
+        return self.nd
+
+    def set_permittivity(self, eps, prescription: str = "ldr"):
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.complex128), (self.nd,)))
+        _check(load().dda_set_permittivity(self.h, _np_ptr(e), _PRESC[prescription]))
+
+    def set_polarizability(self, alpha):
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, np.complex128), (self.nd,)))
+        _check(load().dda_set_polarizability(self.h, _np_ptr(a)))
+
+    def build_spectrum(self):
+        _check(load().dda_build_spectrum(self.h, _stream()))
+
+    def info(self) -> dict:
+        dims = np.zeros(9, np.int64)
+        _check(load().dda_target_info(self.h, _np_ptr(dims)))
+        keys = ["Kpp", "Jpp", "Ppp", "Kh", "Jh", "Ph", "nd", "lines_matvec", "lines_spectrum"]
+        return {k: int(v) for k, v in zip(keys, dims)}
+
+    def spectrum(self, precision: int = DDA_FP64) -> torch.Tensor:
+        i = self.info()
+        dt = torch.complex128 if precision == DDA_FP64 else torch.complex64
+        out = torch.empty((6, i["Ph"], i["Jh"], i["Kh"]), dtype=dt, device=self.dev)
+        _check(load().dda_get_spectrum(self.h, precision, _dptr(out), _stream()))
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def matvec(self, x: torch.Tensor, S=None, jacobi: bool = False, out: torch.Tensor | None = None):
+        if x.dim() != 3 or x.shape[1] != 3 or x.shape[2] != self.nd:
+            raise ValueError("x must be [nrhs, 3, N_d]")
+        prec = {torch.complex128: DDA_FP64, torch.complex64: DDA_FP32}[x.dtype]
+        nrhs = x.shape[0]
+        y = torch.empty_like(x) if out is None else out
+        Sa, Sp = _opt_np(S, np.float64, nrhs)
+        _check(load().dda_matvec(self.h, prec, nrhs, Sp, int(bool(jacobi)), _dptr(x), _dptr(y), _stream()))
+        return y
+
+    def incident_field(self, khat, ehat) -> torch.Tensor:
+        kh = np.ascontiguousarray(np.asarray(khat, np.float64).reshape(-1, 3))
+        eh = np.ascontiguousarray(np.asarray(ehat, np.complex128).reshape(-1, 3))
+        nrhs = kh.shape[0]
+        E = torch.empty((nrhs, 3, self.nd), dtype=torch.complex128, device=self.dev)
+        _check(load().dda_incident_field(self.h, nrhs, _np_ptr(kh), _np_ptr(eh), _dptr(E), _stream()))
+        return E
+
+    @staticmethod
+    def make_opts(solver="qmr", precision="fp64", tol=1e-6, inner_tol=0.0, max_iter=0, max_outer=0,
+                  jacobi=True, check_every=0, use_graph=False) -> dda_solve_opts:
+        return dda_solve_opts(_SOLVER[solver], _SPREC[precision], int(max_iter), int(max_outer), float(tol),
+                              float(inner_tol), int(bool(jacobi)), int(check_every), int(bool(use_graph)))
+
+    def solve(self, khat=None, ehat=None, S=None, einc: torch.Tensor | None = None, raise_on_fail=True, **kw):
+        """Solve A P = E_inc.  Returns (P [nrhs,3,N_d] complex128, list of info dicts)."""
+        opts = self.make_opts(**kw)
+        kh = eh = None
+        khp = ehp = None
+        if khat is not None:
+            kh = np.ascontiguousarray(np.asarray(khat, np.float64).reshape(-1, 3))
+            eh = np.ascontiguousarray(np.asarray(ehat, np.complex128).reshape(-1, 3))
+            khp, ehp = _np_ptr(kh), _np_ptr(eh)
+            nrhs = kh.shape[0]
+        else:
+            nrhs = einc.shape[0]
+        Sa, Sp = _opt_np(S, np.float64, nrhs)
+        P = torch.empty((nrhs, 3, self.nd), dtype=torch.complex128, device=self.dev)
+        info = (dda_solve_info * nrhs)()
+        ep = _dptr(einc) if einc is not None else None
+        rc = load().dda_solve(self.h, ctypes.byref(opts), nrhs, khp, ehp, Sp, ep, _dptr(P), info, _stream())
+        infos = [dict(converged=i.converged, iterations=i.iterations, outer_iterations=i.outer_iterations,
+                      matvecs=i.matvecs, rel_residual=i.rel_residual) for i in info]
+        if rc != DDA_ENOTCONV or raise_on_fail:
+            _check(rc)
+        return P, infos
+
+    def cross_sections(self, einc: torch.Tensor, P: torch.Tensor, S=None):
+        nrhs = P.shape[0]
+        Sa, Sp = _opt_np(S, np.float64, nrhs)
+        ce = np.zeros(nrhs)
+        ca = np.zeros(nrhs)
+        cs = np.zeros(nrhs)
+        _check(load().dda_cross_sections(self.h, nrhs, Sp, _dptr(einc), _dptr(P), _np_ptr(ce), _np_ptr(ca),
+                                         _np_ptr(cs), _stream()))
+        return ce, ca, cs
+
+    def grad_cabs_eps(self, P: torch.Tensor, S=None, **kw) -> torch.Tensor:
+        opts = self.make_opts(**kw)
+        nrhs = P.shape[0]
+        Sa, Sp = _opt_np(S, np.float64, nrhs)
+        g = torch.empty((nrhs, self.nd), dtype=torch.complex128, device=self.dev)
+        _check(load().dda_grad_cabs_eps(self.h, ctypes.byref(opts), nrhs, Sp, _dptr(P), _dptr(g), _stream()))
+        return g

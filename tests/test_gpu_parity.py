@@ -1,0 +1,195 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: FP64 matrix-vector product within 1e-12 relative (2-norm) of the dense
+O(N_d^2) oracle; FP64 solves within 1e-10 of the oracle's LU solution;
+FP32-vector paths within the bound derived in the design doc from FP32 rounding of
+the FFT passes (2e-6 relative in the 2-norm at these sizes).
+"""
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_0908_0863_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0908_0863_amd import dda
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return dda.Library(0)
+
+
+def _target(lib, occ, kd, eps, presc="ldr"):
+    from paper_0908_0863_amd import dda
+    P, J, K = occ.shape
+    t = dda.Target(lib, K, J, P, kd)
+    nd = t.set_occupancy(occ)
+    t.set_permittivity(np.full(nd, eps) if np.isscalar(eps) else eps, presc)
+    t.build_spectrum()
+    return t, nd
+
+
+def _rand_occ(shape, seed, frac=0.7):
+    rng = np.random.default_rng(seed)
+    occ = (rng.random(shape) < frac).astype(np.uint8)
+    occ.flat[0] = 1
+    return occ
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+SHAPES = [  # (K, J, P): single dipole, radix-3/5 paddings, ragged tiles, thin lattices
+    (1, 1, 1), (2, 1, 1), (1, 3, 1), (3, 4, 2), (5, 3, 7), (7, 5, 9), (4, 9, 3), (12, 5, 6), (33, 2, 3),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_spectrum_matches_circulant_dft(lib, shape):
+    K, J, P = shape
+    occ = _rand_occ((P, J, K), 1)
+    kd = 0.37
+    t, nd = _target(lib, occ, kd, 2.1 + 0.2j)
+    i = t.info()
+    Yg = t.spectrum().cpu().numpy()
+    Yo = ora.circulant_spectrum(K, J, P, i["Kpp"], i["Jpp"], i["Ppp"], kd)
+    assert Yg.shape == Yo.shape
+    assert np.abs(Yg - Yo).max() <= 1e-13 * np.abs(Yo).max() + 1e-15
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_matvec_fp64_matches_dense(lib, shape, jacobi):
+    K, J, P = shape
+    occ = _rand_occ((P, J, K), 2)
+    kd = 0.5
+    eps = 2.4 + 0.3j
+    t, nd = _target(lib, occ, kd, eps)
+    sites = ora.sites_of(occ)
+    S = [0.0, 0.35]
+    x = inputs.complex_gaussian(3, (2, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", S[r])
+        if jacobi:
+            s = 1.0 / np.sqrt(ainv)
+            yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
+        else:
+            yo = ora.dense_matvec(sites, kd, ainv, x[r])
+        assert _rel(y[r], yo) < 1e-12, (shape, r)
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 2), (7, 5, 9), (16, 16, 16)])
+def test_matvec_fp32_matches_dense(lib, shape):
+    K, J, P = shape
+    occ = _rand_occ((P, J, K), 4) if shape != (16, 16, 16) else inputs.sphere(16)
+    kd = 0.45
+    eps = 1.77 + 0.03j
+    t, nd = _target(lib, occ, kd, eps)
+    sites = ora.sites_of(occ)
+    x = inputs.complex_gaussian(5, (1, 3, nd))
+    y = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda()).cpu().numpy()
+    ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr")
+    yo = ora.dense_matvec(sites, kd, ainv, x[0].astype(np.complex64).astype(np.complex128))
+    assert _rel(y[0], yo) < 2e-6
+
+
+def test_matvec_sphere16_fp64(lib):
+    w = inputs.workload("sphere16")
+    eps = w["m"] ** 2
+    t, nd = _target(lib, w["occ"], w["kd"], eps)
+    assert nd == 2176
+    sites = ora.sites_of(w["occ"])
+    x = inputs.complex_gaussian(0, (1, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    yo = ora.dense_matvec(sites, w["kd"], ora.alpha_inv(np.full(nd, eps), w["kd"], "ldr"), x[0])
+    assert _rel(y[0], yo) < 1e-12
+
+
+def test_symmetry_of_gpu_matvec(lib):
+    occ = _rand_occ((6, 5, 7), 6)
+    t, nd = _target(lib, occ, 0.6, 2.0 + 0.5j)
+    x = torch.from_numpy(inputs.complex_gaussian(7, (1, 3, nd))).cuda()
+    z = torch.from_numpy(inputs.complex_gaussian(8, (1, 3, nd))).cuda()
+    Ax, Az = t.matvec(x), t.matvec(z)
+    a = torch.sum(z * Ax).item()
+    b = torch.sum(x * Az).item()
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "qmr"])
+def test_solve_fp64_sphere16_matches_lu(lib, solver):
+    w = inputs.workload("sphere16")
+    eps = w["m"] ** 2
+    t, nd = _target(lib, w["occ"], w["kd"], eps)
+    sites = ora.sites_of(w["occ"])
+    khat = np.array(w["khat"])
+    ehat = np.array(w["ehat"], dtype=np.complex128)
+    P, info = t.solve(khat=khat, ehat=ehat, solver=solver, precision="fp64", tol=1e-12)
+    P = P.cpu().numpy()
+    for r in range(2):
+        assert info[r]["converged"] and info[r]["rel_residual"] <= 1e-12
+        S = ora.ldr_S(khat[r], ehat[r])
+        ainv = ora.alpha_inv(np.full(nd, eps), w["kd"], "ldr", S)
+        E = ora.einc(sites, w["kd"], khat[r], ehat[r])
+        Po = ora.solve_dense(sites, w["kd"], ainv, E)
+        assert _rel(P[r], Po) < 1e-10
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "qmr"])
+def test_solve_mixed_sphere16(lib, solver):
+    w = inputs.workload("sphere16")
+    eps = w["m"] ** 2
+    t, nd = _target(lib, w["occ"], w["kd"], eps)
+    sites = ora.sites_of(w["occ"])
+    P, info = t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]], solver=solver, precision="mixed", tol=1e-10,
+                      inner_tol=1e-4)
+    ainv = ora.alpha_inv(np.full(nd, eps), w["kd"], "ldr", 0.0)
+    E = ora.einc(sites, w["kd"], [0, 0, 1], [1, 0, 0])
+    Po = ora.solve_dense(sites, w["kd"], ainv, E)
+    assert info[0]["converged"] and info[0]["outer_iterations"] >= 2
+    assert _rel(P[0].cpu().numpy(), Po) < 1e-8
+
+
+def test_cross_sections_sphere16(lib):
+    w = inputs.workload("sphere16")
+    eps = w["m"] ** 2
+    kd = w["kd"]
+    t, nd = _target(lib, w["occ"], kd, eps)
+    sites = ora.sites_of(w["occ"])
+    khat, ehat = np.array(w["khat"]), np.array(w["ehat"], np.complex128)
+    E = t.incident_field(khat, ehat)
+    P, info = t.solve(einc=E, S=[0.0, 0.0], solver="qmr", precision="fp64", tol=1e-12)
+    ce, ca, cs = t.cross_sections(E, P, S=[0.0, 0.0])
+    Eo = ora.einc(sites, kd, khat[0], ehat[0])
+    assert _rel(E[0].cpu().numpy(), Eo) < 1e-14
+    ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0)
+    Po = ora.solve_dense(sites, kd, ainv, Eo)
+    assert ce[0] == pytest.approx(ora.c_ext(kd, Eo, Po), rel=1e-10)
+    assert ca[0] == pytest.approx(ora.c_abs(kd, ainv, Po), rel=1e-10)
+    assert cs[0] == pytest.approx(ora.c_sca_quadrature(sites, kd, Po), rel=1e-9)
+    # x-y symmetric target: both polarisations along z give the same answer
+    assert ce[1] == pytest.approx(ce[0], rel=1e-10)
+
+
+def test_gradient_matches_dense_adjoint_sphere10(lib):
+    w = inputs.workload("sphere10")
+    kd = w["kd"]
+    occ = w["occ"]
+    sites = ora.sites_of(occ)
+    nd = sites.shape[0]
+    rng = np.random.default_rng(9)
+    eps = w["m"] ** 2 + 0.05 * (rng.random(nd) + 1j * rng.random(nd))
+    t, _ = _target(lib, occ, kd, eps)
+    E = t.incident_field([[0, 0, 1]], [[1, 0, 0]])
+    P, info = t.solve(einc=E, S=[0.0], solver="qmr", precision="fp64", tol=1e-12)
+    g = t.grad_cabs_eps(P, S=[0.0], solver="qmr", precision="fp64", tol=1e-12).cpu().numpy()
+    Eo = ora.einc(sites, kd, [0, 0, 1], [1, 0, 0])
+    go, _ = ora.grad_cabs_adjoint_dense(sites, kd, eps, "ldr", 0.0, Eo)
+    assert _rel(g[0], go) < 1e-9
