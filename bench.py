@@ -1,0 +1,225 @@
+"""Benchmark: DDA solves per second on one MI355X.
+
+Workload (default): the 64^3 filled cube, 262,144 dipoles, m = 1.5 + 0.02i,
+size parameter x = 10, one plane wave along +z polarised along x, LDR
+polarisabilities, FFT grid 128^3.  One step = the whole hot path for this
+target: interaction spectrum (tensor first column + pruned DFTs), the
+QMR_sym solve to a true FP64 residual of 1e-6 in mixed precision (FP32 FFT
+passes and Krylov vectors, FP64 residuals, refinement and inner products),
+and the cross sections.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
+this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DDA solves/sec at 1e-6 residual (mixed vs FP64); matvec HBM GB/s vs peak"
+HBM_PEAK_GBPS = 8000.0
+
+
+def pass_bytes(K, J, P, Kpp, Jpp, Kh, Jh, Ph, nd, b, jacobi):
+    """Algorithmic HBM bytes of one launch of each matrix-vector pass, one
+    right-hand side, b bytes per complex value."""
+    grid_y = 3 * K * Jpp * P      # y-transformed array, complex values
+    grid_xy = 3 * Kpp * Jpp * P   # x- and y-transformed array
+    spec = 6 * Kh * Jh * Ph
+    idx = 4 * K * J * P           # int32 site map
+    diag = nd * b * (1 if jacobi else 1)
+    return {
+        "y_forward": 3 * nd * b + idx + grid_y * b + (diag if jacobi else 0),
+        "x_forward": (grid_y + grid_xy) * b,
+        "z_product": (2 * grid_xy + spec) * b,
+        "x_inverse": (grid_xy + grid_y) * b,
+        "y_inverse": grid_y * b + idx + 3 * nd * b + diag + 3 * nd * b,
+    }
+
+
+def b3_bytes(K, J, P, Jpp, Kh, Jh, Ph, nd, b):
+    """Minimal 3-pass data motion of one matrix-vector product (y pass, fused
+    xz-plane pass, inverse y pass): b [9 N_d + 12 K J'' P + 6 K_h J_h P_h]."""
+    return b * (9 * nd + 12 * K * Jpp * P + 6 * Kh * Jh * Ph)
+
+
+def cpu_baseline(w, nd, matvecs_per_solve, budget_s=12.0):
+    """The CPU oracle (dense O(N_d^2) FP64 matvec, OpenMP over rows) timed on a
+    bounded sample of rows of the same matrix, extrapolated to the matvecs one
+    FP64 solve of this workload needs."""
+    import numpy as np
+
+    import oracle as ora
+    from paper_0908_0863_amd import inputs
+
+    sites = ora.sites_of(w["occ"])
+    eps = w["m"] ** 2
+    ainv = ora.alpha_inv(np.full(nd, eps), w["kd"], "ldr", 0.0)
+    x = inputs.complex_gaussian(0, (3, nd))
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    rows = 16
+    t = 0.0
+    while True:
+        sel = np.linspace(0, nd - 1, rows).astype(np.int64)
+        t0 = time.perf_counter()
+        ora.dense_matvec(sites, w["kd"], ainv, x, rows=sel, nthreads=cores)
+        t = time.perf_counter() - t0
+        if t > budget_s / 4 or rows >= nd:
+            break
+        rows = min(nd, int(rows * max(2.0, min(8.0, (budget_s / 4) / max(t, 1e-3)))))
+    t_matvec = t * nd / rows
+    t_solve = t_matvec * matvecs_per_solve
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"dense FP64 matvec on {rows} of {nd} rows ({t:.1f} s), extrapolated to a full matvec "
+                      f"({t_matvec:.1f} s) x {matvecs_per_solve} matvecs per FP64 QMR_sym solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cube64")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0908_0863_amd import dda, inputs
+
+    torch.cuda.set_device(0)
+    w = inputs.workload(args.workload)
+    K, J, P = w["K"], w["J"], w["P"]
+    lib = dda.Library(0)
+    t = dda.Target(lib, K, J, P, w["kd"])
+    nd = t.set_occupancy(w["occ"])
+    eps = w["m"] ** 2
+    t.set_permittivity(eps, "ldr")
+    khat = np.array(w["khat"][:1])
+    ehat = np.array(w["ehat"][:1], np.complex128)
+    E = t.incident_field(khat, ehat)
+    S = [float(np.real(np.sum((khat[0] * ehat[0]) ** 2)))]
+    info = t.info()
+
+    def step(precision):
+        t.build_spectrum()
+        P_, inf = t.solve(einc=E, S=S, solver="qmr", precision=precision, tol=args.tol,
+                          inner_tol=args.inner_tol, check_every=16)
+        ce, ca, cs = t.cross_sections(E, P_, S=S)
+        return P_, inf, (ce[0], ca[0], cs[0])
+
+    # reference cross sections: FP64 solve to 1e-12
+    t.build_spectrum()
+    Pref, infref = t.solve(einc=E, S=S, solver="qmr", precision="fp64", tol=1e-12)
+    cref = [c[0] for c in t.cross_sections(E, Pref, S=S)]
+    del Pref
+
+    for _ in range(args.warmup):
+        step("mixed")
+    torch.cuda.synchronize()
+    lib.profile(True)
+    lib.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Pm, infm, cm = step("mixed")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = lib.profile_read()
+    lib.profile(False)
+    value = args.steps / el
+
+    # plain FP64 single-RHS GPU path on the same right-hand side
+    fp64 = None
+    if not args.no_fp64:
+        step("fp64")
+        torch.cuda.synchronize()
+        k64 = max(1, args.steps // 2)
+        t1 = time.perf_counter()
+        for _ in range(k64):
+            P64, inf64, c64 = step("fp64")
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t1
+        fp64 = dict(solves_per_s=k64 / e64, iterations=inf64[0]["iterations"], matvecs=inf64[0]["matvecs"],
+                    rel_residual=inf64[0]["rel_residual"],
+                    cross_section_rel_err=[abs(c64[i] - cref[i]) / abs(cref[i]) for i in range(3)])
+
+    # roofline of the dominant kernel (FP32 passes dominate the mixed solve)
+    bpe = pass_bytes(K, J, P, info["Kpp"], info["Jpp"], info["Kh"], info["Jh"], info["Ph"], nd, 8, True)
+    best = None
+    for (name, prec), (ms, n) in prof.items():
+        if n == 0 or prec != "fp32":
+            continue
+        if best is None or ms > best[2]:
+            best = (name, prec, ms, n)
+    name, prec, ms, n = best
+    avg_s = ms / n / 1e3
+    achieved = bpe[name] / avg_s / 1e9
+    passes = {f"{k[0]}_{k[1]}": dict(avg_us=round(v[0] / v[1] * 1e3, 2), launches=v[1],
+                                     gbps=round((pass_bytes(K, J, P, info["Kpp"], info["Jpp"], info["Kh"], info["Jh"],
+                                                            info["Ph"], nd, 8 if k[1] == "fp32" else 16, True)[k[0]])
+                                                / (v[0] / v[1] / 1e3) / 1e9, 1))
+              for k, v in prof.items() if v[1] > 0}
+    # whole FP32 matvec: sum of the five pass averages, against the 3-pass byte model
+    mv_s = sum(prof[(p, "fp32")][0] / prof[(p, "fp32")][1] for p in dda.PASS_NAMES if prof[(p, "fp32")][1]) / 1e3
+    b3 = b3_bytes(K, J, P, info["Jpp"], info["Kh"], info["Jh"], info["Ph"], nd, 8)
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 (FP32 FFT passes and Krylov vectors; FP64 residual, refinement, inner products)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {K}x{J}x{P} lattice, {nd} dipoles, m={w['m']}, "
+                               f"kd={w['kd']:.5f}, FFT grid {info['Kpp']}x{info['Jpp']}x{info['Ppp']}, "
+                               f"QMR_sym to {args.tol:g} true FP64 residual, 1 RHS",
+                   "solver": "qmr_sym", "precision": "mixed", "tol": args.tol, "inner_tol": args.inner_tol,
+                   "nrhs": 1, "nd": nd},
+        "roofline": {"bound": "hbm", "kernel": f"{name} ({prec})", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+                     "bytes_per_launch": bpe[name]},
+        "solve": {"iterations": infm[0]["iterations"], "outer_iterations": infm[0]["outer_iterations"],
+                  "matvecs": infm[0]["matvecs"], "rel_residual": infm[0]["rel_residual"],
+                  "cross_sections": {"cext": cm[0], "cabs": cm[1], "csca": cm[2]},
+                  "cross_section_rel_err_vs_fp64_1e-12": [abs(cm[i] - cref[i]) / abs(cref[i]) for i in range(3)]},
+        "fp64_single_rhs": fp64,
+        "mixed_vs_fp64_speedup": round(value / fp64["solves_per_s"], 3) if fp64 else None,
+        "matvec_fp32": {"us": round(mv_s * 1e6, 2), "B3_bytes": b3, "gbps_B3": round(b3 / mv_s / 1e9, 1)},
+        "passes": passes,
+    }
+    if not args.no_cpu:
+        mv = fp64["matvecs"] if fp64 else infref[0]["matvecs"]
+        res["cpu_baseline"] = cpu_baseline(w, nd, mv)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,16 @@ int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
 /* Copy the spectrum [6][P_h][J_h][K_h] (complex128 or complex64) to out_dev. */
 int dda_get_spectrum(dda_target *t, int precision, void *out_dev, void *hip_stream);
 
+/* Kernel timing for measurement: while enabled, every launch of the five
+ * matrix-vector passes is bracketed by HIP events on its own stream.
+ * dda_profile_read fills ms[10] (summed milliseconds) and count[10]
+ * (launches) for the passes y-forward, x-forward, z (forward, product,
+ * inverse), x-inverse, y-inverse with FP64 vectors (0..4) and FP32 vectors
+ * (5..9); it waits for the recorded events. */
+int dda_profile_enable(dda_lib *lib, int enable);
+int dda_profile_read(dda_lib *lib, double *ms /* 10 */, int64_t *count /* 10 */);
+int dda_profile_reset(dda_lib *lib);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *dda_last_error(void);
 

@@ -117,9 +117,49 @@ static int pow2_floor(long v) {
 // ----------------------------------------------------------------------------
 // handles
 // ----------------------------------------------------------------------------
+// Optional per-pass kernel timing: HIP events recorded on the launch stream
+// around every matrix-vector pass.
+enum { PASS_YFWD = 0, PASS_XFWD, PASS_ZMUL, PASS_XINV, PASS_YINV, PASS_COUNT = 10 };  // +5 for FP32 vectors
+
 struct dda_lib {
   int device = 0;
   std::string tune_path;
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;                 // free events
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (pass, start, stop)
+  double prof_ms[PASS_COUNT] = {0};
+  long prof_n[PASS_COUNT] = {0};
+};
+
+static hipEvent_t take_event(dda_lib* l) {
+  if (!l->ev_pool.empty()) {
+    hipEvent_t e = l->ev_pool.back();
+    l->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PassTimer {
+  dda_lib* l;
+  int pass;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  PassTimer(dda_lib* l_, int p, hipStream_t s) : l(l_), pass(p), st(s) {
+    if (l->prof) {
+      a = take_event(l);
+      b = take_event(l);
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~PassTimer() {
+    if (l->prof && a && b) {
+      (void)hipEventRecord(b, st);
+      l->pending.push_back({pass, {a, b}});
+    }
+  }
 };
 
 template <typename R>
@@ -236,6 +276,44 @@ extern "C" {
 
 const char* dda_last_error(void) { return g_err.c_str(); }
 
+int dda_profile_enable(dda_lib* lib, int enable) {
+  if (!lib) return fail(DDA_EINVAL, "dda_profile_enable: NULL lib");
+  lib->prof = enable != 0;
+  return DDA_OK;
+}
+
+int dda_profile_read(dda_lib* lib, double* ms, int64_t* count) {
+  if (!lib || !ms || !count) return fail(DDA_EINVAL, "dda_profile_read: NULL argument");
+  HIPCHK(hipSetDevice(lib->device));
+  for (auto& pe : lib->pending) {
+    HIPCHK(hipEventSynchronize(pe.second.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+    lib->prof_ms[pe.first] += t;
+    lib->prof_n[pe.first] += 1;
+    lib->ev_pool.push_back(pe.second.first);
+    lib->ev_pool.push_back(pe.second.second);
+  }
+  lib->pending.clear();
+  for (int p = 0; p < PASS_COUNT; ++p) {
+    ms[p] = lib->prof_ms[p];
+    count[p] = lib->prof_n[p];
+  }
+  return DDA_OK;
+}
+
+int dda_profile_reset(dda_lib* lib) {
+  if (!lib) return fail(DDA_EINVAL, "dda_profile_reset: NULL lib");
+  double ms[PASS_COUNT];
+  int64_t n[PASS_COUNT];
+  CHK(dda_profile_read(lib, ms, n));
+  for (int p = 0; p < PASS_COUNT; ++p) {
+    lib->prof_ms[p] = 0;
+    lib->prof_n[p] = 0;
+  }
+  return DDA_OK;
+}
+
 int dda_open(int hip_device, const char* tune_cache_path, dda_lib** out) {
   if (!out) return fail(DDA_EINVAL, "dda_open: out is NULL");
   *out = nullptr;
@@ -250,7 +328,17 @@ int dda_open(int hip_device, const char* tune_cache_path, dda_lib** out) {
   return DDA_OK;
 }
 
-void dda_close(dda_lib* lib) { delete lib; }
+void dda_close(dda_lib* lib) {
+  if (!lib) return;
+  (void)hipSetDevice(lib->device);
+  for (auto& pe : lib->pending) {
+    (void)hipEventSynchronize(pe.second.second);
+    lib->ev_pool.push_back(pe.second.first);
+    lib->ev_pool.push_back(pe.second.second);
+  }
+  for (hipEvent_t e : lib->ev_pool) (void)hipEventDestroy(e);
+  delete lib;
+}
 
 int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target** out) {
   if (!lib || !out) return fail(DDA_EINVAL, "dda_target_create: NULL argument");
@@ -556,6 +644,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
   {
+    PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? 5 : 0), st);
     const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
     dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
     hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, t->map.as<int>(), a0, a1, dS,
@@ -563,9 +652,13 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     LAUNCHCHK();
   }
   const long rows = (long)nrhs * 3 * P * Jpp;
+  {
+  PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? 5 : 0), st);
   CHK(launch_contig<R>(G1, G2, rows, K, Kpp, K, Kpp, t->fx, b.tw[0].template as<cx<R>>(), false, false, 0, 0,
                        3L * P * Jpp, active, 1.0, st));
+  }
   {
+    PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? 5 : 0), st);
     ZArgs za;
     za.Kpp = Kpp;
     za.Jpp = Jpp;
@@ -581,9 +674,13 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
                        t->fz, b.tw[2].template as<cx<R>>());
     LAUNCHCHK();
   }
+  {
+  PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? 5 : 0), st);
   CHK(launch_contig<R>(G2, G1, rows, Kpp, K, Kpp, K, t->fx, b.tw[0].template as<cx<R>>(), true, false, 0, 0, 3L * P * Jpp,
                        active, 1.0, st));
+  }
   {
+    PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? 5 : 0), st);
     const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
     dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
     hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, t->map.as<int>(), a0, a1, dS,

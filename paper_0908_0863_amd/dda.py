@@ -56,7 +56,10 @@ class dda_solve_info(ctypes.Structure):
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
            "dda_set_permittivity", "dda_set_polarizability", "dda_build_spectrum", "dda_matvec", "dda_solve",
            "dda_incident_field", "dda_cross_sections", "dda_grad_cabs_eps", "dda_target_info",
-           "dda_get_spectrum", "dda_last_error"]
+           "dda_get_spectrum", "dda_profile_enable", "dda_profile_read", "dda_profile_reset",
+           "dda_last_error"]
+
+PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse"]
 
 _lib = None
 
@@ -87,6 +90,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_grad_cabs_eps": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp]),
         "dda_target_info": (i, [vp, vp]),
         "dda_get_spectrum": (i, [vp, i, vp, vp]),
+        "dda_profile_enable": (i, [vp, i]),
+        "dda_profile_read": (i, [vp, vp, vp]),
+        "dda_profile_reset": (i, [vp]),
         "dda_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -146,6 +152,20 @@ class Library:
         if self.h:
             load().dda_close(self.h)
             self.h = None
+
+    def profile(self, enable: bool = True):
+        _check(load().dda_profile_enable(self.h, int(bool(enable))))
+
+    def profile_reset(self):
+        _check(load().dda_profile_reset(self.h))
+
+    def profile_read(self) -> dict:
+        """{(pass name, 'fp64'|'fp32'): (total ms, launches)} over the recorded launches."""
+        ms = np.zeros(10)
+        n = np.zeros(10, np.int64)
+        _check(load().dda_profile_read(self.h, _np_ptr(ms), _np_ptr(n)))
+        keys = [(p, "fp64") for p in PASS_NAMES] + [(p, "fp32") for p in PASS_NAMES]
+        return {k: (float(a), int(b)) for k, a, b in zip(keys, ms, n)}
 
     def __del__(self):
         try:
