@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_solver.hpp"
+#include "fft_fast.hpp"
 
 using namespace dda;
 
@@ -86,10 +87,29 @@ static bool smooth235(int n) {
   return n == 1;
 }
 
-// smallest 2^a 3^b 5^c >= m (m >= 1)
+// lengths with a register-resident kernel (fft_fast.hpp)
+#define DDA_FAST_SIZES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(24) X(48) X(96) X(192) X(384)
+static bool fast_size(int n) {
+  switch (n) {
+#define DDA_CASE(N) case N:
+    DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+// Padded FFT length for a lattice extent: any n'' >= 2n - 1 embeds the
+// Toeplitz matrix in a circulant (Sec. 3).  Take the smallest 2^a 3^b 5^c
+// length, or the smallest length with a register-resident kernel when it is
+// at most 25% longer.
 static int fft_size_at_least(int m) {
   int n = std::max(1, m);
   while (!smooth235(n)) ++n;
+  int f = std::max(1, m);
+  while (!fast_size(f) && f < 4 * n) ++f;
+  if (fast_size(f) && 4 * f <= 5 * n) return f;
   return n;
 }
 
@@ -620,6 +640,60 @@ static int ensure_matvec_ws(dda_target* t, int nrhs) {
   return DDA_OK;
 }
 
+// ---- register-resident passes -------------------------------------------
+template <int N>
+constexpr int fast_tx() {
+  constexpr int T = FastPlan<N>::T;
+  constexpr int tx = 256 / T;
+  return tx < 8 ? 8 : (tx > 64 ? 64 : tx);
+}
+template <typename R, int N>
+constexpr int fast_txz() {
+  int tx = fast_tx<N>();
+  while (tx > 2 && 3 * N * tx * (int)sizeof(cx<R>) > 48 * 1024) tx /= 2;
+  return tx;
+}
+template <int N>
+constexpr int fast_rw() {
+  constexpr int T = FastPlan<N>::T;
+  constexpr int rw = 256 / T;
+  return rw < 1 ? 1 : (rw > 64 ? 64 : rw);
+}
+
+template <typename R>
+struct FastLaunch {
+  template <int N>
+  static void yfwd(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, const int* map, const cx<R>* a0,
+                   const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw) {
+    constexpr int TX = fast_tx<N>();
+    dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
+    hipLaunchKernelGGL((k_fast_yfwd<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0, a1, S, act,
+                       va, tw);
+  }
+  template <int N>
+  static void yinv(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, const int* map,
+                   const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw) {
+    constexpr int TX = fast_tx<N>();
+    dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
+    hipLaunchKernelGGL((k_fast_yinv<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G1, x, y, map, a0, a1, S,
+                       act, va, tw);
+  }
+  template <int N, bool INV>
+  static void xpass(hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride, int lout_stride,
+                    int Lin, int Lout, long rows_per_rhs, const int* act, const cx<R>* tw) {
+    constexpr int RW = fast_rw<N>();
+    dim3 grid((unsigned)((nrows + RW - 1) / RW));
+    hipLaunchKernelGGL((k_fast_x<R, INV, N, RW>), grid, dim3(FastPlan<N>::T * RW), 0, st, in, out, nrows, lin_stride,
+                       lout_stride, Lin, Lout, rows_per_rhs, act, tw);
+  }
+  template <int N>
+  static void zmul(int nrhs, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za, const cx<R>* tw) {
+    constexpr int TX = fast_txz<R, N>();
+    dim3 grid((za.Kpp + TX - 1) / TX, za.Jpp, nrhs);
+    hipLaunchKernelGGL((k_fast_zmul<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G2, Y, act, za, tw);
+  }
+};
+
 // y = A x (jacobi = 0) or D^{-1/2} A D^{-1/2} x (jacobi = 1); S and active are
 // device arrays [nrhs] (nullable).
 template <typename R>
@@ -645,17 +719,42 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.TX = tile_width<R>(K, Jpp, 2);
   {
     PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? 5 : 0), st);
-    const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
-    dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
-    hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, t->map.as<int>(), a0, a1, dS,
-                       active, va, t->fy, b.tw[1].template as<cx<R>>());
+    if (fast_size(Jpp)) {
+      switch (Jpp) {
+#define DDA_CASE(N)                                                                                         \
+  case N:                                                                                                   \
+    FastLaunch<R>::template yfwd<N>(dim3(1, P, nrhs * 3), st, x, G1, t->map.as<int>(), a0, a1, dS, active, va, \
+                                    b.tw[1].template as<cx<R>>());                                            \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+    } else {
+      const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
+      dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
+      hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, t->map.as<int>(), a0, a1, dS,
+                         active, va, t->fy, b.tw[1].template as<cx<R>>());
+    }
     LAUNCHCHK();
   }
   const long rows = (long)nrhs * 3 * P * Jpp;
   {
   PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? 5 : 0), st);
-  CHK(launch_contig<R>(G1, G2, rows, K, Kpp, K, Kpp, t->fx, b.tw[0].template as<cx<R>>(), false, false, 0, 0,
-                       3L * P * Jpp, active, 1.0, st));
+  if (fast_size(Kpp)) {
+    switch (Kpp) {
+#define DDA_CASE(N)                                                                                          \
+  case N:                                                                                                    \
+    FastLaunch<R>::template xpass<N, false>(st, G1, G2, rows, K, Kpp, K, Kpp, 3L * P * Jpp, active,           \
+                                            b.tw[0].template as<cx<R>>());                                   \
+    break;
+      DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+    }
+    LAUNCHCHK();
+  } else {
+    CHK(launch_contig<R>(G1, G2, rows, K, Kpp, K, Kpp, t->fx, b.tw[0].template as<cx<R>>(), false, false, 0, 0,
+                         3L * P * Jpp, active, 1.0, st));
+  }
   }
   {
     PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? 5 : 0), st);
@@ -667,24 +766,61 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     za.Kh = t->Kh;
     za.Jh = t->Jh;
     za.Ph = t->Ph;
-    za.TX = tile_width<R>(Kpp, Ppp, 4);
-    const size_t lds = 4 * (size_t)Ppp * za.TX * sizeof(cx<R>);
-    dim3 grid((Kpp + za.TX - 1) / za.TX, Jpp, nrhs);
-    hipLaunchKernelGGL((k_vec_zmul<R>), grid, dim3(kThreads), lds, st, G2, b.Y.template as<cx<R>>(), active, za,
-                       t->fz, b.tw[2].template as<cx<R>>());
+    if (fast_size(Ppp)) {
+      switch (Ppp) {
+#define DDA_CASE(N)                                                                                      \
+  case N:                                                                                                \
+    FastLaunch<R>::template zmul<N>(nrhs, st, G2, b.Y.template as<cx<R>>(), active, za,                   \
+                                    b.tw[2].template as<cx<R>>());                                        \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+    } else {
+      za.TX = tile_width<R>(Kpp, Ppp, 4);
+      const size_t lds = 4 * (size_t)Ppp * za.TX * sizeof(cx<R>);
+      dim3 grid((Kpp + za.TX - 1) / za.TX, Jpp, nrhs);
+      hipLaunchKernelGGL((k_vec_zmul<R>), grid, dim3(kThreads), lds, st, G2, b.Y.template as<cx<R>>(), active, za,
+                         t->fz, b.tw[2].template as<cx<R>>());
+    }
     LAUNCHCHK();
   }
   {
   PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? 5 : 0), st);
-  CHK(launch_contig<R>(G2, G1, rows, Kpp, K, Kpp, K, t->fx, b.tw[0].template as<cx<R>>(), true, false, 0, 0, 3L * P * Jpp,
-                       active, 1.0, st));
+  if (fast_size(Kpp)) {
+    switch (Kpp) {
+#define DDA_CASE(N)                                                                                         \
+  case N:                                                                                                   \
+    FastLaunch<R>::template xpass<N, true>(st, G2, G1, rows, Kpp, K, Kpp, K, 3L * P * Jpp, active,           \
+                                           b.tw[0].template as<cx<R>>());                                   \
+    break;
+      DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+    }
+    LAUNCHCHK();
+  } else {
+    CHK(launch_contig<R>(G2, G1, rows, Kpp, K, Kpp, K, t->fx, b.tw[0].template as<cx<R>>(), true, false, 0, 0,
+                         3L * P * Jpp, active, 1.0, st));
+  }
   }
   {
     PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? 5 : 0), st);
-    const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
-    dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
-    hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, t->map.as<int>(), a0, a1, dS,
-                       active, va, t->fy, b.tw[1].template as<cx<R>>());
+    if (fast_size(Jpp)) {
+      switch (Jpp) {
+#define DDA_CASE(N)                                                                                             \
+  case N:                                                                                                       \
+    FastLaunch<R>::template yinv<N>(dim3(1, P, nrhs * 3), st, G1, x, y, t->map.as<int>(), a0, a1, dS, active, va, \
+                                    b.tw[1].template as<cx<R>>());                                                \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+    } else {
+      const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
+      dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
+      hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, t->map.as<int>(), a0, a1, dS,
+                         active, va, t->fy, b.tw[1].template as<cx<R>>());
+    }
     LAUNCHCHK();
   }
   t->matvecs += 1;

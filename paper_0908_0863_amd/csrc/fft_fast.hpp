@@ -1,0 +1,383 @@
+// Register-resident Stockham FFTs with compile-time length, and the
+// matrix-vector passes built on them.
+//
+// A line of length N is held by T = N/E threads, E complex values each:
+// thread t holds positions t + T*m, m = 0..E-1.  In every Stockham stage of
+// radix r the butterflies a thread owns read exactly its own positions
+// (q + j N/r = t + T (u + j E/r) for q = t + T u), so data only moves through
+// LDS between stages (one write, one barrier, one read of the own positions);
+// the first stage reads global memory directly and the last one leaves the
+// result in the same positions, ready for a coalesced global store.  Lines
+// that are only partly non-zero (the padded vector lines of Sec. 3) are loaded
+// with zeros and stored up to their useful length.
+//
+// Lengths: 2^k with E = 8 (radix-8 stages, then 4 or 2) and 3*2^k with
+// E = 12 (radix-4 stages, then 2, then 3).  Other 5-smooth lengths use the
+// generic LDS kernels of kernels_fft.hpp.
+#pragma once
+#include "fft_core.hpp"
+#include "kernels_fft.hpp"
+
+namespace dda {
+
+template <int N>
+struct FastPlan {
+  static constexpr bool pow2 = N >= 16 && (N & (N - 1)) == 0;
+  static constexpr bool three = N >= 24 && N % 3 == 0 && ((N / 3) & (N / 3 - 1)) == 0;
+  static constexpr bool ok = pow2 || three;
+  static constexpr int E = pow2 ? 8 : 12;
+  static constexpr int T = N / E;
+  static constexpr int nst_calc() {
+    int n = N, s = 0;
+    if (pow2) {
+      while (n >= 8) { n /= 8; ++s; }
+      if (n > 1) ++s;
+    } else {
+      n /= 3;
+      while (n >= 4) { n /= 4; ++s; }
+      if (n > 1) ++s;
+      ++s;
+    }
+    return s;
+  }
+  static constexpr int S = nst_calc();
+  static constexpr int radix(int s) {
+    int n = N, i = 0;
+    if (pow2) {
+      while (n >= 8) {
+        if (i == s) return 8;
+        n /= 8;
+        ++i;
+      }
+      return n;
+    }
+    n /= 3;
+    while (n >= 4) {
+      if (i == s) return 4;
+      n /= 4;
+      ++i;
+    }
+    if (n > 1) {
+      if (i == s) return n;
+      ++i;
+    }
+    return 3;
+  }
+  static constexpr int pbefore(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i);
+    return p;
+  }
+};
+
+// One stage of radix RR at Stockham offset P (product of previous radices).
+// lds(e) addresses element e of this thread's line.
+template <int PS>
+__device__ __forceinline__ int padpos(int e) {
+  if constexpr (PS > 0) return e + (e >> PS);
+  else return e;
+}
+
+template <typename R, bool INV, int N, int E, int RR, int P, bool LAST, int PS>
+__device__ __forceinline__ void fast_stage(cx<R> (&v)[E], int t, cx<R>* __restrict__ lds, int es, int off,
+                                           const cx<R>* __restrict__ tw) {
+  constexpr int T = N / E, B = E / RR, TWS = N / (P * RR);
+  static_assert(E % RR == 0, "radix must divide the per-thread count");
+  cx<R> nv[E];
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int q = t + T * u;
+    const int k = q % P;
+    cx<R> a[RR];
+#pragma unroll
+    for (int j = 0; j < RR; ++j) a[j] = v[u + j * B];
+    if constexpr (P > 1) {
+#pragma unroll
+      for (int j = 1; j < RR; ++j) {
+        cx<R> w = tw[j * k * TWS];
+        if (INV) w.y = -w.y;
+        a[j] = a[j] * w;
+      }
+    }
+    dft_small<RR, R, INV>(a);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int j = 0; j < RR; ++j) nv[u + j * B] = a[j];
+    } else {
+      const int base = (q - k) * RR + k;
+#pragma unroll
+      for (int j = 0; j < RR; ++j) lds[padpos<PS>(base + j * P) * es + off] = a[j];
+    }
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = nv[m];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = lds[padpos<PS>(t + T * m) * es + off];
+    __syncthreads();
+  }
+}
+
+template <typename R, bool INV, int N, int S, int PS>
+struct FastStages {
+  template <int s>
+  __device__ __forceinline__ static void run(cx<R> (&v)[FastPlan<N>::E], int t, cx<R>* lds, int es, int off,
+                                             const cx<R>* tw) {
+    if constexpr (s < S) {
+      constexpr int RR = FastPlan<N>::radix(s);
+      constexpr int P = FastPlan<N>::pbefore(s);
+      fast_stage<R, INV, N, FastPlan<N>::E, RR, P, s == S - 1, PS>(v, t, lds, es, off, tw);
+      run<s + 1>(v, t, lds, es, off, tw);
+    }
+  }
+};
+
+// In: v[m] = x[t + T m].  Out: v[m] = X[t + T m].  Every thread of the block
+// must call it (it contains barriers).  PS > 0 inserts one padding slot every
+// 2^PS elements of a line in LDS (spreads the strided Stockham writes over
+// the LDS banks).
+template <typename R, bool INV, int N, int PS = 0>
+__device__ __forceinline__ void fast_fft(cx<R> (&v)[FastPlan<N>::E], int t, cx<R>* lds, int es, int off,
+                                         const cx<R>* tw) {
+  FastStages<R, INV, N, FastPlan<N>::S, PS>::template run<0>(v, t, lds, es, off, tw);
+}
+
+// Three interleaved transforms (the three vector components) sharing the
+// barriers: lds holds three [N][es] planes at offsets 0, cs, 2 cs.
+template <typename R, bool INV, int N, int E, int RR, int P, bool LAST>
+__device__ __forceinline__ void fast_stage3(cx<R> (&v)[3][E], int t, cx<R>* __restrict__ lds, int es, int off,
+                                            int cs, const cx<R>* __restrict__ tw) {
+  constexpr int T = N / E, B = E / RR, TWS = N / (P * RR);
+  cx<R> nv[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int q = t + T * u;
+      const int k = q % P;
+      cx<R> a[RR];
+#pragma unroll
+      for (int j = 0; j < RR; ++j) a[j] = v[c][u + j * B];
+      if constexpr (P > 1) {
+#pragma unroll
+        for (int j = 1; j < RR; ++j) {
+          cx<R> w = tw[j * k * TWS];
+          if (INV) w.y = -w.y;
+          a[j] = a[j] * w;
+        }
+      }
+      dft_small<RR, R, INV>(a);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int j = 0; j < RR; ++j) nv[c][u + j * B] = a[j];
+      } else {
+        const int base = (q - k) * RR + k;
+#pragma unroll
+        for (int j = 0; j < RR; ++j) lds[c * cs + (base + j * P) * es + off] = a[j];
+      }
+    }
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = nv[c][m];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = lds[c * cs + (t + T * m) * es + off];
+    __syncthreads();
+  }
+}
+
+template <typename R, bool INV, int N, int S>
+struct FastStages3 {
+  template <int s>
+  __device__ __forceinline__ static void run(cx<R> (&v)[3][FastPlan<N>::E], int t, cx<R>* lds, int es, int off,
+                                             int cs, const cx<R>* tw) {
+    if constexpr (s < S) {
+      constexpr int RR = FastPlan<N>::radix(s);
+      constexpr int P = FastPlan<N>::pbefore(s);
+      fast_stage3<R, INV, N, FastPlan<N>::E, RR, P, s == S - 1>(v, t, lds, es, off, cs, tw);
+      run<s + 1>(v, t, lds, es, off, cs, tw);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// y forward with expansion (Sec. 3 and 4): grid (ceil(K/TX), P, nrhs*3),
+// block T*TX threads; lane = t*TX + l (l fastest: coalesced rows).
+// ---------------------------------------------------------------------------
+template <typename R, int N, int TX>
+__global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
+    const cx<R>* __restrict__ x, cx<R>* __restrict__ G1, const int* __restrict__ map, const cx<R>* __restrict__ a0,
+    const cx<R>* __restrict__ a1, const double* __restrict__ S, const int* __restrict__ active, VecArgs a,
+    const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
+  __shared__ cx<R> lds[N * TX];
+  const int rc = blockIdx.z, rhs = rc / 3;
+  if (active && !active[rhs]) return;
+  const int l = threadIdx.x % TX, t = threadIdx.x / TX;
+  const int i = blockIdx.x * TX + l, k = blockIdx.y;
+  const R Sr = S ? (R)S[rhs] : (R)0;
+  const cx<R>* xv = x + (long)rc * a.nd;
+  cx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    cx<R> val = mk((R)0, (R)0);
+    if (e < a.J && i < a.K) {
+      const int n = map[((long)k * a.J + e) * a.K + i];
+      if (n >= 0) {
+        val = xv[n];
+        if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, n)) * val;
+      }
+    }
+    v[m] = val;
+  }
+  fast_fft<R, false, N>(v, t, lds, TX, l, tw);
+  if (i < a.K) {
+    cx<R>* dst = G1 + ((long)rc * a.P + k) * N * a.K + i;
+#pragma unroll
+    for (int m = 0; m < E; ++m) dst[(long)(t + T * m) * a.K] = v[m];
+  }
+}
+
+// y inverse, normalisation, compression and diagonal (Sec. 3, 4; step 5 of the
+// standard algorithm).
+template <typename R, int N, int TX>
+__global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
+    const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, const int* __restrict__ map,
+    const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1, const double* __restrict__ S,
+    const int* __restrict__ active, VecArgs a, const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
+  __shared__ cx<R> lds[N * TX];
+  const int rc = blockIdx.z, rhs = rc / 3;
+  if (active && !active[rhs]) return;
+  const int l = threadIdx.x % TX, t = threadIdx.x / TX;
+  const int i = blockIdx.x * TX + l, k = blockIdx.y;
+  const cx<R>* src = G1 + ((long)rc * a.P + k) * N * a.K + i;
+  cx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = (i < a.K) ? src[(long)(t + T * m) * a.K] : mk((R)0, (R)0);
+  fast_fft<R, true, N>(v, t, lds, TX, l, tw);
+  if (i >= a.K) return;
+  const R Sr = S ? (R)S[rhs] : (R)0;
+  const R sc = (R)a.scale;
+  const cx<R>* xv = x + (long)rc * a.nd;
+  cx<R>* yv = y + (long)rc * a.nd;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    if (e >= a.J) continue;
+    const int n = map[((long)k * a.J + e) * a.K + i];
+    if (n < 0) continue;
+    const cx<R> conv = sc * v[m];
+    const cx<R> dg = diag_of(a0, a1, Sr, n);
+    if (a.jacobi) yv[n] = xv[n] + jacobi_scale(dg) * conv;
+    else yv[n] = dg * xv[n] + conv;
+  }
+}
+
+// x direction on rows: RW rows per block, lane = row*T + t (t fastest).
+// Forward: rows of length Lin (K) -> N; inverse: N -> Lout (K).
+template <typename R, bool INV, int N, int RW>
+__global__ void __launch_bounds__(FastPlan<N>::T * RW) k_fast_x(const cx<R>* __restrict__ in, cx<R>* __restrict__ out,
+                                                                 long nrows, int lin_stride, int lout_stride, int Lin,
+                                                                 int Lout, long rows_per_rhs,
+                                                                 const int* __restrict__ active,
+                                                                 const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
+  constexpr int ES = 1, LS = N + N / 8 + 1;  // padded row stride in LDS
+  __shared__ cx<R> lds[RW * LS];
+  const int t = threadIdx.x % T, rw = threadIdx.x / T;
+  const long row = (long)blockIdx.x * RW + rw;
+  const bool valid = row < nrows && (!active || active[row / rows_per_rhs]);
+  const cx<R>* src = in + row * lin_stride;
+  cx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    v[m] = (valid && e < Lin) ? src[e] : mk((R)0, (R)0);
+  }
+  fast_fft<R, INV, N, 3>(v, t, lds, ES, rw * LS, tw);
+  if (!valid) return;
+  cx<R>* dst = out + row * lout_stride;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    if (e < Lout) dst[e] = v[m];
+  }
+}
+
+// z direction with the spectral product (Eqs. Q0-Q2, mirrored octant access
+// with Table 1 signs), in place on G2: grid (ceil(K''/TX), J'', nrhs).
+template <typename R, int N, int TX>
+__global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y,
+                                                                    const int* __restrict__ active, ZArgs a,
+                                                                    const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
+  __shared__ cx<R> lds[3 * N * TX];
+  const int rhs = blockIdx.z;
+  if (active && !active[rhs]) return;
+  const int l = threadIdx.x % TX, t = threadIdx.x / TX;
+  const int i = blockIdx.x * TX + l, jj = blockIdx.y;
+  const long plane = (long)a.Jpp * a.Kpp;
+  const bool ok = i < a.Kpp;
+  cx<R> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<R>* src = G2 + ((long)(rhs * 3 + c) * a.P) * plane + (long)jj * a.Kpp + i;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      v[c][m] = (ok && e < a.P) ? src[e * plane] : mk((R)0, (R)0);
+    }
+  }
+  FastStages3<R, false, N, FastPlan<N>::S>::template run<0>(v, t, lds, TX, l, N * TX, tw);
+  if (ok) {
+    const int jm = min(jj, a.Jpp - jj);
+    const bool my = jj > a.Jpp - jj;
+    const int im = min(i, a.Kpp - i);
+    const bool mx = i > a.Kpp - i;
+    int sxy[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sxy[c] = (mx ? c_sign[0][c] : 1) * (my ? c_sign[1][c] : 1);
+    const long cs = (long)a.Ph * a.Jh * a.Kh;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      const int km = min(e, N - e);
+      const bool mz = e > N - e;
+      const cx<R>* ys = Y + ((long)km * a.Jh + jm) * a.Kh + im;
+      cx<R> yv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int sg = sxy[c] * (mz ? c_sign[2][c] : 1);
+        const cx<R> w = ys[c * cs];
+        yv[c] = sg < 0 ? mk(-w.x, -w.y) : w;
+      }
+      const cx<R> x0 = v[0][m], x1 = v[1][m], x2 = v[2][m];
+      v[0][m] = yv[0] * x0 + yv[1] * x1 + yv[2] * x2;
+      v[1][m] = yv[1] * x0 + yv[3] * x1 + yv[4] * x2;
+      v[2][m] = yv[2] * x0 + yv[4] * x1 + yv[5] * x2;
+    }
+  }
+  FastStages3<R, true, N, FastPlan<N>::S>::template run<0>(v, t, lds, TX, l, N * TX, tw);
+  if (!ok) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R>* dst = G2 + ((long)(rhs * 3 + c) * a.P) * plane + (long)jj * a.Kpp + i;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      if (e < a.P) dst[e * plane] = v[c][m];
+    }
+  }
+}
+
+}  // namespace dda

@@ -45,8 +45,10 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
-SHAPES = [  # (K, J, P): single dipole, radix-3/5 paddings, ragged tiles, thin lattices
+SHAPES = [  # (K, J, P): single dipole, radix-3/5 paddings, ragged tiles, thin lattices, and lengths
+    # served by the register-resident kernels (16, 24, 32, 48, 96) next to generic ones (9, 40, 45)
     (1, 1, 1), (2, 1, 1), (1, 3, 1), (3, 4, 2), (5, 3, 7), (7, 5, 9), (4, 9, 3), (12, 5, 6), (33, 2, 3),
+    (8, 8, 8), (16, 5, 12), (12, 12, 12), (40, 3, 20), (24, 20, 6), (23, 17, 2),
 ]
 
 
@@ -85,7 +87,7 @@ def test_matvec_fp64_matches_dense(lib, shape, jacobi):
         assert _rel(y[r], yo) < 1e-12, (shape, r)
 
 
-@pytest.mark.parametrize("shape", [(3, 4, 2), (7, 5, 9), (16, 16, 16)])
+@pytest.mark.parametrize("shape", [(3, 4, 2), (7, 5, 9), (16, 16, 16), (12, 12, 12), (40, 3, 20)])
 def test_matvec_fp32_matches_dense(lib, shape):
     K, J, P = shape
     occ = _rand_occ((P, J, K), 4) if shape != (16, 16, 16) else inputs.sphere(16)
