@@ -96,6 +96,10 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-matvec", type=int, default=0,
+                    help="only run this many FP32 matrix-vector products (for rocprofv3 counter runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -108,6 +112,15 @@ def main():
     from paper_0908_0863_amd import dda, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = 1 << 27  # complex64 elements: 1 GiB
+        a = torch.ones(n, dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+        return
     w = inputs.workload(args.workload)
     K, J, P = w["K"], w["J"], w["P"]
     lib = dda.Library(0)
@@ -121,13 +134,28 @@ def main():
     S = [float(np.real(np.sum((khat[0] * ehat[0]) ** 2)))]
     info = t.info()
 
+    if args.profile_matvec:
+        t.build_spectrum()
+        x = torch.from_numpy(inputs.complex_gaussian(0, (1, 3, nd), np.complex64)).cuda()
+        y = torch.empty_like(x)
+        t.matvec(x, S=S, jacobi=True, out=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.profile_matvec):
+            t.matvec(x, S=S, jacobi=True, out=y)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.profile_matvec
+        print(json.dumps({"matvec_fp32_us": el * 1e6, "count": args.profile_matvec}))
+        return
+
     def step(precision):
         t.build_spectrum()
         P_, inf = t.solve(einc=E, S=S, solver="qmr", precision=precision, tol=args.tol,
-                          inner_tol=args.inner_tol, check_every=16)
+                          inner_tol=args.inner_tol, check_every=16, use_graph=not profiling[0])
         ce, ca, cs = t.cross_sections(E, P_, S=S)
         return P_, inf, (ce[0], ca[0], cs[0])
 
+    profiling = [False]
     # reference cross sections: FP64 solve to 1e-12
     t.build_spectrum()
     Pref, infref = t.solve(einc=E, S=S, solver="qmr", precision="fp64", tol=1e-12)
@@ -137,17 +165,26 @@ def main():
     for _ in range(args.warmup):
         step("mixed")
     torch.cuda.synchronize()
-    lib.profile(True)
-    lib.profile_reset()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         Pm, infm, cm = step("mixed")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    value = args.steps / el
+    # the same steps again with every matrix-vector pass bracketed by HIP
+    # events on its stream (eager launches: events are not captured)
+    profiling[0] = True
+    lib.profile(True)
+    lib.profile_reset()
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        step("mixed")
+    torch.cuda.synchronize()
+    el_prof = time.perf_counter() - tp0
     prof = lib.profile_read()
     lib.profile(False)
-    value = args.steps / el
+    profiling[0] = False
 
     # plain FP64 single-RHS GPU path on the same right-hand side
     fp64 = None
@@ -203,6 +240,8 @@ def main():
                    "solver": "qmr_sym", "precision": "mixed", "tol": args.tol, "inner_tol": args.inner_tol,
                    "nrhs": 1, "nd": nd},
         "roofline": {"bound": "hbm", "kernel": f"{name} ({prec})", "achieved": round(achieved, 1),
+                     "timed": f"HIP events around each launch over {args.steps} profiled steps "
+                              f"({el_prof / args.steps * 1e3:.2f} ms/step)",
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
                      "bytes_per_launch": bpe[name]},

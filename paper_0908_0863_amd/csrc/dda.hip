@@ -215,11 +215,20 @@ struct dda_target {
   DevBuf state;   // solver states
   DevBuf part;    // reduction partials
   DevBuf scal;    // double [cap] scale factors
+  DevBuf tolv;    // double [cap] inner tolerances
   DevBuf outer;   // FP64 outer vectors: E, r, y  (3 x [cap][3][nd])
   DevBuf khat, ehat;
   int scap = 0;
   std::vector<int> h_active;
   int matvecs = 0;
+  // captured inner iteration
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uintptr_t> graph_key;
+  hipStream_t cap_stream = nullptr;
+  ~dda_target() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 template <typename R>
@@ -622,6 +631,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active.ensure(cap * sizeof(int)));
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
+  CHK(t->tolv.ensure(cap * sizeof(double)));
   CHK(t->state.ensure(cap * std::max(sizeof(BcgState), sizeof(QmrState))));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
   CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
@@ -888,13 +898,18 @@ static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
 }
 
 // Solve (jacobi-scaled) A u = b for the right-hand sides flagged in
-// t->active; b and u are slots 0 and 1 of the solver vectors.
+// t->active; b and u are slots 0 and 1 of the solver vectors.  The
+// iteration is enqueued as a fixed kernel sequence; with use_graph a chunk of
+// `check` iterations is captured once into a HIP graph (on a private stream)
+// and replayed on the caller's stream, the host reading the `active` flags
+// only between chunks.
 template <typename R>
-static int inner_solve(dda_target* t, int solver, int nrhs, double tol, int max_iter, int jacobi, int check_every,
-                       hipStream_t st, InnerResult& res) {
+static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, int max_iter, int jacobi,
+                       int check_every, int use_graph, hipStream_t st, InnerResult& res) {
   PrecBufs<R>& B = bufs<R>(t);
   const long n3 = 3 * t->nd;
   const size_t vsz = (size_t)nrhs * n3;
+  CHK(ensure_matvec_ws<R>(t, nrhs));
   cx<R>* V = B.vec.template as<cx<R>>();
   auto slot = [&](int k) { return V + k * vsz; };
   cx<R>* b = slot(0);
@@ -907,72 +922,136 @@ static int inner_solve(dda_target* t, int solver, int nrhs, double tol, int max_
   int* act = t->active.as<int>();
   const double* dS = t->S.as<double>();
   dim3 vg(dm.nblk, nrhs), fg(nrhs);
-  const int check = check_every > 0 ? check_every : 8;
+  int check = check_every > 0 ? check_every : 8;
+  if (check % 2) ++check;  // the QMR vector ring has period 2
   int n_active = 0;
-  if (solver == DDA_BICGSTAB) {
+  const bool bcg = solver == DDA_BICGSTAB;
+  const int mv_per_iter = bcg ? 2 : 1;
+
+  // ---- initialisation (eager)
+  if (bcg) {
     BcgState* stt = t->state.as<BcgState>();
-    cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
-    hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(256), 0, st, b, r, rhat, p, v, u, act, dm, part);
-    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tol);
-    LAUNCHCHK();
-    for (int it = 0; it < max_iter; ++it) {
-      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, st, r, p, v, stt, act, dm);
-      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, st));
-      hipLaunchKernelGGL((k_dots<R, 1>), vg, dim3(256), 0, st, rhat, v, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_alpha, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, st, r, v, stt, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_s, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, st));
-      hipLaunchKernelGGL((k_dots<R, 2>), vg, dim3(256), 0, st, tt, r, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_omega, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, st, u, r, p, tt, rhat, stt, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_iter, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      LAUNCHCHK();
-      if ((it + 1) % check == 0 || it + 1 == max_iter) {
-        CHK(read_active(t, nrhs, st, n_active));
-        if (n_active == 0) break;
-      }
-    }
-    std::vector<BcgState> hs(nrhs);
-    HIPCHK(hipMemcpyAsync(hs.data(), stt, nrhs * sizeof(BcgState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int q = 0; q < nrhs; ++q) {
-      res.iters[q] = hs[q].iters;
-      res.converged[q] = hs[q].converged;
-      res.breakdown[q] = hs[q].breakdown;
-      res.rnorm2[q] = hs[q].rnorm2;
-      res.bnorm2[q] = hs[q].bnorm2;
-    }
+    hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(256), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
+                       part);
+    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tolv);
   } else {
     QmrState* stt = t->state.as<QmrState>();
-    cx<R>*r = slot(2), *va = slot(3), *vb = slot(4), *w = slot(5), *pa = slot(6), *pb = slot(7), *qa = slot(8),
-          *qb = slot(9);
-    // va = v_{n-1} (initially 0), vb = v_n
-    hipLaunchKernelGGL((k_qmr_init_a<R>), vg, dim3(256), 0, st, b, r, u, va, pa, pb, qa, qb, act, dm, part);
-    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tol);
-    hipLaunchKernelGGL((k_qmr_init_b<R>), vg, dim3(256), 0, st, b, vb, stt, act, dm);
-    LAUNCHCHK();
-    cx<R>*vprev = va, *vcur = vb, *p1 = pa, *p2 = pb, *q1 = qa, *q2 = qb;
-    for (int it = 0; it < max_iter; ++it) {
-      CHK(matvec_T<R>(t, nrhs, dS, jacobi, vcur, w, act, st));
-      hipLaunchKernelGGL((k_bil_dot<R>), vg, dim3(256), 0, st, vcur, w, act, dm, part);
-      hipLaunchKernelGGL(k_qmr_fin_alpha, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_qmr_vt<R>), vg, dim3(256), 0, st, w, vcur, vprev, stt, act, dm, part);
-      hipLaunchKernelGGL(k_qmr_fin_givens, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_qmr_update<R>), vg, dim3(256), 0, st, vprev, vcur, w, p1, p2, q1, q2, u, r, stt, act, dm,
+    // slot 3 = v_{n-1} (initially 0), slot 4 = v_n
+    hipLaunchKernelGGL((k_qmr_init_a<R>), vg, dim3(256), 0, st, b, slot(2), u, slot(3), slot(6), slot(7), slot(8),
+                       slot(9), act, dm, part);
+    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tolv);
+    hipLaunchKernelGGL((k_qmr_init_b<R>), vg, dim3(256), 0, st, b, slot(4), stt, act, dm);
+  }
+  LAUNCHCHK();
+
+  // ---- one iteration; `par` selects the roles of the ring buffers
+  auto body = [&](hipStream_t s, int par) -> int {
+    if (bcg) {
+      BcgState* stt = t->state.as<BcgState>();
+      cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
+      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, s, r, p, v, stt, act, dm);
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, s));
+      hipLaunchKernelGGL((k_dots<R, 1>), vg, dim3(256), 0, s, rhat, v, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_alpha, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, s, r, v, stt, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_s, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s));
+      hipLaunchKernelGGL((k_dots<R, 2>), vg, dim3(256), 0, s, tt, r, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_omega, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, s, u, r, p, tt, rhat, stt, act, dm, part);
+      hipLaunchKernelGGL(k_bcg_fin_iter, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+    } else {
+      QmrState* stt = t->state.as<QmrState>();
+      cx<R>* r = slot(2);
+      cx<R>* w = slot(5);
+      cx<R>* vprev = par ? slot(4) : slot(3);
+      cx<R>* vcur = par ? slot(3) : slot(4);
+      cx<R>* p1 = par ? slot(7) : slot(6);
+      cx<R>* p2 = par ? slot(6) : slot(7);
+      cx<R>* q1 = par ? slot(9) : slot(8);
+      cx<R>* q2 = par ? slot(8) : slot(9);
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, vcur, w, act, s));
+      hipLaunchKernelGGL((k_bil_dot<R>), vg, dim3(256), 0, s, vcur, w, act, dm, part);
+      hipLaunchKernelGGL(k_qmr_fin_alpha, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_qmr_vt<R>), vg, dim3(256), 0, s, w, vcur, vprev, stt, act, dm, part);
+      hipLaunchKernelGGL(k_qmr_fin_givens, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      // v_{n+1} lands in vprev's slot, p_n in p2's, q_n in q2's: the roles
+      // swap for the next iteration
+      hipLaunchKernelGGL((k_qmr_update<R>), vg, dim3(256), 0, s, vprev, vcur, w, p1, p2, q1, q2, u, r, stt, act, dm,
                          part);
-      hipLaunchKernelGGL(k_qmr_fin_conv, fg, dim3(256), 0, st, part, dm.nblk, stt, act);
-      LAUNCHCHK();
-      std::swap(vprev, vcur);  // v_{n+1} now in vcur
-      std::swap(p1, p2);       // p_n now in p1
-      std::swap(q1, q2);
-      if ((it + 1) % check == 0 || it + 1 == max_iter) {
-        CHK(read_active(t, nrhs, st, n_active));
-        if (n_active == 0) break;
+      hipLaunchKernelGGL(k_qmr_fin_conv, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+    }
+    LAUNCHCHK();
+    return DDA_OK;
+  };
+
+  int it = 0;
+  bool done = false;
+  if (use_graph && !t->lib->prof) {
+    std::vector<uintptr_t> key = {sizeof(R),
+                                  (uintptr_t)solver,
+                                  (uintptr_t)nrhs,
+                                  (uintptr_t)jacobi,
+                                  (uintptr_t)check,
+                                  (uintptr_t)V,
+                                  (uintptr_t)part,
+                                  (uintptr_t)act,
+                                  (uintptr_t)dS,
+                                  (uintptr_t)t->state.p,
+                                  (uintptr_t)B.G1.p,
+                                  (uintptr_t)B.G2.p,
+                                  (uintptr_t)B.Y.p,
+                                  (uintptr_t)B.a0.p,
+                                  (uintptr_t)B.a1.p};
+    if (!t->graph_exec || t->graph_key != key) {
+      if (t->graph_exec) {
+        (void)hipGraphExecDestroy(t->graph_exec);
+        t->graph_exec = nullptr;
+      }
+      if (!t->cap_stream) HIPCHK(hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking));
+      const int mv_save = t->matvecs;
+      HIPCHK(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeRelaxed));
+      int rc = DDA_OK;
+      for (int g = 0; g < check && rc == DDA_OK; ++g) rc = body(t->cap_stream, g & 1);
+      hipGraph_t graph = nullptr;
+      hipError_t ec = hipStreamEndCapture(t->cap_stream, &graph);
+      t->matvecs = mv_save;
+      if (rc != DDA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return fail(DDA_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+      ec = hipGraphInstantiate(&t->graph_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ec != hipSuccess) {
+        t->graph_exec = nullptr;
+        return fail(DDA_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ec));
+      }
+      t->graph_key = key;
+    }
+    while (it + check <= max_iter) {
+      HIPCHK(hipGraphLaunch(t->graph_exec, st));
+      it += check;
+      t->matvecs += check * mv_per_iter;
+      CHK(read_active(t, nrhs, st, n_active));
+      if (n_active == 0) {
+        done = true;
+        break;
       }
     }
-    std::vector<QmrState> hs(nrhs);
-    HIPCHK(hipMemcpyAsync(hs.data(), stt, nrhs * sizeof(QmrState), hipMemcpyDeviceToHost, st));
+  }
+  for (; !done && it < max_iter; ++it) {
+    CHK(body(st, it & 1));
+    if ((it + 1) % check == 0 || it + 1 == max_iter) {
+      CHK(read_active(t, nrhs, st, n_active));
+      if (n_active == 0) break;
+    }
+  }
+
+  auto collect = [&](auto* hs_dev, auto tag) -> int {
+    using S = decltype(tag);
+    std::vector<S> hs(nrhs);
+    HIPCHK(hipMemcpyAsync(hs.data(), hs_dev, nrhs * sizeof(S), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int q = 0; q < nrhs; ++q) {
       res.iters[q] = hs[q].iters;
@@ -981,8 +1060,10 @@ static int inner_solve(dda_target* t, int solver, int nrhs, double tol, int max_
       res.rnorm2[q] = hs[q].rnorm2;
       res.bnorm2[q] = hs[q].bnorm2;
     }
-  }
-  return DDA_OK;
+    return DDA_OK;
+  };
+  if (bcg) return collect(t->state.as<BcgState>(), BcgState{});
+  return collect(t->state.as<QmrState>(), QmrState{});
 }
 
 // FP64 true residual r = E - A P for all right-hand sides; returns |r|^2 and
@@ -1064,7 +1145,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   ir.rnorm2.resize(nrhs);
   ir.bnorm2.resize(nrhs);
   std::vector<int> hact(nrhs);
-  std::vector<double> hsc(nrhs);
+  std::vector<double> hsc(nrhs), htol(nrhs);
   for (int step = 0; step < max_outer; ++step) {
     int n_left = 0;
     for (int q = 0; q < nrhs; ++q) {
@@ -1072,6 +1153,9 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       hact[q] = !done[q];
       n_left += hact[q];
       hsc[q] = rn2[q] > 0 ? 1.0 / std::sqrt(rn2[q]) : 0.0;
+      // solve only as far as the outer target needs: ||r_new|| <= tol ||E|| / 2
+      const double need = rn2[q] > 0 ? 0.5 * tol * std::sqrt(en2[q] / rn2[q]) : 1.0;
+      htol[q] = std::min(0.5, std::max(tol_in, need));
     }
     if (n_left == 0) break;
     int budget = 0;
@@ -1080,6 +1164,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
     HIPCHK(hipMemcpyAsync(t->active.p, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(t->active_outer.p, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(t->scal.p, hsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(t->tolv.p, htol.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     const unsigned gx = (unsigned)std::min<long>((n3 + 255) / 256, 4096);
     const c64* a0 = t->p64.a0.as<c64>();
     const c64* a1 = t->has_a1 ? t->p64.a1.as<c64>() : nullptr;
@@ -1087,12 +1172,14 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       hipLaunchKernelGGL((k_scale_rhs<float>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p32.vec.as<c32>(), a0, a1,
                          t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
       LAUNCHCHK();
-      CHK(inner_solve<float>(t, o.solver, nrhs, tol_in, budget, o.jacobi ? 1 : 0, o.check_every, st, ir));
+      CHK(inner_solve<float>(t, o.solver, nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
+                             ir));
     } else {
       hipLaunchKernelGGL((k_scale_rhs<double>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p64.vec.as<c64>(), a0, a1,
                          t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
       LAUNCHCHK();
-      CHK(inner_solve<double>(t, o.solver, nrhs, tol_in, budget, o.jacobi ? 1 : 0, o.check_every, st, ir));
+      CHK(inner_solve<double>(t, o.solver, nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
+                              ir));
     }
     // P += |r| D^{-1/2} u
     for (int q = 0; q < nrhs; ++q) hsc[q] = std::sqrt(rn2[q]);

@@ -73,10 +73,15 @@ struct SolverDims {
 // ============================================================================
 // BiCGSTAB (van der Vorst 1992), complex, Hermitian inner products
 // ============================================================================
+// Iterations without a 1% improvement of the best residual after which an
+// inner solve is declared stagnated (FP32 vectors stall near their rounding
+// level); the refinement loop then restarts from the true residual.
+constexpr int kStallWindow = 64;
+
 struct BcgState {
   c64 rho, rho_old, alpha, omega, beta;
-  double bnorm2, rnorm2, tol2;
-  int s_conv, converged, breakdown, iters;
+  double bnorm2, rnorm2, tol2, best2;
+  int s_conv, converged, breakdown, iters, best_it;
 };
 
 // r = b, rhat = b, p = v = u = 0; partials |b|^2
@@ -105,7 +110,7 @@ __global__ void __launch_bounds__(256) k_bcg_init(const cx<R>* __restrict__ b, c
 }
 
 __global__ void k_bcg_fin_init(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
-                               int* __restrict__ active, double tol) {
+                               int* __restrict__ active, const double* __restrict__ tolv) {
   const int rhs = blockIdx.x;
   if (!active[rhs]) return;
   c64 v[1];
@@ -114,7 +119,10 @@ __global__ void k_bcg_fin_init(const c64* __restrict__ part, int nblk, BcgState*
     BcgState s;
     s.bnorm2 = v[0].x;
     s.rnorm2 = v[0].x;
+    const double tol = tolv[rhs];
     s.tol2 = tol * tol * v[0].x;
+    s.best2 = v[0].x;
+    s.best_it = 0;
     s.rho = mk(v[0].x, 0.0);  // rhat = r = b
     s.rho_old = mk(1.0, 0.0);
     s.alpha = mk(1.0, 0.0);
@@ -290,6 +298,14 @@ __global__ void k_bcg_fin_iter(const c64* __restrict__ part, int nblk, BcgState*
       active[rhs] = 0;
       return;
     }
+    if (s.rnorm2 < 0.98 * s.best2) {
+      s.best2 = s.rnorm2;
+      s.best_it = s.iters;
+    } else if (s.iters - s.best_it > kStallWindow) {
+      s.breakdown = 2;  // stagnated
+      active[rhs] = 0;
+      return;
+    }
     if (tiny(s.omega, 1.0) || tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32)) {
       s.breakdown = 1;  // restart from the current iterate (host)
       active[rhs] = 0;
@@ -310,8 +326,8 @@ struct QmrState {
   c64 s1, s2;                          // sines of rotations n-1, n-2
   double c1, c2;                       // cosines of rotations n-1, n-2
   c64 tau, coef, ep, fpp, rnn;         // quasi-residual, step, new column entries
-  double bnorm2, rnorm2, tol2;
-  int converged, breakdown, iters, n;
+  double bnorm2, rnorm2, tol2, best2;
+  int converged, breakdown, iters, n, best_it;
 };
 
 // r = b; u = 0; vprev = 0; v = b/|b|; p, pprev, q, qprev = 0; partials |b|^2, b^T b
@@ -349,7 +365,7 @@ __global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b,
 }
 
 __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
-                               int* __restrict__ active, double tol) {
+                               int* __restrict__ active, const double* __restrict__ tolv) {
   const int rhs = blockIdx.x;
   if (!active[rhs]) return;
   c64 v[2];
@@ -359,7 +375,10 @@ __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState*
     const double nb2 = v[0].x;
     s.bnorm2 = nb2;
     s.rnorm2 = nb2;
+    const double tol = tolv[rhs];
     s.tol2 = tol * tol * nb2;
+    s.best2 = nb2;
+    s.best_it = 0;
     s.rho = sqrt(nb2);
     s.rho_next = 0.0;
     s.delta = nb2 > 0 ? mk(v[1].x / nb2, v[1].y / nb2) : mk(1.0, 0.0);
@@ -550,6 +569,12 @@ __global__ void k_qmr_fin_conv(const c64* __restrict__ part, int nblk, QmrState*
       active[rhs] = 0;
     } else if (!(s.rho > 0.0) || !(abs2(s.delta) > 1e-300)) {
       s.breakdown = 1;
+      active[rhs] = 0;
+    } else if (s.rnorm2 < 0.98 * s.best2) {
+      s.best2 = s.rnorm2;
+      s.best_it = s.iters;
+    } else if (s.iters - s.best_it > kStallWindow) {
+      s.breakdown = 2;  // stagnated
       active[rhs] = 0;
     }
   }

@@ -195,3 +195,21 @@ def test_gradient_matches_dense_adjoint_sphere10(lib):
     Eo = ora.einc(sites, kd, [0, 0, 1], [1, 0, 0])
     go, _ = ora.grad_cabs_adjoint_dense(sites, kd, eps, "ldr", 0.0, Eo)
     assert _rel(g[0], go) < 1e-9
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "qmr"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(lib, solver, precision):
+    """The captured iteration (HIP graph, replayed several times with eager
+    work and host read-backs in between) gives bitwise the eager result."""
+    w = inputs.workload("sphere16")
+    t, nd = _target(lib, w["occ"], w["kd"], w["m"] ** 2)
+    kw = dict(khat=[[0, 0, 1], [0, 0, 1]], ehat=[[1, 0, 0], [0, 1, 0]], solver=solver, precision=precision,
+              tol=1e-9, inner_tol=1e-4, check_every=4)
+    Pe, ie = t.solve(use_graph=False, **kw)
+    for _ in range(3):
+        Pg, ig = t.solve(use_graph=True, **kw)
+        x = torch.from_numpy(inputs.complex_gaussian(1, (1, 3, nd))).cuda()
+        t.matvec(x)  # unrelated eager work between replays
+        assert torch.equal(Pg, Pe)
+        assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
