@@ -632,7 +632,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
-  CHK(t->state.ensure(cap * std::max(sizeof(BcgState), sizeof(QmrState))));
+  CHK(t->state.ensure(2 * cap * std::max(sizeof(BcgState), sizeof(QmrState))));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
   CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
   t->h_active.resize(cap);
@@ -699,8 +699,13 @@ struct FastLaunch {
   template <int N>
   static void zmul(int nrhs, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za, const cx<R>* tw) {
     constexpr int TX = fast_txz<R, N>();
-    dim3 grid((za.Kpp + TX - 1) / TX, za.Jpp, nrhs);
-    hipLaunchKernelGGL((k_fast_zmul<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G2, Y, act, za, tw);
+    ZMap zm;
+    zm.NX = (za.Kpp + TX - 1) / TX;
+    zm.ngx = (zm.NX + 1) / 2;
+    zm.ngy = za.Jpp / 2 + 1;
+    zm.ngroups = nrhs * zm.ngx * zm.ngy;
+    dim3 grid(32 * ((zm.ngroups + 7) / 8));
+    hipLaunchKernelGGL((k_fast_zmul<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G2, Y, act, za, zm, tw);
   }
 };
 
@@ -917,51 +922,52 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   SolverDims dm;
   dm.n3 = n3;
   dm.nblk = nblocks_for(n3);
-  CHK(t->part.ensure((size_t)nrhs * dm.nblk * 2 * sizeof(c64)));
+  // four regions of partial sums (each nrhs x nblk x 2)
+  const size_t preg = (size_t)nrhs * dm.nblk * 2;
+  CHK(t->part.ensure(4 * preg * sizeof(c64)));
   c64* part = t->part.as<c64>();
+  c64 *R0 = part, *R1 = part + preg, *R2 = part + 2 * preg, *R3 = part + 3 * preg;
   int* act = t->active.as<int>();
   const double* dS = t->S.as<double>();
   dim3 vg(dm.nblk, nrhs), fg(nrhs);
   int check = check_every > 0 ? check_every : 8;
-  if (check % 2) ++check;  // the QMR vector ring has period 2
+  if (check % 2) ++check;  // vector rings and state buffers have period 2
   int n_active = 0;
   const bool bcg = solver == DDA_BICGSTAB;
   const int mv_per_iter = bcg ? 2 : 1;
 
-  // ---- initialisation (eager)
+  // ---- initialisation (eager); state buffer 0 receives the initial state
   if (bcg) {
-    BcgState* stt = t->state.as<BcgState>();
+    BcgState* S0 = t->state.as<BcgState>();
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(256), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
-                       part);
-    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tolv);
+                       R3);
+    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, R3, dm.nblk, S0, act, tolv);
   } else {
-    QmrState* stt = t->state.as<QmrState>();
+    QmrState* S0 = t->state.as<QmrState>();
     // slot 3 = v_{n-1} (initially 0), slot 4 = v_n
     hipLaunchKernelGGL((k_qmr_init_a<R>), vg, dim3(256), 0, st, b, slot(2), u, slot(3), slot(6), slot(7), slot(8),
-                       slot(9), act, dm, part);
-    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, part, dm.nblk, stt, act, tolv);
-    hipLaunchKernelGGL((k_qmr_init_b<R>), vg, dim3(256), 0, st, b, slot(4), stt, act, dm);
+                       slot(9), act, dm, R2, R3);
+    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, R2, dm.nblk, S0, act, tolv);
+    hipLaunchKernelGGL((k_qmr_init_b<R>), vg, dim3(256), 0, st, b, slot(4), S0, act, dm);
   }
   LAUNCHCHK();
 
-  // ---- one iteration; `par` selects the roles of the ring buffers
+  // ---- one iteration; `par` selects the roles of the ring and state buffers
   auto body = [&](hipStream_t s, int par) -> int {
     if (bcg) {
-      BcgState* stt = t->state.as<BcgState>();
+      BcgState* SA = t->state.as<BcgState>() + (par ? nrhs : 0);
+      BcgState* SB = t->state.as<BcgState>() + (par ? 0 : nrhs);
       cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
-      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, s, r, p, v, stt, act, dm);
+      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, s, r, p, v, R3, SA, SB, act, dm);
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, s));
-      hipLaunchKernelGGL((k_dots<R, 1>), vg, dim3(256), 0, s, rhat, v, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_alpha, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, s, r, v, stt, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_s, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_dots<R, 1>), vg, dim3(256), 0, s, rhat, v, act, dm, R0);
+      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, s, r, v, R0, SB, SA, act, dm, R1);
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s));
-      hipLaunchKernelGGL((k_dots<R, 2>), vg, dim3(256), 0, s, tt, r, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_omega, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, s, u, r, p, tt, rhat, stt, act, dm, part);
-      hipLaunchKernelGGL(k_bcg_fin_iter, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_dots<R, 2>), vg, dim3(256), 0, s, tt, r, act, dm, R2);
+      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, s, u, r, p, tt, rhat, R1, R2, SA, SB, act, dm, R3);
     } else {
-      QmrState* stt = t->state.as<QmrState>();
+      QmrState* SA = t->state.as<QmrState>();
+      QmrState* SB = SA + nrhs;
       cx<R>* r = slot(2);
       cx<R>* w = slot(5);
       cx<R>* vprev = par ? slot(4) : slot(3);
@@ -971,15 +977,12 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       cx<R>* q1 = par ? slot(9) : slot(8);
       cx<R>* q2 = par ? slot(8) : slot(9);
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, vcur, w, act, s));
-      hipLaunchKernelGGL((k_bil_dot<R>), vg, dim3(256), 0, s, vcur, w, act, dm, part);
-      hipLaunchKernelGGL(k_qmr_fin_alpha, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
-      hipLaunchKernelGGL((k_qmr_vt<R>), vg, dim3(256), 0, s, w, vcur, vprev, stt, act, dm, part);
-      hipLaunchKernelGGL(k_qmr_fin_givens, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_bil_dot<R>), vg, dim3(256), 0, s, vcur, w, act, dm, R0);
+      hipLaunchKernelGGL((k_qmr_vt<R>), vg, dim3(256), 0, s, w, vcur, vprev, R0, R3, SA, SB, act, dm, R1);
       // v_{n+1} lands in vprev's slot, p_n in p2's, q_n in q2's: the roles
       // swap for the next iteration
-      hipLaunchKernelGGL((k_qmr_update<R>), vg, dim3(256), 0, s, vprev, vcur, w, p1, p2, q1, q2, u, r, stt, act, dm,
-                         part);
-      hipLaunchKernelGGL(k_qmr_fin_conv, fg, dim3(256), 0, s, part, dm.nblk, stt, act);
+      hipLaunchKernelGGL((k_qmr_update<R>), vg, dim3(256), 0, s, vprev, vcur, w, p1, p2, q1, q2, u, r, R1, SB, SA,
+                         act, dm, R3);
     }
     LAUNCHCHK();
     return DDA_OK;
@@ -1050,15 +1053,16 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
 
   auto collect = [&](auto* hs_dev, auto tag) -> int {
     using S = decltype(tag);
-    std::vector<S> hs(nrhs);
-    HIPCHK(hipMemcpyAsync(hs.data(), hs_dev, nrhs * sizeof(S), hipMemcpyDeviceToHost, st));
+    std::vector<S> hs(2 * nrhs);
+    HIPCHK(hipMemcpyAsync(hs.data(), hs_dev, 2 * nrhs * sizeof(S), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int q = 0; q < nrhs; ++q) {
-      res.iters[q] = hs[q].iters;
-      res.converged[q] = hs[q].converged;
-      res.breakdown[q] = hs[q].breakdown;
-      res.rnorm2[q] = hs[q].rnorm2;
-      res.bnorm2[q] = hs[q].bnorm2;
+      const S& a = hs[q].ver >= hs[nrhs + q].ver ? hs[q] : hs[nrhs + q];  // the later write
+      res.iters[q] = a.iters < 0 ? 0 : a.iters;
+      res.converged[q] = a.converged;
+      res.breakdown[q] = a.breakdown;
+      res.rnorm2[q] = a.rnorm2;
+      res.bnorm2[q] = a.bnorm2;
     }
     return DDA_OK;
   };

@@ -315,17 +315,44 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RW) k_fast_x(const cx<R>* __r
 }
 
 // z direction with the spectral product (Eqs. Q0-Q2, mirrored octant access
-// with Table 1 signs), in place on G2: grid (ceil(K''/TX), J'', nrhs).
+// with Table 1 signs), in place on G2.
+//
+// The spectrum entry of column (i, j) is shared by the mirror columns
+// (K''-i, j), (i, J''-j) and (K''-i, J''-j).  Blocks are therefore grouped by
+// mirror quadruple {x tile, mirrored x tile} x {j, J''-j}, and the four
+// members of a group get consecutive dispatch slots on the same XCD (blocks
+// are dealt round-robin to the 8 XCDs: block b runs on XCD b mod 8), so the
+// spectrum tile is fetched from HBM once and served to the other three from
+// that XCD's L2.  1D grid of 32 * ceil(groups / 8) blocks.
+struct ZMap {
+  int NX;      // x tiles covering [0, K'')
+  int ngx;     // x tile pairs (t, NX-1-t)
+  int ngy;     // y pairs (j, J''-j), j in [0, J_h)
+  int ngroups; // nrhs * ngx * ngy
+};
+
 template <typename R, int N, int TX>
 __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y,
-                                                                    const int* __restrict__ active, ZArgs a,
+                                                                    const int* __restrict__ active, ZArgs a, ZMap zm,
                                                                     const cx<R>* __restrict__ tw) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
   __shared__ cx<R> lds[3 * N * TX];
-  const int rhs = blockIdx.z;
+  const int b = blockIdx.x;
+  const int group = (b >> 5) * 8 + (b & 7);
+  const int member = (b >> 3) & 3;
+  if (group >= zm.ngroups) return;
+  const int per_rhs = zm.ngx * zm.ngy;
+  const int rhs = group / per_rhs;
+  const int rem = group - rhs * per_rhs;
+  const int gx = rem / zm.ngy, gy = rem - (rem / zm.ngy) * zm.ngy;
+  const int mxm = member & 1, mym = member >> 1;
+  const int xt = mxm ? zm.NX - 1 - gx : gx;
+  if (mxm && xt == gx) return;
+  const int jj = mym ? a.Jpp - gy : gy;
+  if (mym && (gy == 0 || jj == gy)) return;
   if (active && !active[rhs]) return;
   const int l = threadIdx.x % TX, t = threadIdx.x / TX;
-  const int i = blockIdx.x * TX + l, jj = blockIdx.y;
+  const int i = xt * TX + l;
   const long plane = (long)a.Jpp * a.Kpp;
   const bool ok = i < a.Kpp;
   cx<R> v[3][E];

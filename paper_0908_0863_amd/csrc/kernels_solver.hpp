@@ -71,83 +71,33 @@ struct SolverDims {
        i += (long)(dims).nblk * blockDim.x)
 
 // ============================================================================
-// BiCGSTAB (van der Vorst 1992), complex, Hermitian inner products
+// Shared pieces of the fused iteration kernels.
+//
+// Every scalar the next vector update needs is reduced from the partial sums
+// of the previous kernel by each block redundantly (the same fixed-order
+// reduction in every block, so all blocks agree bit for bit); block 0 writes
+// the updated scalars to the *other* state buffer, so no block can observe a
+// half-updated state.  The iteration therefore needs no single-block
+// finalising launches.
 // ============================================================================
-// Iterations without a 1% improvement of the best residual after which an
+
+// Iterations without a 2% improvement of the best residual after which an
 // inner solve is declared stagnated (FP32 vectors stall near their rounding
 // level); the refinement loop then restarts from the true residual.
 constexpr int kStallWindow = 64;
 
-struct BcgState {
-  c64 rho, rho_old, alpha, omega, beta;
-  double bnorm2, rnorm2, tol2, best2;
-  int s_conv, converged, breakdown, iters, best_it;
-};
-
-// r = b, rhat = b, p = v = u = 0; partials |b|^2
-template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
-                                                  cx<R>* __restrict__ rhat, cx<R>* __restrict__ p,
-                                                  cx<R>* __restrict__ v, cx<R>* __restrict__ u,
-                                                  const int* __restrict__ active, SolverDims dm,
-                                                  c64* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  c64 acc[1] = {mk(0.0, 0.0)};
-  if (active[rhs]) {
-    const long o = (long)rhs * dm.n3;
-    DDA_RANGE(dm, i) {
-      const cx<R> bv = b[o + i];
-      r[o + i] = bv;
-      rhat[o + i] = bv;
-      p[o + i] = mk((R)0, (R)0);
-      v[o + i] = mk((R)0, (R)0);
-      u[o + i] = mk((R)0, (R)0);
-      acc[0].x += abs2(up(bv));
-    }
-  }
-  block_sum<1>(acc);
-  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
+// Reduce the partials of right-hand side `rhs` and broadcast to every thread.
+template <int ND>
+__device__ __forceinline__ void reduce_all(const c64* __restrict__ part, int nblk, int rhs, c64 (&v)[ND]) {
+  __shared__ c64 bc[ND];
+  reduce_partials<ND>(part, nblk, rhs, v);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < ND; ++q) bc[q] = v[q];
+  __syncthreads();
+  for (int q = 0; q < ND; ++q) v[q] = bc[q];
 }
 
-__global__ void k_bcg_fin_init(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
-                               int* __restrict__ active, const double* __restrict__ tolv) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[1];
-  reduce_partials<1>(part, nblk, rhs, v);
-  if (threadIdx.x == 0) {
-    BcgState s;
-    s.bnorm2 = v[0].x;
-    s.rnorm2 = v[0].x;
-    const double tol = tolv[rhs];
-    s.tol2 = tol * tol * v[0].x;
-    s.best2 = v[0].x;
-    s.best_it = 0;
-    s.rho = mk(v[0].x, 0.0);  // rhat = r = b
-    s.rho_old = mk(1.0, 0.0);
-    s.alpha = mk(1.0, 0.0);
-    s.omega = mk(1.0, 0.0);
-    s.beta = mk(0.0, 0.0);
-    s.s_conv = 0;
-    s.converged = v[0].x == 0.0;
-    s.breakdown = 0;
-    s.iters = 0;
-    st[rhs] = s;
-    if (s.converged) active[rhs] = 0;
-  }
-}
-
-// p = r + beta (p - omega v)
-template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R>* __restrict__ p,
-                                               const cx<R>* __restrict__ v, const BcgState* __restrict__ st,
-                                               const int* __restrict__ active, SolverDims dm) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  const cx<R> beta = cvt<R>(st[rhs].beta), om = cvt<R>(st[rhs].omega);
-  const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) { p[o + i] = r[o + i] + beta * (p[o + i] - om * v[o + i]); }
-}
+__device__ __forceinline__ bool tiny(c64 a, double scale) { return !(abs2(a) > 1e-300 * scale); }
 
 // partials of a^H b (ND = 1) or of a^H b and a^H a (ND = 2)
 template <typename R, int ND>
@@ -170,83 +120,200 @@ __global__ void __launch_bounds__(256) k_dots(const cx<R>* __restrict__ a, const
     for (int q = 0; q < ND; ++q) part[((long)rhs * dm.nblk + blockIdx.x) * ND + q] = acc[q];
 }
 
-__device__ __forceinline__ bool tiny(c64 a, double scale) { return !(abs2(a) > 1e-300 * scale); }
-
-// alpha = rho / (rhat^H v)
-__global__ void k_bcg_fin_alpha(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
-                                int* __restrict__ active) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[1];
-  reduce_partials<1>(part, nblk, rhs, v);
-  if (threadIdx.x == 0) {
-    BcgState& s = st[rhs];
-    if (tiny(v[0], s.bnorm2 * s.bnorm2) || !isfinite(v[0].x)) {
-      s.breakdown = 1;
-      active[rhs] = 0;
-      return;
-    }
-    s.alpha = cdiv(s.rho, v[0]);
-  }
-}
-
-// s = r - alpha v (stored in r); partials |s|^2
+// partials of v^T w (bilinear)
 template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_s(cx<R>* __restrict__ r, const cx<R>* __restrict__ v,
-                                               const BcgState* __restrict__ st, const int* __restrict__ active,
-                                               SolverDims dm, c64* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_bil_dot(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
+                                                 const int* __restrict__ active, SolverDims dm,
+                                                 c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const cx<R> al = cvt<R>(st[rhs].alpha);
   c64 acc[1] = {mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) {
-    const cx<R> s = r[o + i] - al * v[o + i];
-    r[o + i] = s;
-    acc[0].x += abs2(up(s));
-  }
+  DDA_RANGE(dm, i) { acc[0] = acc[0] + up(a[o + i]) * up(b[o + i]); }
   block_sum<1>(acc);
   if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
 }
 
-__global__ void k_bcg_fin_s(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
-                            const int* __restrict__ active) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[1];
-  reduce_partials<1>(part, nblk, rhs, v);
+// ============================================================================
+// BiCGSTAB (van der Vorst 1992), complex, Hermitian inner products
+//   p = r + beta (p - omega v);  v = A p;  alpha = rho / rhat^H v;  s = r - alpha v;
+//   t = A s;  omega = t^H s / t^H t;  u += alpha p + omega s;  r = s - omega t;
+//   rho' = rhat^H r;  beta = (rho'/rho)(alpha/omega)
+// ============================================================================
+struct BcgState {
+  c64 rho, rho_old, alpha, omega, beta;
+  double bnorm2, rnorm2, tol2, best2;
+  int s_conv, converged, breakdown, iters, best_it;
+  int ver;  // incremented by every kernel that writes the state
+};
+
+// r = b, rhat = b, p = v = u = 0; partials |b|^2 (slot 0) and rhat^H r = |b|^2 (slot 1)
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
+                                                  cx<R>* __restrict__ rhat, cx<R>* __restrict__ p,
+                                                  cx<R>* __restrict__ v, cx<R>* __restrict__ u,
+                                                  const int* __restrict__ active, SolverDims dm,
+                                                  c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[1] = {mk(0.0, 0.0)};
+  if (active[rhs]) {
+    const long o = (long)rhs * dm.n3;
+    DDA_RANGE(dm, i) {
+      const cx<R> bv = b[o + i];
+      r[o + i] = bv;
+      rhat[o + i] = bv;
+      p[o + i] = mk((R)0, (R)0);
+      v[o + i] = mk((R)0, (R)0);
+      u[o + i] = mk((R)0, (R)0);
+      acc[0].x += abs2(up(bv));
+    }
+  }
+  block_sum<1>(acc);
   if (threadIdx.x == 0) {
-    BcgState& s = st[rhs];
-    s.s_conv = v[0].x <= s.tol2;
-    if (s.s_conv) s.rnorm2 = v[0].x;
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[0];
   }
 }
 
-// omega = t^H s / t^H t  (partials: [t^H s, t^H t])
-__global__ void k_bcg_fin_omega(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
-                                const int* __restrict__ active) {
+// initial state (one block per right-hand side)
+__global__ void k_bcg_fin_init(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
+                               int* __restrict__ active, const double* __restrict__ tolv) {
   const int rhs = blockIdx.x;
   if (!active[rhs]) return;
   c64 v[2];
   reduce_partials<2>(part, nblk, rhs, v);
   if (threadIdx.x == 0) {
-    BcgState& s = st[rhs];
-    if (s.s_conv) return;
-    s.omega = (v[1].x > 0.0) ? mk(v[0].x / v[1].x, v[0].y / v[1].x) : mk(0.0, 0.0);
+    BcgState s;
+    s.bnorm2 = v[0].x;
+    s.rnorm2 = v[0].x;
+    const double tol = tolv[rhs];
+    s.tol2 = tol * tol * v[0].x;
+    s.best2 = v[0].x;
+    s.best_it = 0;
+    s.rho = mk(0.0, 0.0);  // the first p kernel moves rho' = |b|^2 into rho
+    s.rho_old = mk(1.0, 0.0);
+    s.alpha = mk(1.0, 0.0);
+    s.omega = mk(1.0, 0.0);
+    s.beta = mk(0.0, 0.0);
+    s.s_conv = 0;
+    s.converged = v[0].x == 0.0;
+    s.breakdown = 0;
+    s.iters = -1;  // the first p kernel counts iteration 0 as not yet done
+    s.ver = 0;
+    st[rhs] = s;
+    if (s.converged) active[rhs] = 0;
   }
 }
 
-// u += alpha p + omega s;  r = s - omega t;  partials |r|^2, rhat^H r
+// Start of an iteration: from the previous update's partials [|r|^2, rhat^H r]
+// decide convergence / stagnation / breakdown, then beta and
+// p = r + beta (p - omega v).
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R>* __restrict__ p,
+                                               const cx<R>* __restrict__ v, const c64* __restrict__ pupd,
+                                               const BcgState* __restrict__ sin, BcgState* __restrict__ sout,
+                                               int* __restrict__ active, SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[2];
+  reduce_all<2>(pupd, dm.nblk, rhs, red);
+  BcgState s = sin[rhs];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  s.iters += 1;
+  int stop = 0;
+  if (s.converged || s.s_conv) {
+    s.converged = 1;
+    stop = 1;
+  } else {
+    s.rnorm2 = red[0].x;
+    s.rho_old = s.rho;
+    s.rho = red[1];
+    if (!isfinite(red[0].x)) {
+      s.breakdown = 1;
+      stop = 1;
+    } else if (s.rnorm2 <= s.tol2) {
+      s.converged = 1;
+      stop = 1;
+    } else if (s.rnorm2 < 0.98 * s.best2) {
+      s.best2 = s.rnorm2;
+      s.best_it = s.iters;
+    } else if (s.iters - s.best_it > kStallWindow) {
+      s.breakdown = 2;  // stagnated
+      stop = 1;
+    }
+    if (!stop && s.iters > 0) {
+      if (tiny(s.omega, 1.0) || tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32)) {
+        s.breakdown = 1;  // restart from the current iterate (refinement loop)
+        stop = 1;
+      } else {
+        s.beta = cdiv(s.rho, s.rho_old) * cdiv(s.alpha, s.omega);
+      }
+    }
+  }
+  if (lead) {
+    { s.ver += 1; sout[rhs] = s; }
+    if (stop) active[rhs] = 0;
+  }
+  if (stop) return;
+  const cx<R> beta = cvt<R>(s.beta), om = cvt<R>(s.omega);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) { p[o + i] = r[o + i] + beta * (p[o + i] - om * v[o + i]); }
+}
+
+// alpha = rho / (rhat^H v);  s = r - alpha v (stored in r); partials |s|^2
+template <typename R>
+__global__ void __launch_bounds__(256) k_bcg_s(cx<R>* __restrict__ r, const cx<R>* __restrict__ v,
+                                               const c64* __restrict__ pdot, const BcgState* __restrict__ sin,
+                                               BcgState* __restrict__ sout, int* __restrict__ active, SolverDims dm,
+                                               c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[1];
+  reduce_all<1>(pdot, dm.nblk, rhs, red);
+  BcgState s = sin[rhs];
+  const bool bad = tiny(red[0], s.bnorm2 * s.bnorm2) || !isfinite(red[0].x);
+  if (bad) {
+    s.breakdown = 1;
+  } else {
+    s.alpha = cdiv(s.rho, red[0]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    { s.ver += 1; sout[rhs] = s; }
+    if (bad) active[rhs] = 0;
+  }
+  if (bad) return;
+  const cx<R> al = cvt<R>(s.alpha);
+  c64 acc[1] = {mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> sv = r[o + i] - al * v[o + i];
+    r[o + i] = sv;
+    acc[0].x += abs2(up(sv));
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
+}
+
+// omega = t^H s / t^H t (partials pts = [t^H s, t^H t]); |s|^2 from ps.
+// u += alpha p + omega s;  r = s - omega t;  partials [|r|^2, rhat^H r]
+// (if |s| already met the tolerance: u += alpha p and stop next iteration).
 template <typename R>
 __global__ void __launch_bounds__(256) k_bcg_update(cx<R>* __restrict__ u, cx<R>* __restrict__ r,
                                                     const cx<R>* __restrict__ p, const cx<R>* __restrict__ t,
-                                                    const cx<R>* __restrict__ rhat,
-                                                    const BcgState* __restrict__ st,
-                                                    const int* __restrict__ active, SolverDims dm,
-                                                    c64* __restrict__ part) {
+                                                    const cx<R>* __restrict__ rhat, const c64* __restrict__ ps,
+                                                    const c64* __restrict__ pts, const BcgState* __restrict__ sin,
+                                                    BcgState* __restrict__ sout, const int* __restrict__ active,
+                                                    SolverDims dm, c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const BcgState& s = st[rhs];
+  c64 rs[1], rt[2];
+  reduce_all<1>(ps, dm.nblk, rhs, rs);
+  reduce_all<2>(pts, dm.nblk, rhs, rt);
+  BcgState s = sin[rhs];
+  s.s_conv = rs[0].x <= s.tol2;
+  if (s.s_conv) s.rnorm2 = rs[0].x;
+  else s.omega = (rt[1].x > 0.0) ? mk(rt[0].x / rt[1].x, rt[0].y / rt[1].x) : mk(0.0, 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) { s.ver += 1; sout[rhs] = s; }
   const cx<R> al = cvt<R>(s.alpha), om = cvt<R>(s.omega);
   const bool sc = s.s_conv;
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
@@ -271,50 +338,6 @@ __global__ void __launch_bounds__(256) k_bcg_update(cx<R>* __restrict__ u, cx<R>
   }
 }
 
-__global__ void k_bcg_fin_iter(const c64* __restrict__ part, int nblk, BcgState* __restrict__ st,
-                               int* __restrict__ active) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[2];
-  reduce_partials<2>(part, nblk, rhs, v);
-  if (threadIdx.x == 0) {
-    BcgState& s = st[rhs];
-    s.iters += 1;
-    if (s.s_conv) {
-      s.converged = 1;
-      active[rhs] = 0;
-      return;
-    }
-    s.rnorm2 = v[0].x;
-    s.rho_old = s.rho;
-    s.rho = v[1];
-    if (!isfinite(v[0].x)) {
-      s.breakdown = 1;
-      active[rhs] = 0;
-      return;
-    }
-    if (s.rnorm2 <= s.tol2) {
-      s.converged = 1;
-      active[rhs] = 0;
-      return;
-    }
-    if (s.rnorm2 < 0.98 * s.best2) {
-      s.best2 = s.rnorm2;
-      s.best_it = s.iters;
-    } else if (s.iters - s.best_it > kStallWindow) {
-      s.breakdown = 2;  // stagnated
-      active[rhs] = 0;
-      return;
-    }
-    if (tiny(s.omega, 1.0) || tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32)) {
-      s.breakdown = 1;  // restart from the current iterate (host)
-      active[rhs] = 0;
-      return;
-    }
-    s.beta = cdiv(s.rho, s.rho_old) * cdiv(s.alpha, s.omega);
-  }
-}
-
 // ============================================================================
 // QMR for complex-symmetric matrices (Freund 1992): Lanczos with the bilinear
 // form x^T y and Euclidean-normalised vectors, quasi-minimal residual by
@@ -328,16 +351,17 @@ struct QmrState {
   c64 tau, coef, ep, fpp, rnn;         // quasi-residual, step, new column entries
   double bnorm2, rnorm2, tol2, best2;
   int converged, breakdown, iters, n, best_it;
+  int ver;  // incremented by every kernel that writes the state
 };
 
-// r = b; u = 0; vprev = 0; v = b/|b|; p, pprev, q, qprev = 0; partials |b|^2, b^T b
+// r = b; u = 0; vprev = 0; p, q rings = 0; partials [|b|^2, b^T b]
 template <typename R>
 __global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
                                                     cx<R>* __restrict__ u, cx<R>* __restrict__ vprev,
                                                     cx<R>* __restrict__ pa, cx<R>* __restrict__ pb,
                                                     cx<R>* __restrict__ qa, cx<R>* __restrict__ qb,
                                                     const int* __restrict__ active, SolverDims dm,
-                                                    c64* __restrict__ part) {
+                                                    c64* __restrict__ part, c64* __restrict__ pres) {
   const int rhs = blockIdx.y;
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   if (active[rhs]) {
@@ -361,6 +385,7 @@ __global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b,
   if (threadIdx.x == 0) {
     part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
     part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+    pres[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
   }
 }
 
@@ -392,6 +417,7 @@ __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState*
     s.breakdown = 0;
     s.iters = 0;
     s.n = 0;
+    s.ver = 0;
     st[rhs] = s;
     if (s.converged) active[rhs] = 0;
   }
@@ -409,44 +435,55 @@ __global__ void __launch_bounds__(256) k_qmr_init_b(const cx<R>* __restrict__ b,
   DDA_RANGE(dm, i) { v[o + i] = inv * b[o + i]; }
 }
 
-// partials of v^T w (bilinear)
-template <typename R>
-__global__ void __launch_bounds__(256) k_bil_dot(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
-                                                 const int* __restrict__ active, SolverDims dm,
-                                                 c64* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  c64 acc[1] = {mk(0.0, 0.0)};
-  const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) { acc[0] = acc[0] + up(a[o + i]) * up(b[o + i]); }
-  block_sum<1>(acc);
-  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
-}
-
-// alpha_n = v_n^T A v_n / delta_n;  beta_n = rho_n delta_n / delta_{n-1} (0 for n = 1)
-__global__ void k_qmr_fin_alpha(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
-                                int* __restrict__ active) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[1];
-  reduce_partials<1>(part, nblk, rhs, v);
-  if (threadIdx.x == 0) {
-    QmrState& s = st[rhs];
-    s.n += 1;
-    s.alpha = cdiv(v[0], s.delta);
-    s.beta = (s.n == 1) ? mk(0.0, 0.0) : s.rho * cdiv(s.delta, s.delta_prev);
-  }
-}
-
-// vt = w - alpha v - beta vprev, written over vprev; partials |vt|^2, vt^T vt
+// Iteration n, first half.  From the previous update's partials |r_{n-1}|^2:
+// convergence / stagnation / breakdown; from the matvec's partials v_n^T w:
+// alpha_n = v_n^T A v_n / delta_n, beta_n = rho_n delta_n / delta_{n-1}
+// (0 for n = 1); vt = w - alpha_n v_n - beta_n v_{n-1} over v_{n-1};
+// partials [|vt|^2, vt^T vt].
 template <typename R>
 __global__ void __launch_bounds__(256) k_qmr_vt(const cx<R>* __restrict__ w, const cx<R>* __restrict__ v,
-                                                cx<R>* __restrict__ vprev, const QmrState* __restrict__ st,
-                                                const int* __restrict__ active, SolverDims dm,
+                                                cx<R>* __restrict__ vprev, const c64* __restrict__ pdot,
+                                                const c64* __restrict__ pres, const QmrState* __restrict__ sin,
+                                                QmrState* __restrict__ sout, int* __restrict__ active, SolverDims dm,
                                                 c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const cx<R> al = cvt<R>(st[rhs].alpha), be = cvt<R>(st[rhs].beta);
+  c64 rr[1], rd[1];
+  reduce_all<1>(pres, dm.nblk, rhs, rr);
+  reduce_all<1>(pdot, dm.nblk, rhs, rd);
+  QmrState s = sin[rhs];
+  int stop = 0;
+  s.rnorm2 = rr[0].x;
+  if (s.n > 0) {
+    s.iters = s.n;
+    if (!isfinite(rr[0].x) || s.breakdown) {
+      s.breakdown = s.breakdown ? s.breakdown : 1;
+      stop = 1;
+    } else if (s.rnorm2 <= s.tol2) {
+      s.converged = 1;
+      stop = 1;
+    } else if (!(s.rho > 0.0) || !(abs2(s.delta) > 1e-300)) {
+      s.breakdown = 1;
+      stop = 1;
+    } else if (s.rnorm2 < 0.98 * s.best2) {
+      s.best2 = s.rnorm2;
+      s.best_it = s.iters;
+    } else if (s.iters - s.best_it > kStallWindow) {
+      s.breakdown = 2;  // stagnated
+      stop = 1;
+    }
+  }
+  if (!stop) {
+    s.n += 1;
+    s.alpha = cdiv(rd[0], s.delta);
+    s.beta = (s.n == 1) ? mk(0.0, 0.0) : s.rho * cdiv(s.delta, s.delta_prev);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    { s.ver += 1; sout[rhs] = s; }
+    if (stop) active[rhs] = 0;
+  }
+  if (stop) return;
+  const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta);
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
   DDA_RANGE(dm, i) {
@@ -463,82 +500,72 @@ __global__ void __launch_bounds__(256) k_qmr_vt(const cx<R>* __restrict__ w, con
   }
 }
 
-// rho_{n+1}, delta_{n+1}; the new column (beta_n, alpha_n, rho_{n+1}) of the
-// tridiagonal matrix is rotated by the two previous Givens rotations and a new
-// one annihilates rho_{n+1}.
-__global__ void k_qmr_fin_givens(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
-                                 int* __restrict__ active) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[2];
-  reduce_partials<2>(part, nblk, rhs, v);
-  if (threadIdx.x == 0) {
-    QmrState& s = st[rhs];
-    const double h = sqrt(v[0].x);
-    s.rho_next = h;
-    const c64 f = s.beta, g = s.alpha;
-    // rotation n-2 acts on rows (n-2, n-1): entry of row n-2 was 0
-    const c64 ep = s.s2 * f;
-    const c64 fp = s.c2 * f;
-    // rotation n-1 acts on rows (n-1, n)
-    const c64 fpp = s.c1 * fp + s.s1 * g;
-    const c64 gp = s.c1 * g - conjg(s.s1) * fp;
-    // new rotation: [c s; -conj(s) c] (gp, h)^T = (rnn, 0)^T
-    const double ag = sqrt(abs2(gp));
-    double c;
-    c64 sn, rnn;
-    if (ag == 0.0) {
-      c = 0.0;
-      sn = mk(1.0, 0.0);
-      rnn = mk(h, 0.0);
-    } else {
-      const double nrm = sqrt(ag * ag + h * h);
-      c = ag / nrm;
-      sn = (c * h) * cdiv(mk(1.0, 0.0), conjg(gp));
-      rnn = (nrm / ag) * gp;
-    }
-    s.ep = ep;
-    s.fpp = fpp;
-    s.rnn = rnn;
-    s.coef = c * s.tau;
-    s.tau = (-1.0) * (conjg(sn) * s.tau);
-    s.c2 = s.c1;
-    s.s2 = s.s1;
-    s.c1 = c;
-    s.s1 = sn;
-    // Lanczos normalisation for the next step
-    s.delta_prev = s.delta;
-    s.delta = (h > 0.0) ? mk(v[1].x / (h * h), v[1].y / (h * h)) : mk(0.0, 0.0);
-    if (!(abs2(rnn) > 0.0) || !isfinite(h)) {
-      s.breakdown = 1;
-      active[rhs] = 0;
-    }
-  }
-}
-
-// v_{n+1} = vt / rho_{n+1} (in place over vprev), p_n = (v_n - f'' p_{n-1} - e' p_{n-2}) / r_nn
-// written over p_{n-2}, q_n = A p_n likewise from w, u += coef p_n,
-// r -= coef q_n; partials |r|^2
+// Iteration n, second half.  rho_{n+1} = |vt|, delta_{n+1} = vt^T vt / rho^2;
+// the new column (beta_n, alpha_n, rho_{n+1}) of the tridiagonal matrix is
+// rotated by the two previous Givens rotations and a new rotation annihilates
+// rho_{n+1}.  Then v_{n+1} = vt / rho_{n+1} (in place), p_n =
+// (v_n - f'' p_{n-1} - e' p_{n-2}) / r_nn over p_{n-2}, q_n = A p_n likewise
+// from w, u += c_n tau_n p_n, r -= c_n tau_n q_n; partials |r|^2.
 template <typename R>
 __global__ void __launch_bounds__(256) k_qmr_update(cx<R>* __restrict__ vnext, const cx<R>* __restrict__ v,
                                                     const cx<R>* __restrict__ w, const cx<R>* __restrict__ p1,
                                                     cx<R>* __restrict__ p2, const cx<R>* __restrict__ q1,
                                                     cx<R>* __restrict__ q2, cx<R>* __restrict__ u,
-                                                    cx<R>* __restrict__ r, const QmrState* __restrict__ st,
+                                                    cx<R>* __restrict__ r, const c64* __restrict__ pnorm,
+                                                    const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
                                                     const int* __restrict__ active, SolverDims dm,
                                                     c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const QmrState& s = st[rhs];
-  const R hinv = s.rho_next > 0.0 ? (R)(1.0 / s.rho_next) : (R)0;
-  const c64 ri = cdiv(mk(1.0, 0.0), s.rnn);
-  const cx<R> fpp = cvt<R>(s.fpp), ep = cvt<R>(s.ep), rinv = cvt<R>(ri), cf = cvt<R>(s.coef);
+  c64 red[2];
+  reduce_all<2>(pnorm, dm.nblk, rhs, red);
+  QmrState s = sin[rhs];
+  const double h = sqrt(red[0].x);
+  s.rho_next = h;
+  const c64 f = s.beta, g = s.alpha;
+  // rotation n-2 acts on rows (n-2, n-1): entry of row n-2 was 0
+  const c64 ep = s.s2 * f;
+  const c64 fp = s.c2 * f;
+  // rotation n-1 acts on rows (n-1, n)
+  const c64 fpp = s.c1 * fp + s.s1 * g;
+  const c64 gp = s.c1 * g - conjg(s.s1) * fp;
+  // new rotation [c s; -conj(s) c] (gp, h)^T = (rnn, 0)^T
+  const double ag = sqrt(abs2(gp));
+  double c;
+  c64 sn, rnn;
+  if (ag == 0.0) {
+    c = 0.0;
+    sn = mk(1.0, 0.0);
+    rnn = mk(h, 0.0);
+  } else {
+    const double nrm = sqrt(ag * ag + h * h);
+    c = ag / nrm;
+    sn = (c * h) * cdiv(mk(1.0, 0.0), conjg(gp));
+    rnn = (nrm / ag) * gp;
+  }
+  s.ep = ep;
+  s.fpp = fpp;
+  s.rnn = rnn;
+  s.coef = c * s.tau;
+  s.tau = (-1.0) * (conjg(sn) * s.tau);
+  s.c2 = s.c1;
+  s.s2 = s.s1;
+  s.c1 = c;
+  s.s1 = sn;
+  s.delta_prev = s.delta;
+  s.delta = (h > 0.0) ? mk(red[1].x / (h * h), red[1].y / (h * h)) : mk(0.0, 0.0);
+  s.rho = h;
+  if (!(abs2(rnn) > 0.0) || !isfinite(h)) s.breakdown = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) { s.ver += 1; sout[rhs] = s; }
+  const R hinv = h > 0.0 ? (R)(1.0 / h) : (R)0;
+  const c64 ri = (abs2(rnn) > 0.0) ? cdiv(mk(1.0, 0.0), rnn) : mk(0.0, 0.0);
+  const cx<R> fppr = cvt<R>(fpp), epr = cvt<R>(ep), rinv = cvt<R>(ri), cf = cvt<R>(s.coef);
   c64 acc[1] = {mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
   DDA_RANGE(dm, i) {
     vnext[o + i] = hinv * vnext[o + i];
-    const cx<R> pn = rinv * (v[o + i] - fpp * p1[o + i] - ep * p2[o + i]);
-    const cx<R> qn = rinv * (w[o + i] - fpp * q1[o + i] - ep * q2[o + i]);
+    const cx<R> pn = rinv * (v[o + i] - fppr * p1[o + i] - epr * p2[o + i]);
+    const cx<R> qn = rinv * (w[o + i] - fppr * q1[o + i] - epr * q2[o + i]);
     p2[o + i] = pn;
     q2[o + i] = qn;
     u[o + i] = u[o + i] + cf * pn;
@@ -548,36 +575,6 @@ __global__ void __launch_bounds__(256) k_qmr_update(cx<R>* __restrict__ vnext, c
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
-}
-
-__global__ void k_qmr_fin_conv(const c64* __restrict__ part, int nblk, QmrState* __restrict__ st,
-                               int* __restrict__ active) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  c64 v[1];
-  reduce_partials<1>(part, nblk, rhs, v);
-  if (threadIdx.x == 0) {
-    QmrState& s = st[rhs];
-    s.iters += 1;
-    s.rho = s.rho_next;
-    s.rnorm2 = v[0].x;
-    if (!isfinite(v[0].x)) {
-      s.breakdown = 1;
-      active[rhs] = 0;
-    } else if (s.rnorm2 <= s.tol2) {
-      s.converged = 1;
-      active[rhs] = 0;
-    } else if (!(s.rho > 0.0) || !(abs2(s.delta) > 1e-300)) {
-      s.breakdown = 1;
-      active[rhs] = 0;
-    } else if (s.rnorm2 < 0.98 * s.best2) {
-      s.best2 = s.rnorm2;
-      s.best_it = s.iters;
-    } else if (s.iters - s.best_it > kStallWindow) {
-      s.breakdown = 2;  // stagnated
-      active[rhs] = 0;
-    }
-  }
 }
 
 // ============================================================================
