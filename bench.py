@@ -44,6 +44,39 @@ def pass_bytes(K, J, P, Kpp, Jpp, Kh, Jh, Ph, nd, b, jacobi):
     }
 
 
+KERNEL_OF_PASS = {  # (pass, precision) -> kernel template name in the rocprofv3 summaries
+    ("y_forward", "fp32"): "dda::k_fast_yfwd<float", ("x_forward", "fp32"): "dda::k_fast_x<float, false",
+    ("z_product", "fp32"): "dda::k_fast_zmul<float", ("x_inverse", "fp32"): "dda::k_fast_x<float, true",
+    ("y_inverse", "fp32"): "dda::k_fast_yinv<float",
+}
+
+
+def kernel_source_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ["fft_fast.hpp", "fft_core.hpp", "kernels_fft.hpp"]:
+        with open(os.path.join(ROOT, "paper_0908_0863_amd", "csrc", f), "rb") as fh:
+            h.update(hashlib.sha1(fh.read()).hexdigest().encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pass_name, prec, workload):
+    """HBM bytes per launch of a pass from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_matvec_fp32_{workload}.txt")
+    key = KERNEL_OF_PASS.get((pass_name, prec))
+    if key is None or not os.path.exists(path):
+        return None
+    sha = None
+    for line in open(path):
+        if line.startswith("source_sha1:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith(key) and sha == kernel_source_sha1():
+            return int(float(line.split()[-2]))
+    return None
+
+
 def b3_bytes(K, J, P, Jpp, Kh, Jh, Ph, nd, b):
     """Minimal 3-pass data motion of one matrix-vector product (y pass, fused
     xz-plane pass, inverse y pass): b [9 N_d + 12 K J'' P + 6 K_h J_h P_h]."""
@@ -243,7 +276,8 @@ def main():
                      "timed": f"HIP events around each launch over {args.steps} profiled steps "
                               f"({el_prof / args.steps * 1e3:.2f} ms/step)",
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+                     "traffic": measured_traffic(name, prec, args.workload),
+                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
                      "bytes_per_launch": bpe[name]},
         "solve": {"iterations": infm[0]["iterations"], "outer_iterations": infm[0]["outer_iterations"],
                   "matvecs": infm[0]["matvecs"], "rel_residual": infm[0]["rel_residual"],
