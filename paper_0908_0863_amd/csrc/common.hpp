@@ -64,6 +64,45 @@ using c32 = cx<float>;
 
 constexpr int kMaxStages = 16;
 
+// Sum of two complex values over a block of any size <= 1024 (a multiple of
+// the 64-lane wavefront), in a fixed order; result valid in thread 0.
+__device__ __forceinline__ void block_sum2_any(cx<double>& v0, cx<double>& v1) {
+  __shared__ cx<double> sh[2][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  double a[4] = {v0.x, v0.y, v1.x, v1.y};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
+  if (lane == 0) {
+    sh[0][wv] = mk(a[0], a[1]);
+    sh[1][wv] = mk(a[2], a[3]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cx<double> s0 = sh[0][0], s1 = sh[1][0];
+    for (int w = 1; w < nw; ++w) {
+      s0 = s0 + sh[0][w];
+      s1 = s1 + sh[1][w];
+    }
+    v0 = s0;
+    v1 = s1;
+  }
+}
+
+// Inner products fused into the last pass of the matrix-vector product y = A x
+// (accumulated in FP64 while the compressed result is written):
+//   DOT_BIL  x^T y            (QMR_sym, bilinear)
+//   DOT_HA   a^H y            (BiCGSTAB rhat^H v)
+//   DOT_TS   y^H x, y^H y     (BiCGSTAB t^H s, t^H t)
+// Partials per block: part[(rhs * nblk + block) * 2 + q].
+enum { DOT_NONE = 0, DOT_BIL = 1, DOT_HA = 2, DOT_TS = 3 };
+struct DotArgs {
+  int mode = DOT_NONE;
+  const void* a = nullptr;
+  cx<double>* part = nullptr;
+};
+
 // A 1D FFT length and its Stockham radix schedule.
 struct FftDesc {
   int n;

@@ -189,7 +189,7 @@ struct PrecBufs {
   DevBuf a0, a1;            // diagonal alpha^{-1} = a0 + S a1
   DevBuf G1, G2;            // matvec workspaces
   int cap = 0;              // right-hand sides the workspaces hold
-  DevBuf vec;               // solver vectors: 10 x [cap][3][nd]
+  DevBuf vec;               // solver vectors: 7 x [cap][3][nd]
   int vec_cap = 0;
 };
 
@@ -214,6 +214,7 @@ struct dda_target {
   DevBuf active_outer;
   DevBuf state;   // solver states
   DevBuf part;    // reduction partials
+  DevBuf part_mv; // partials of the inner products fused into the matvec
   DevBuf scal;    // double [cap] scale factors
   DevBuf tolv;    // double [cap] inner tolerances
   DevBuf outer;   // FP64 outer vectors: E, r, y  (3 x [cap][3][nd])
@@ -682,11 +683,12 @@ struct FastLaunch {
   }
   template <int N>
   static void yinv(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, const int* map,
-                   const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw) {
+                   const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
+                   DotArgs dot) {
     constexpr int TX = fast_tx<N>();
     dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
     hipLaunchKernelGGL((k_fast_yinv<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G1, x, y, map, a0, a1, S,
-                       act, va, tw);
+                       act, va, tw, dot);
   }
   template <int N, bool INV>
   static void xpass(hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride, int lout_stride,
@@ -711,9 +713,26 @@ struct FastLaunch {
 
 // y = A x (jacobi = 0) or D^{-1/2} A D^{-1/2} x (jacobi = 1); S and active are
 // device arrays [nrhs] (nullable).
+// blocks per right-hand side of the last matvec pass (fused-dot partials)
+template <typename R>
+static int yinv_blocks(const dda_target* t) {
+  int tx = 0;
+  switch (t->Jpp) {
+#define DDA_CASE(N) \
+  case N:           \
+    tx = fast_tx<N>(); \
+    break;
+    DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+    default:
+      tx = tile_width<R>(t->K, t->Jpp, 2);
+  }
+  return 3 * t->P * ((t->K + tx - 1) / tx);
+}
+
 template <typename R>
 static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
-                    const int* active, hipStream_t st) {
+                    const int* active, hipStream_t st, DotArgs dot = DotArgs()) {
   CHK(ensure_matvec_ws<R>(t, nrhs));
   PrecBufs<R>& b = bufs<R>(t);
   const int K = t->K, J = t->J, P = t->P, Jpp = t->Jpp, Kpp = t->Kpp, Ppp = t->Ppp;
@@ -825,7 +844,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
 #define DDA_CASE(N)                                                                                             \
   case N:                                                                                                       \
     FastLaunch<R>::template yinv<N>(dim3(1, P, nrhs * 3), st, G1, x, y, t->map.as<int>(), a0, a1, dS, active, va, \
-                                    b.tw[1].template as<cx<R>>());                                                \
+                                    b.tw[1].template as<cx<R>>(), dot);                                           \
     break;
         DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
@@ -834,7 +853,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
       const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
       dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
       hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, t->map.as<int>(), a0, a1, dS,
-                         active, va, t->fy, b.tw[1].template as<cx<R>>());
+                         active, va, t->fy, b.tw[1].template as<cx<R>>(), dot);
     }
     LAUNCHCHK();
   }
@@ -888,7 +907,7 @@ template <typename R>
 static int ensure_solver_ws(dda_target* t, int nrhs) {
   PrecBufs<R>& b = bufs<R>(t);
   if (nrhs <= b.vec_cap) return DDA_OK;
-  CHK(b.vec.ensure((size_t)10 * nrhs * 3 * t->nd * sizeof(cx<R>)));
+  CHK(b.vec.ensure((size_t)7 * nrhs * 3 * t->nd * sizeof(cx<R>)));
   b.vec_cap = nrhs;
   return DDA_OK;
 }
@@ -937,6 +956,10 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   const int mv_per_iter = bcg ? 2 : 1;
 
   // ---- initialisation (eager); state buffer 0 receives the initial state
+  const int nblk_mv = yinv_blocks<R>(t);
+  CHK(t->part_mv.ensure((size_t)2 * nrhs * nblk_mv * 2 * sizeof(c64)));
+  c64* M0 = t->part_mv.as<c64>();
+  c64* M1 = M0 + (size_t)nrhs * nblk_mv * 2;
   if (bcg) {
     BcgState* S0 = t->state.as<BcgState>();
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(256), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
@@ -944,11 +967,10 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, R3, dm.nblk, S0, act, tolv);
   } else {
     QmrState* S0 = t->state.as<QmrState>();
-    // slot 3 = v_{n-1} (initially 0), slot 4 = v_n
-    hipLaunchKernelGGL((k_qmr_init_a<R>), vg, dim3(256), 0, st, b, slot(2), u, slot(3), slot(6), slot(7), slot(8),
-                       slot(9), act, dm, R2, R3);
-    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, R2, dm.nblk, S0, act, tolv);
-    hipLaunchKernelGGL((k_qmr_init_b<R>), vg, dim3(256), 0, st, b, slot(4), S0, act, dm);
+    // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring
+    hipLaunchKernelGGL((k_qmr_init<R>), vg, dim3(256), 0, st, b, u, slot(2), slot(3), slot(5), slot(6), act, dm,
+                       R1);
+    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, R1, dm.nblk, S0, act, tolv);
   }
   LAUNCHCHK();
 
@@ -959,30 +981,35 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       BcgState* SB = t->state.as<BcgState>() + (par ? 0 : nrhs);
       cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
       hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, s, r, p, v, R3, SA, SB, act, dm);
-      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, s));
-      hipLaunchKernelGGL((k_dots<R, 1>), vg, dim3(256), 0, s, rhat, v, act, dm, R0);
-      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, s, r, v, R0, SB, SA, act, dm, R1);
-      CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s));
-      hipLaunchKernelGGL((k_dots<R, 2>), vg, dim3(256), 0, s, tt, r, act, dm, R2);
-      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, s, u, r, p, tt, rhat, R1, R2, SA, SB, act, dm, R3);
+      DotArgs d1;
+      d1.mode = DOT_HA;
+      d1.a = rhat;
+      d1.part = M0;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, s, d1));
+      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, s, r, v, M0, nblk_mv, SB, SA, act, dm, R1);
+      DotArgs d2;
+      d2.mode = DOT_TS;
+      d2.part = M1;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s, d2));
+      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, s, u, r, p, tt, rhat, R1, M1, nblk_mv, SA, SB, act, dm,
+                         R3);
     } else {
-      QmrState* SA = t->state.as<QmrState>();
-      QmrState* SB = SA + nrhs;
-      cx<R>* r = slot(2);
-      cx<R>* w = slot(5);
-      cx<R>* vprev = par ? slot(4) : slot(3);
-      cx<R>* vcur = par ? slot(3) : slot(4);
-      cx<R>* p1 = par ? slot(7) : slot(6);
-      cx<R>* p2 = par ? slot(6) : slot(7);
-      cx<R>* q1 = par ? slot(9) : slot(8);
-      cx<R>* q2 = par ? slot(8) : slot(9);
-      CHK(matvec_T<R>(t, nrhs, dS, jacobi, vcur, w, act, s));
-      hipLaunchKernelGGL((k_bil_dot<R>), vg, dim3(256), 0, s, vcur, w, act, dm, R0);
-      hipLaunchKernelGGL((k_qmr_vt<R>), vg, dim3(256), 0, s, w, vcur, vprev, R0, R3, SA, SB, act, dm, R1);
-      // v_{n+1} lands in vprev's slot, p_n in p2's, q_n in q2's: the roles
-      // swap for the next iteration
-      hipLaunchKernelGGL((k_qmr_update<R>), vg, dim3(256), 0, s, vprev, vcur, w, p1, p2, q1, q2, u, r, R1, SB, SA,
-                         act, dm, R3);
+      QmrState* SA = t->state.as<QmrState>() + (par ? nrhs : 0);
+      QmrState* SB = t->state.as<QmrState>() + (par ? 0 : nrhs);
+      cx<R>* w = slot(4);
+      cx<R>* vn = par ? slot(3) : slot(2);
+      cx<R>* vp = par ? slot(2) : slot(3);
+      cx<R>* p1 = par ? slot(6) : slot(5);
+      cx<R>* p2 = par ? slot(5) : slot(6);
+      c64* pn_in = par ? R3 : R1;
+      c64* pn_out = par ? R1 : R3;
+      DotArgs d;
+      d.mode = DOT_BIL;
+      d.part = M0;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, vn, w, act, s, d));
+      // vt_{n+1} lands in vp's slot and p_{n-1} in p2's: roles swap next time
+      hipLaunchKernelGGL((k_qmr_step<R>), vg, dim3(256), 0, s, w, vn, vp, p1, p2, u, pn_in, M0, nblk_mv, SA, SB, act,
+                         dm, pn_out);
     }
     LAUNCHCHK();
     return DDA_OK;
@@ -998,6 +1025,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
                                   (uintptr_t)check,
                                   (uintptr_t)V,
                                   (uintptr_t)part,
+                                  (uintptr_t)t->part_mv.p,
                                   (uintptr_t)act,
                                   (uintptr_t)dS,
                                   (uintptr_t)t->state.p,

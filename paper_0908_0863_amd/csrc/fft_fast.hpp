@@ -248,12 +248,12 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
 }
 
 // y inverse, normalisation, compression and diagonal (Sec. 3, 4; step 5 of the
-// standard algorithm).
+// standard algorithm), with the solver's inner products fused (DotArgs).
 template <typename R, int N, int TX>
 __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
     const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, const int* __restrict__ map,
     const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1, const double* __restrict__ S,
-    const int* __restrict__ active, VecArgs a, const cx<R>* __restrict__ tw) {
+    const int* __restrict__ active, VecArgs a, const cx<R>* __restrict__ tw, DotArgs dt) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
   __shared__ cx<R> lds[N * TX];
   const int rc = blockIdx.z, rhs = rc / 3;
@@ -265,22 +265,27 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = (i < a.K) ? src[(long)(t + T * m) * a.K] : mk((R)0, (R)0);
   fast_fft<R, true, N>(v, t, lds, TX, l, tw);
-  if (i >= a.K) return;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
   cx<R>* yv = y + (long)rc * a.nd;
+  c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
+  if (i < a.K) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int e = t + T * m;
-    if (e >= a.J) continue;
-    const int n = map[((long)k * a.J + e) * a.K + i];
-    if (n < 0) continue;
-    const cx<R> conv = sc * v[m];
-    const cx<R> dg = diag_of(a0, a1, Sr, n);
-    if (a.jacobi) yv[n] = xv[n] + jacobi_scale(dg) * conv;
-    else yv[n] = dg * xv[n] + conv;
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      if (e >= a.J) continue;
+      const int n = map[((long)k * a.J + e) * a.K + i];
+      if (n < 0) continue;
+      const cx<R> conv = sc * v[m];
+      const cx<R> dg = diag_of(a0, a1, Sr, n);
+      const cx<R> xn = xv[n];
+      const cx<R> yn = a.jacobi ? xn + jacobi_scale(dg) * conv : dg * xn + conv;
+      yv[n] = yn;
+      dot_term(dt, xn, yn, (long)rc * a.nd + n, d0, d1);
+    }
   }
+  dot_flush(dt, rhs, rc - 3 * rhs, d0, d1);
 }
 
 // x direction on rows: RW rows per block, lane = row*T + t (t fastest).

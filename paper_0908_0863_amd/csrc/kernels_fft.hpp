@@ -231,12 +231,39 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
 // Inverse DFT along y on the K*P lines that contribute, normalisation,
 // compression back to occupied sites (Sec. 4) and the diagonal term added back
 // (step 5 of the standard algorithm).  grid = (ceil(K/TX), P, nrhs*3).
+// Accumulate the fused inner product terms of one written element.
+template <typename R>
+__device__ __forceinline__ void dot_term(const DotArgs& dt, cx<R> xv, cx<R> yv, long gidx, c64& d0, c64& d1) {
+  const c64 xd = mk((double)xv.x, (double)xv.y), yd = mk((double)yv.x, (double)yv.y);
+  if (dt.mode == DOT_BIL) {
+    d0 = d0 + xd * yd;
+  } else if (dt.mode == DOT_HA) {
+    const cx<R> av = reinterpret_cast<const cx<R>*>(dt.a)[gidx];
+    d0 = d0 + conjg(mk((double)av.x, (double)av.y)) * yd;
+  } else if (dt.mode == DOT_TS) {
+    d0 = d0 + conjg(yd) * xd;
+    d1.x += abs2(yd);
+  }
+}
+
+// Write the block's fused inner-product partials (all threads must call).
+__device__ __forceinline__ void dot_flush(const DotArgs& dt, int rhs, int c, c64 d0, c64 d1) {
+  if (dt.mode == DOT_NONE) return;
+  block_sum2_any(d0, d1);
+  if (threadIdx.x == 0) {
+    const long nblk = 3L * gridDim.y * gridDim.x;
+    const long blk = ((long)c * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    dt.part[((long)rhs * nblk + blk) * 2] = d0;
+    dt.part[((long)rhs * nblk + blk) * 2 + 1] = d1;
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x,
                                                   cx<R>* __restrict__ y, const int* __restrict__ map,
                                                   const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
                                                   const double* __restrict__ S, const int* __restrict__ active,
-                                                  VecArgs a, FftDesc d, const cx<R>* __restrict__ tw) {
+                                                  VecArgs a, FftDesc d, const cx<R>* __restrict__ tw, DotArgs dt) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int rc = blockIdx.z, rhs = rc / 3;
   if (active && !active[rhs]) return;
@@ -255,6 +282,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
   cx<R>* yv = y + (long)rc * a.nd;
+  c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   for (int idx = tid; idx < a.J * TX; idx += nthr) {
     const int e = idx / TX, l = idx - e * TX, i = i0 + l;
     if (i >= a.K) continue;
@@ -262,12 +290,12 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
     if (m < 0) continue;
     const cx<R> conv = sc * res[e * TX + l];
     const cx<R> dg = diag_of(a0, a1, Sr, m);
-    if (a.jacobi) {
-      yv[m] = xv[m] + jacobi_scale(dg) * conv;
-    } else {
-      yv[m] = dg * xv[m] + conv;
-    }
+    const cx<R> xm = xv[m];
+    const cx<R> ym = a.jacobi ? xm + jacobi_scale(dg) * conv : dg * xm + conv;
+    yv[m] = ym;
+    dot_term(dt, xm, ym, (long)rc * a.nd + m, d0, d1);
   }
+  dot_flush(dt, rhs, rc - 3 * rhs, d0, d1);
 }
 
 // z direction: forward DFT of the three components on all K''*J'' lines, the

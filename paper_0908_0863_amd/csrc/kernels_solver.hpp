@@ -263,13 +263,13 @@ __global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R
 // alpha = rho / (rhat^H v);  s = r - alpha v (stored in r); partials |s|^2
 template <typename R>
 __global__ void __launch_bounds__(256) k_bcg_s(cx<R>* __restrict__ r, const cx<R>* __restrict__ v,
-                                               const c64* __restrict__ pdot, const BcgState* __restrict__ sin,
-                                               BcgState* __restrict__ sout, int* __restrict__ active, SolverDims dm,
-                                               c64* __restrict__ part) {
+                                               const c64* __restrict__ pdot, int nblk_mv,
+                                               const BcgState* __restrict__ sin, BcgState* __restrict__ sout,
+                                               int* __restrict__ active, SolverDims dm, c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  c64 red[1];
-  reduce_all<1>(pdot, dm.nblk, rhs, red);
+  c64 red[2];
+  reduce_all<2>(pdot, nblk_mv, rhs, red);
   BcgState s = sin[rhs];
   const bool bad = tiny(red[0], s.bnorm2 * s.bnorm2) || !isfinite(red[0].x);
   if (bad) {
@@ -301,14 +301,15 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_bcg_update(cx<R>* __restrict__ u, cx<R>* __restrict__ r,
                                                     const cx<R>* __restrict__ p, const cx<R>* __restrict__ t,
                                                     const cx<R>* __restrict__ rhat, const c64* __restrict__ ps,
-                                                    const c64* __restrict__ pts, const BcgState* __restrict__ sin,
-                                                    BcgState* __restrict__ sout, const int* __restrict__ active,
-                                                    SolverDims dm, c64* __restrict__ part) {
+                                                    const c64* __restrict__ pts, int nblk_mv,
+                                                    const BcgState* __restrict__ sin, BcgState* __restrict__ sout,
+                                                    const int* __restrict__ active, SolverDims dm,
+                                                    c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
   c64 rs[1], rt[2];
   reduce_all<1>(ps, dm.nblk, rhs, rs);
-  reduce_all<2>(pts, dm.nblk, rhs, rt);
+  reduce_all<2>(pts, nblk_mv, rhs, rt);
   BcgState s = sin[rhs];
   s.s_conv = rs[0].x <= s.tol2;
   if (s.s_conv) s.rnorm2 = rs[0].x;
@@ -340,28 +341,32 @@ __global__ void __launch_bounds__(256) k_bcg_update(cx<R>* __restrict__ u, cx<R>
 
 // ============================================================================
 // QMR for complex-symmetric matrices (Freund 1992): Lanczos with the bilinear
-// form x^T y and Euclidean-normalised vectors, quasi-minimal residual by
-// Givens rotations, the residual carried alongside via q_n = A p_n.
+// form x^T y and Euclidean-normalised vectors v_n = vt_n / rho_n, the
+// tridiagonal matrix reduced by Givens rotations, iterate u_n updated through
+// p_n.  The unnormalised vectors vt_n are what is stored (and fed to the
+// matrix-vector product); 1/rho_n is applied on the fly.  One fused kernel per
+// iteration finishes column n-1 (rotation, p_{n-1}, u) and builds vt_{n+1}.
+// Stopping: the quasi-residual |tau_n| <= tol |b| (the QMR residual estimate);
+// the FP64 refinement loop checks the true residual.
 // ============================================================================
 struct QmrState {
-  c64 alpha, beta, delta, delta_prev;  // Lanczos scalars
-  double rho, rho_next;                // Euclidean norms of the unnormalised vectors
-  c64 s1, s2;                          // sines of rotations n-1, n-2
-  double c1, c2;                       // cosines of rotations n-1, n-2
-  c64 tau, coef, ep, fpp, rnn;         // quasi-residual, step, new column entries
+  c64 alpha_prev, beta_prev, delta_prev;  // alpha_{n-1}, beta_{n-1}, delta_{n-1}
+  double rho_prev;                        // rho_{n-1} = |vt_{n-1}|
+  c64 s1, s2;                             // sines of rotations n-2, n-3
+  double c1, c2;                          // cosines of rotations n-2, n-3
+  c64 tau;                                // quasi-residual tau_{n-1}
   double bnorm2, rnorm2, tol2, best2;
-  int converged, breakdown, iters, n, best_it;
+  int n, converged, breakdown, iters, best_it;
   int ver;  // incremented by every kernel that writes the state
 };
 
-// r = b; u = 0; vprev = 0; p, q rings = 0; partials [|b|^2, b^T b]
+// u = 0; vt_1 = b; vt_0 = 0; p ring = 0; partials [|b|^2, b^T b]
 template <typename R>
-__global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
-                                                    cx<R>* __restrict__ u, cx<R>* __restrict__ vprev,
-                                                    cx<R>* __restrict__ pa, cx<R>* __restrict__ pb,
-                                                    cx<R>* __restrict__ qa, cx<R>* __restrict__ qb,
-                                                    const int* __restrict__ active, SolverDims dm,
-                                                    c64* __restrict__ part, c64* __restrict__ pres) {
+__global__ void __launch_bounds__(256) k_qmr_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ u,
+                                                  cx<R>* __restrict__ v1, cx<R>* __restrict__ v0,
+                                                  cx<R>* __restrict__ pa, cx<R>* __restrict__ pb,
+                                                  const int* __restrict__ active, SolverDims dm,
+                                                  c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   if (active[rhs]) {
@@ -369,13 +374,11 @@ __global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b,
     const cx<R> z = mk((R)0, (R)0);
     DDA_RANGE(dm, i) {
       const cx<R> bv = b[o + i];
-      r[o + i] = bv;
       u[o + i] = z;
-      vprev[o + i] = z;
+      v1[o + i] = bv;
+      v0[o + i] = z;
       pa[o + i] = z;
       pb[o + i] = z;
-      qa[o + i] = z;
-      qb[o + i] = z;
       const c64 bd = up(bv);
       acc[0].x += abs2(bd);
       acc[1] = acc[1] + bd * bd;
@@ -385,7 +388,6 @@ __global__ void __launch_bounds__(256) k_qmr_init_a(const cx<R>* __restrict__ b,
   if (threadIdx.x == 0) {
     part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
     part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
-    pres[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
   }
 }
 
@@ -404,177 +406,143 @@ __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState*
     s.tol2 = tol * tol * nb2;
     s.best2 = nb2;
     s.best_it = 0;
-    s.rho = sqrt(nb2);
-    s.rho_next = 0.0;
-    s.delta = nb2 > 0 ? mk(v[1].x / nb2, v[1].y / nb2) : mk(1.0, 0.0);
+    s.alpha_prev = s.beta_prev = mk(0.0, 0.0);
     s.delta_prev = mk(1.0, 0.0);
-    s.alpha = s.beta = mk(0.0, 0.0);
+    s.rho_prev = 1.0;
     s.s1 = s.s2 = mk(0.0, 0.0);
     s.c1 = s.c2 = 1.0;
-    s.tau = mk(s.rho, 0.0);
-    s.coef = s.ep = s.fpp = s.rnn = mk(0.0, 0.0);
+    s.tau = mk(0.0, 0.0);
+    s.n = 1;
     s.converged = nb2 == 0.0;
     s.breakdown = 0;
     s.iters = 0;
-    s.n = 0;
     s.ver = 0;
     st[rhs] = s;
     if (s.converged) active[rhs] = 0;
   }
 }
 
-// v = b / rho_1
+// Iteration n (after w~ = A vt_n).  pnorm_in: partials [|vt_n|^2, vt_n^T vt_n]
+// (dm.nblk blocks); pdot: vt_n^T w~ from the matrix-vector product (nblk_mv
+// blocks, stride 2).  vn = vt_n, vp = vt_{n-1} (overwritten by vt_{n+1}),
+// p1 = p_{n-2}, p2 = p_{n-3} (overwritten by p_{n-1}).
 template <typename R>
-__global__ void __launch_bounds__(256) k_qmr_init_b(const cx<R>* __restrict__ b, cx<R>* __restrict__ v,
-                                                    const QmrState* __restrict__ st,
-                                                    const int* __restrict__ active, SolverDims dm) {
+__global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, const cx<R>* __restrict__ vn,
+                                                  cx<R>* __restrict__ vp, const cx<R>* __restrict__ p1,
+                                                  cx<R>* __restrict__ p2, cx<R>* __restrict__ u,
+                                                  const c64* __restrict__ pnorm_in, const c64* __restrict__ pdot,
+                                                  int nblk_mv, const QmrState* __restrict__ sin,
+                                                  QmrState* __restrict__ sout, int* __restrict__ active,
+                                                  SolverDims dm, c64* __restrict__ pnorm_out) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
-  const R inv = (R)(1.0 / st[rhs].rho);
-  const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) { v[o + i] = inv * b[o + i]; }
-}
-
-// Iteration n, first half.  From the previous update's partials |r_{n-1}|^2:
-// convergence / stagnation / breakdown; from the matvec's partials v_n^T w:
-// alpha_n = v_n^T A v_n / delta_n, beta_n = rho_n delta_n / delta_{n-1}
-// (0 for n = 1); vt = w - alpha_n v_n - beta_n v_{n-1} over v_{n-1};
-// partials [|vt|^2, vt^T vt].
-template <typename R>
-__global__ void __launch_bounds__(256) k_qmr_vt(const cx<R>* __restrict__ w, const cx<R>* __restrict__ v,
-                                                cx<R>* __restrict__ vprev, const c64* __restrict__ pdot,
-                                                const c64* __restrict__ pres, const QmrState* __restrict__ sin,
-                                                QmrState* __restrict__ sout, int* __restrict__ active, SolverDims dm,
-                                                c64* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  c64 rr[1], rd[1];
-  reduce_all<1>(pres, dm.nblk, rhs, rr);
-  reduce_all<1>(pdot, dm.nblk, rhs, rd);
+  c64 rn[2], rd[2];
+  reduce_all<2>(pnorm_in, dm.nblk, rhs, rn);
+  reduce_all<2>(pdot, nblk_mv, rhs, rd);
   QmrState s = sin[rhs];
+  const int n = s.n;
+  const double rho = sqrt(rn[0].x);
   int stop = 0;
-  s.rnorm2 = rr[0].x;
-  if (s.n > 0) {
-    s.iters = s.n;
-    if (!isfinite(rr[0].x) || s.breakdown) {
-      s.breakdown = s.breakdown ? s.breakdown : 1;
-      stop = 1;
-    } else if (s.rnorm2 <= s.tol2) {
-      s.converged = 1;
-      stop = 1;
-    } else if (!(s.rho > 0.0) || !(abs2(s.delta) > 1e-300)) {
+  // Lanczos scalars of step n
+  c64 alpha = mk(0.0, 0.0), beta = mk(0.0, 0.0), delta = mk(0.0, 0.0);
+  double sig = 0.0;
+  if (rho > 0.0 && isfinite(rho)) {
+    sig = 1.0 / rho;
+    delta = (sig * sig) * rn[1];
+    if (!(abs2(delta) > 1e-300)) {
+      s.breakdown = 1;  // Lanczos breakdown: vt_n^T vt_n = 0
+    } else {
+      alpha = cdiv((sig * sig) * rd[0], delta);
+      beta = (n == 1) ? mk(0.0, 0.0) : rho * cdiv(delta, s.delta_prev);
+    }
+  }
+  if (n == 1) s.tau = mk(rho, 0.0);
+  // column n-1 of the tridiagonal matrix: (beta_{n-1}, alpha_{n-1}, rho_n)
+  const bool upd = n >= 2;
+  c64 ep = mk(0.0, 0.0), fpp = mk(0.0, 0.0), rinv = mk(0.0, 0.0), coef = mk(0.0, 0.0);
+  if (upd) {
+    const double h = rho;
+    const c64 f = s.beta_prev, g = s.alpha_prev;
+    ep = s.s2 * f;
+    const c64 fp = s.c2 * f;
+    fpp = s.c1 * fp + s.s1 * g;
+    const c64 gp = s.c1 * g - conjg(s.s1) * fp;
+    const double ag = sqrt(abs2(gp));
+    double c;
+    c64 sn, rnn;
+    if (ag == 0.0) {
+      c = 0.0;
+      sn = mk(1.0, 0.0);
+      rnn = mk(h, 0.0);
+    } else {
+      const double nrm = sqrt(ag * ag + h * h);
+      c = ag / nrm;
+      sn = (c * h) * cdiv(mk(1.0, 0.0), conjg(gp));
+      rnn = (nrm / ag) * gp;
+    }
+    if (abs2(rnn) > 0.0) {
+      rinv = cdiv(mk(1.0, 0.0), rnn);
+      coef = c * s.tau;
+      s.tau = (-1.0) * (conjg(sn) * s.tau);
+    } else {
       s.breakdown = 1;
-      stop = 1;
+    }
+    s.c2 = s.c1;
+    s.s2 = s.s1;
+    s.c1 = c;
+    s.s1 = sn;
+    s.iters = n - 1;
+    s.rnorm2 = abs2(s.tau);
+    if (s.rnorm2 <= s.tol2) {
+      s.converged = 1;
     } else if (s.rnorm2 < 0.98 * s.best2) {
       s.best2 = s.rnorm2;
       s.best_it = s.iters;
     } else if (s.iters - s.best_it > kStallWindow) {
       s.breakdown = 2;  // stagnated
-      stop = 1;
     }
   }
-  if (!stop) {
-    s.n += 1;
-    s.alpha = cdiv(rd[0], s.delta);
-    s.beta = (s.n == 1) ? mk(0.0, 0.0) : s.rho * cdiv(s.delta, s.delta_prev);
-  }
+  if (!(rho > 0.0)) s.converged = 1;  // vt_n = 0: the Krylov space is invariant
+  if (!isfinite(rho) || !isfinite(s.rnorm2)) s.breakdown = 1;
+  stop = s.converged || s.breakdown;
+  const double sigp = 1.0 / s.rho_prev;
+  s.alpha_prev = alpha;
+  s.beta_prev = beta;
+  s.delta_prev = delta;
+  s.rho_prev = rho > 0.0 ? rho : 1.0;
+  s.n = n + 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    { s.ver += 1; sout[rhs] = s; }
+    s.ver += 1;
+    sout[rhs] = s;
     if (stop) active[rhs] = 0;
   }
-  if (stop) return;
-  const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta);
+  const R sgp = (R)sigp, sg = (R)sig;
+  const cx<R> fppr = cvt<R>(fpp), epr = cvt<R>(ep), rir = cvt<R>(rinv), cf = cvt<R>(coef);
+  const cx<R> al = cvt<R>(alpha), bs = cvt<R>((double)sigp * beta);
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
   DDA_RANGE(dm, i) {
-    const cx<R> t = w[o + i] - al * v[o + i] - be * vprev[o + i];
-    vprev[o + i] = t;
-    const c64 td = up(t);
-    acc[0].x += abs2(td);
-    acc[1] = acc[1] + td * td;
+    const cx<R> vpi = vp[o + i];
+    if (upd) {
+      const cx<R> pn = rir * (sgp * vpi - fppr * p1[o + i] - epr * p2[o + i]);
+      p2[o + i] = pn;
+      u[o + i] = u[o + i] + cf * pn;
+    }
+    if (!stop) {
+      const cx<R> t = sg * (w[o + i] - al * vn[o + i]) - bs * vpi;
+      vp[o + i] = t;
+      const c64 td = up(t);
+      acc[0].x += abs2(td);
+      acc[1] = acc[1] + td * td;
+    }
   }
-  block_sum<2>(acc);
-  if (threadIdx.x == 0) {
-    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
-    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  if (!stop) {
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+      pnorm_out[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+      pnorm_out[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+    }
   }
-}
-
-// Iteration n, second half.  rho_{n+1} = |vt|, delta_{n+1} = vt^T vt / rho^2;
-// the new column (beta_n, alpha_n, rho_{n+1}) of the tridiagonal matrix is
-// rotated by the two previous Givens rotations and a new rotation annihilates
-// rho_{n+1}.  Then v_{n+1} = vt / rho_{n+1} (in place), p_n =
-// (v_n - f'' p_{n-1} - e' p_{n-2}) / r_nn over p_{n-2}, q_n = A p_n likewise
-// from w, u += c_n tau_n p_n, r -= c_n tau_n q_n; partials |r|^2.
-template <typename R>
-__global__ void __launch_bounds__(256) k_qmr_update(cx<R>* __restrict__ vnext, const cx<R>* __restrict__ v,
-                                                    const cx<R>* __restrict__ w, const cx<R>* __restrict__ p1,
-                                                    cx<R>* __restrict__ p2, const cx<R>* __restrict__ q1,
-                                                    cx<R>* __restrict__ q2, cx<R>* __restrict__ u,
-                                                    cx<R>* __restrict__ r, const c64* __restrict__ pnorm,
-                                                    const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
-                                                    const int* __restrict__ active, SolverDims dm,
-                                                    c64* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  c64 red[2];
-  reduce_all<2>(pnorm, dm.nblk, rhs, red);
-  QmrState s = sin[rhs];
-  const double h = sqrt(red[0].x);
-  s.rho_next = h;
-  const c64 f = s.beta, g = s.alpha;
-  // rotation n-2 acts on rows (n-2, n-1): entry of row n-2 was 0
-  const c64 ep = s.s2 * f;
-  const c64 fp = s.c2 * f;
-  // rotation n-1 acts on rows (n-1, n)
-  const c64 fpp = s.c1 * fp + s.s1 * g;
-  const c64 gp = s.c1 * g - conjg(s.s1) * fp;
-  // new rotation [c s; -conj(s) c] (gp, h)^T = (rnn, 0)^T
-  const double ag = sqrt(abs2(gp));
-  double c;
-  c64 sn, rnn;
-  if (ag == 0.0) {
-    c = 0.0;
-    sn = mk(1.0, 0.0);
-    rnn = mk(h, 0.0);
-  } else {
-    const double nrm = sqrt(ag * ag + h * h);
-    c = ag / nrm;
-    sn = (c * h) * cdiv(mk(1.0, 0.0), conjg(gp));
-    rnn = (nrm / ag) * gp;
-  }
-  s.ep = ep;
-  s.fpp = fpp;
-  s.rnn = rnn;
-  s.coef = c * s.tau;
-  s.tau = (-1.0) * (conjg(sn) * s.tau);
-  s.c2 = s.c1;
-  s.s2 = s.s1;
-  s.c1 = c;
-  s.s1 = sn;
-  s.delta_prev = s.delta;
-  s.delta = (h > 0.0) ? mk(red[1].x / (h * h), red[1].y / (h * h)) : mk(0.0, 0.0);
-  s.rho = h;
-  if (!(abs2(rnn) > 0.0) || !isfinite(h)) s.breakdown = 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) { s.ver += 1; sout[rhs] = s; }
-  const R hinv = h > 0.0 ? (R)(1.0 / h) : (R)0;
-  const c64 ri = (abs2(rnn) > 0.0) ? cdiv(mk(1.0, 0.0), rnn) : mk(0.0, 0.0);
-  const cx<R> fppr = cvt<R>(fpp), epr = cvt<R>(ep), rinv = cvt<R>(ri), cf = cvt<R>(s.coef);
-  c64 acc[1] = {mk(0.0, 0.0)};
-  const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) {
-    vnext[o + i] = hinv * vnext[o + i];
-    const cx<R> pn = rinv * (v[o + i] - fppr * p1[o + i] - epr * p2[o + i]);
-    const cx<R> qn = rinv * (w[o + i] - fppr * q1[o + i] - epr * q2[o + i]);
-    p2[o + i] = pn;
-    q2[o + i] = qn;
-    u[o + i] = u[o + i] + cf * pn;
-    const cx<R> rn = r[o + i] - cf * qn;
-    r[o + i] = rn;
-    acc[0].x += abs2(up(rn));
-  }
-  block_sum<1>(acc);
-  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
 }
 
 // ============================================================================
