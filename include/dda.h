@@ -147,6 +147,12 @@ int dda_cross_sections(dda_target *t, int nrhs, const double *S, const void *ein
 int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *S, const void *p_dev,
                       void *grad_dev, void *hip_stream);
 
+/* Options of a target.  DDA_OPT_FIVE_PASS != 0 runs the matrix-vector product
+ * as five separate passes (y, x, z with product, x inverse, y inverse) even
+ * where the fused xy-plane passes apply (used to test both schedules). */
+enum { DDA_OPT_FIVE_PASS = 1 };
+int dda_target_set_option(dda_target *t, int option, int value);
+
 /* Sizes of the embedding, for inspection:
  * dims[0..8] = K'', J'', P'', K_h, J_h, P_h, N_d, and the 1D transform counts
  * of one matrix-vector product per right-hand side (forward + inverse) and of
@@ -156,14 +162,15 @@ int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
 /* Copy the spectrum [6][P_h][J_h][K_h] (complex128 or complex64) to out_dev. */
 int dda_get_spectrum(dda_target *t, int precision, void *out_dev, void *hip_stream);
 
-/* Kernel timing for measurement: while enabled, every launch of the five
- * matrix-vector passes is bracketed by HIP events on its own stream.
- * dda_profile_read fills ms[10] (summed milliseconds) and count[10]
- * (launches) for the passes y-forward, x-forward, z (forward, product,
- * inverse), x-inverse, y-inverse with FP64 vectors (0..4) and FP32 vectors
- * (5..9); it waits for the recorded events. */
+/* Kernel timing for measurement: while enabled, every launch of a
+ * matrix-vector pass is bracketed by HIP events on its own stream (and the
+ * solver does not capture graphs).  dda_profile_read fills ms[14] (summed
+ * milliseconds) and count[14] (launches) for the passes y-forward, x-forward,
+ * z (forward, product, inverse), x-inverse, y-inverse, fused xy-forward,
+ * fused xy-inverse with FP64 vectors (0..6) and FP32 vectors (7..13); it
+ * waits for the recorded events. */
 int dda_profile_enable(dda_lib *lib, int enable);
-int dda_profile_read(dda_lib *lib, double *ms /* 10 */, int64_t *count /* 10 */);
+int dda_profile_read(dda_lib *lib, double *ms /* 14 */, int64_t *count /* 14 */);
 int dda_profile_reset(dda_lib *lib);
 
 /* Message of the last failing call on this thread ("" if none). */

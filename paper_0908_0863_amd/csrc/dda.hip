@@ -139,7 +139,8 @@ static int pow2_floor(long v) {
 // ----------------------------------------------------------------------------
 // Optional per-pass kernel timing: HIP events recorded on the launch stream
 // around every matrix-vector pass.
-enum { PASS_YFWD = 0, PASS_XFWD, PASS_ZMUL, PASS_XINV, PASS_YINV, PASS_COUNT = 10 };  // +5 for FP32 vectors
+enum { PASS_YFWD = 0, PASS_XFWD, PASS_ZMUL, PASS_XINV, PASS_YINV, PASS_XYFWD, PASS_XYINV, PASS_PER_PREC };
+constexpr int PASS_COUNT = 2 * PASS_PER_PREC;  // second half: FP32 vectors
 
 struct dda_lib {
   int device = 0;
@@ -208,6 +209,7 @@ struct dda_target {
   PrecBufs<double> p64;
   PrecBufs<float> p32;
   bool spec_ready = false;
+  bool force_5pass = false;  // testing: disable the fused xy-plane passes
   // per-solve scratch
   DevBuf S;       // double [cap]
   DevBuf active;  // int [cap]
@@ -423,6 +425,17 @@ void dda_target_destroy(dda_target* t) {
   if (!t) return;
   (void)hipSetDevice(t->lib->device);
   delete t;
+}
+
+int dda_target_set_option(dda_target* t, int option, int value) {
+  if (!t) return fail(DDA_EINVAL, "dda_target_set_option: NULL target");
+  switch (option) {
+    case DDA_OPT_FIVE_PASS:
+      t->force_5pass = value != 0;
+      return DDA_OK;
+    default:
+      return fail(DDA_EINVAL, "dda_target_set_option: option %d", option);
+  }
 }
 
 int dda_target_info(const dda_target* t, int64_t* dims) {
@@ -713,9 +726,85 @@ struct FastLaunch {
 
 // y = A x (jacobi = 0) or D^{-1/2} A D^{-1/2} x (jacobi = 1); S and active are
 // device arrays [nrhs] (nullable).
+// ---- fused xy-plane passes ------------------------------------------------
+#define DDA_XY_SIZES(X) X(32, 2) X(64, 2) X(64, 4) X(128, 2) X(128, 4) X(128, 8) X(256, 2) X(256, 4) \
+  X(256, 8) X(96, 2) X(96, 4) X(192, 2) X(192, 4) X(192, 8)
+static const size_t kXYLds = 80 * 1024;
+
+template <typename R, int NN, int D>
+static size_t xy_fwd_lds(int K) {
+  using PL = XYPlan<R, NN, D>;
+  const int KP = ((K + PL::CA - 1) / PL::CA) * PL::CA;
+  return ((size_t)PL::M * KP + (size_t)PL::RB * PL::LSB) * sizeof(cx<R>);
+}
+template <typename R, int NN, int D>
+static size_t xy_inv_lds(int K) {
+  constexpr int M = NN / D;
+  constexpr int TXT = FastPlan<M>::T, RX = 256 / TXT, LSX = M + M / 8 + 1;
+  constexpr int CY = 256 / FastPlan<NN>::T;
+  const int Q = (K + D - 1) / D;
+  const int QP = ((Q + CY - 1) / CY) * CY;
+  return ((size_t)NN * QP + (size_t)RX * LSX) * sizeof(cx<R>);
+}
+
+// Smallest residue split D whose block fits the LDS budget (0: no fused path).
+template <typename R>
+static void xy_plan(const dda_target* t, int& dfwd, int& dinv) {
+  dfwd = dinv = 0;
+  if (t->Kpp != t->Jpp || 2 * t->K > t->Kpp || 2 * t->J > t->Jpp) return;
+#define DDA_CASE(NN, D)                                                            \
+  if (t->Kpp == NN) {                                                              \
+    if (!dfwd && xy_fwd_lds<R, NN, D>(t->K) <= kXYLds) dfwd = D;                   \
+    if (!dinv && xy_inv_lds<R, NN, D>(t->K) <= kXYLds) dinv = D;                   \
+  }
+  DDA_XY_SIZES(DDA_CASE)
+#undef DDA_CASE
+  if (!dfwd || !dinv) dfwd = dinv = 0;
+}
+
+template <typename R, int NN, int D>
+static int launch_xy_fwd(dda_target* t, int nrhs, hipStream_t st, const cx<R>* x, cx<R>* G2, const cx<R>* a0,
+                         const cx<R>* a1, const double* dS, const int* act, const VecArgs& va) {
+  const size_t lds = xy_fwd_lds<R, NN, D>(t->K);
+  static bool attr = false;
+  if (!attr) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_xy_fwd<R, NN, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kXYLds));
+    attr = true;
+  }
+  const int ngroups = nrhs * 3 * t->P;
+  dim3 grid(8 * D * ((ngroups + 7) / 8));
+  hipLaunchKernelGGL((k_xy_fwd<R, NN, D>), grid, dim3(256), lds, st, x, G2, t->map.as<int>(), a0, a1, dS, act, va,
+                     ngroups, bufs<R>(t).tw[1].template as<cx<R>>(), bufs<R>(t).tw[0].template as<cx<R>>());
+  LAUNCHCHK();
+  return DDA_OK;
+}
+
+template <typename R, int NN, int D>
+static int launch_xy_inv(dda_target* t, int nrhs, hipStream_t st, const cx<R>* G2, const cx<R>* x, cx<R>* y,
+                         const cx<R>* a0, const cx<R>* a1, const double* dS, const int* act, const VecArgs& va,
+                         DotArgs dot) {
+  const size_t lds = xy_inv_lds<R, NN, D>(t->K);
+  static bool attr = false;
+  if (!attr) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_xy_inv<R, NN, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kXYLds));
+    attr = true;
+  }
+  const int ngroups = nrhs * 3 * t->P;
+  dim3 grid(8 * D * ((ngroups + 7) / 8));
+  hipLaunchKernelGGL((k_xy_inv<R, NN, D>), grid, dim3(256), lds, st, G2, x, y, t->map.as<int>(), a0, a1, dS, act,
+                     va, ngroups, bufs<R>(t).tw[1].template as<cx<R>>(), bufs<R>(t).tw[0].template as<cx<R>>(), dot);
+  LAUNCHCHK();
+  return DDA_OK;
+}
+
 // blocks per right-hand side of the last matvec pass (fused-dot partials)
 template <typename R>
 static int yinv_blocks(const dda_target* t) {
+  int dfwd, dinv;
+  xy_plan<R>(t, dfwd, dinv);
+  if (dinv) return 3 * t->P * dinv;
   int tx = 0;
   switch (t->Jpp) {
 #define DDA_CASE(N) \
@@ -751,8 +840,62 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
+  int dfwd = 0, dinv = 0;
+  if (!t->force_5pass) xy_plan<R>(t, dfwd, dinv);
+  if (dfwd) {
+    // fused: xy forward -> z with product -> xy inverse
+    {
+      PassTimer pt(t->lib, PASS_XYFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      int rc = DDA_EINVAL;
+#define DDA_CASE(NN, D)                                                                          \
+  if (Kpp == NN && dfwd == D) rc = launch_xy_fwd<R, NN, D>(t, nrhs, st, x, G2, a0, a1, dS, active, va);
+      DDA_XY_SIZES(DDA_CASE)
+#undef DDA_CASE
+      CHK(rc);
+    }
+    {
+      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      ZArgs za;
+      za.Kpp = Kpp;
+      za.Jpp = Jpp;
+      za.P = P;
+      za.Ppp = Ppp;
+      za.Kh = t->Kh;
+      za.Jh = t->Jh;
+      za.Ph = t->Ph;
+      if (fast_size(Ppp)) {
+        switch (Ppp) {
+#define DDA_CASE(N)                                                                                      \
+  case N:                                                                                                \
+    FastLaunch<R>::template zmul<N>(nrhs, st, G2, b.Y.template as<cx<R>>(), active, za,                   \
+                                    b.tw[2].template as<cx<R>>());                                        \
+    break;
+          DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+        }
+      } else {
+        za.TX = tile_width<R>(Kpp, Ppp, 4);
+        const size_t lds = 4 * (size_t)Ppp * za.TX * sizeof(cx<R>);
+        dim3 grid((Kpp + za.TX - 1) / za.TX, Jpp, nrhs);
+        hipLaunchKernelGGL((k_vec_zmul<R>), grid, dim3(kThreads), lds, st, G2, b.Y.template as<cx<R>>(), active,
+                           za, t->fz, b.tw[2].template as<cx<R>>());
+      }
+      LAUNCHCHK();
+    }
+    {
+      PassTimer pt(t->lib, PASS_XYINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      int rc = DDA_EINVAL;
+#define DDA_CASE(NN, D)                                                                                   \
+  if (Kpp == NN && dinv == D) rc = launch_xy_inv<R, NN, D>(t, nrhs, st, G2, x, y, a0, a1, dS, active, va, dot);
+      DDA_XY_SIZES(DDA_CASE)
+#undef DDA_CASE
+      CHK(rc);
+    }
+    t->matvecs += 1;
+    return DDA_OK;
+  }
   {
-    PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? 5 : 0), st);
+    PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
     if (fast_size(Jpp)) {
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                         \
@@ -773,7 +916,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   }
   const long rows = (long)nrhs * 3 * P * Jpp;
   {
-  PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? 5 : 0), st);
+  PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
   if (fast_size(Kpp)) {
     switch (Kpp) {
 #define DDA_CASE(N)                                                                                          \
@@ -791,7 +934,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   }
   }
   {
-    PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? 5 : 0), st);
+    PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
     ZArgs za;
     za.Kpp = Kpp;
     za.Jpp = Jpp;
@@ -820,7 +963,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     LAUNCHCHK();
   }
   {
-  PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? 5 : 0), st);
+  PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
   if (fast_size(Kpp)) {
     switch (Kpp) {
 #define DDA_CASE(N)                                                                                         \
@@ -838,7 +981,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   }
   }
   {
-    PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? 5 : 0), st);
+    PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
     if (fast_size(Jpp)) {
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                             \

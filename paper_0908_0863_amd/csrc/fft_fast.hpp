@@ -78,10 +78,10 @@ __device__ __forceinline__ int padpos(int e) {
   else return e;
 }
 
-template <typename R, bool INV, int N, int E, int RR, int P, bool LAST, int PS>
+template <typename R, bool INV, int N, int E, int RR, int P, bool LAST, int PS, int TWM = 1>
 __device__ __forceinline__ void fast_stage(cx<R> (&v)[E], int t, cx<R>* __restrict__ lds, int es, int off,
                                            const cx<R>* __restrict__ tw) {
-  constexpr int T = N / E, B = E / RR, TWS = N / (P * RR);
+  constexpr int T = N / E, B = E / RR, TWS = TWM * (N / (P * RR));
   static_assert(E % RR == 0, "radix must divide the per-thread count");
   cx<R> nv[E];
 #pragma unroll
@@ -120,7 +120,7 @@ __device__ __forceinline__ void fast_stage(cx<R> (&v)[E], int t, cx<R>* __restri
   }
 }
 
-template <typename R, bool INV, int N, int S, int PS>
+template <typename R, bool INV, int N, int S, int PS, int TWM>
 struct FastStages {
   template <int s>
   __device__ __forceinline__ static void run(cx<R> (&v)[FastPlan<N>::E], int t, cx<R>* lds, int es, int off,
@@ -128,7 +128,7 @@ struct FastStages {
     if constexpr (s < S) {
       constexpr int RR = FastPlan<N>::radix(s);
       constexpr int P = FastPlan<N>::pbefore(s);
-      fast_stage<R, INV, N, FastPlan<N>::E, RR, P, s == S - 1, PS>(v, t, lds, es, off, tw);
+      fast_stage<R, INV, N, FastPlan<N>::E, RR, P, s == S - 1, PS, TWM>(v, t, lds, es, off, tw);
       run<s + 1>(v, t, lds, es, off, tw);
     }
   }
@@ -138,10 +138,12 @@ struct FastStages {
 // must call it (it contains barriers).  PS > 0 inserts one padding slot every
 // 2^PS elements of a line in LDS (spreads the strided Stockham writes over
 // the LDS banks).
-template <typename R, bool INV, int N, int PS = 0>
+// TWM: the twiddle table has TWM * N entries (a longer length's table used
+// with stride TWM).
+template <typename R, bool INV, int N, int PS = 0, int TWM = 1>
 __device__ __forceinline__ void fast_fft(cx<R> (&v)[FastPlan<N>::E], int t, cx<R>* lds, int es, int off,
                                          const cx<R>* tw) {
-  FastStages<R, INV, N, FastPlan<N>::S, PS>::template run<0>(v, t, lds, es, off, tw);
+  FastStages<R, INV, N, FastPlan<N>::S, PS, TWM>::template run<0>(v, t, lds, es, off, tw);
 }
 
 // Three interleaved transforms (the three vector components) sharing the
@@ -408,6 +410,205 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __rest
     for (int m = 0; m < E; ++m) {
       const int e = t + T * m;
       if (e < a.P) dst[e * plane] = v[c][m];
+    }
+  }
+}
+
+// ===========================================================================
+// Fused xy-plane passes (lattices whose padded x and y lengths are equal, NN).
+//
+// Forward: one z-plane k of one component, restricted to the y frequencies
+// j'' = D q + py (q < M = NN/D).  Since
+//   Y[D q + py] = sum_{j1<M} w_M^{q j1} sum_{j2} X[j1 + M j2] w_NN^{py (j1 + M j2)},
+// the block expands its plane (Sec. 4), folds and pre-twiddles each column,
+// runs an M-point DFT along y (Sec. 3: only the K*P lines that hold data),
+// transposes through LDS and runs the NN-point DFT along x on its M rows
+// (K non-zeros each), writing those rows of G2.  No block depends on
+// another; the D blocks of one plane read the same input and are dealt to the
+// same XCD in consecutive slots.
+//
+// Inverse: one plane, restricted to the x outputs i = D q + rx:
+//   x[D q + rx] = sum_{k1<M} w_M^{-k1 q} sum_{k2} X[k1 + M k2] w_NN^{-(k1 + M k2) rx},
+// so the block folds each G2 row, runs an M-point inverse DFT along x keeping
+// the outputs i < K, transposes, runs the NN-point inverse DFT along y keeping
+// j < J, normalises, compresses and adds the diagonal (with the fused inner
+// products of the solver).
+// ===========================================================================
+template <int D>
+__device__ __forceinline__ void xcd_member(int b, int& group, int& member) {
+  const int xcd = b & 7, slot = b >> 3;
+  member = slot % D;
+  group = (slot / D) * 8 + xcd;
+}
+
+template <typename R, int NN, int D>
+struct XYPlan {
+  static constexpr int M = NN / D;
+  static constexpr int TB = 256;
+  static constexpr int EA = FastPlan<M>::E, TA = FastPlan<M>::T;  // M-point transforms
+  static constexpr int CA = TB / TA;                              // columns per chunk
+  static constexpr int EB = FastPlan<NN>::E, TBT = FastPlan<NN>::T;  // NN-point transforms
+  static constexpr int RB = TB / TBT;                                // rows per chunk
+  static constexpr int LSB = NN + NN / 8 + 1;                        // padded row stride
+};
+
+template <typename R, int NN, int D>
+__global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<R>* __restrict__ G2,
+                                                const int* __restrict__ map, const cx<R>* __restrict__ a0,
+                                                const cx<R>* __restrict__ a1, const double* __restrict__ S,
+                                                const int* __restrict__ active, VecArgs a, int ngroups,
+                                                const cx<R>* __restrict__ twy, const cx<R>* __restrict__ twx) {
+  using PL = XYPlan<R, NN, D>;
+  constexpr int M = PL::M, EA = PL::EA, TA = PL::TA, CA = PL::CA, EB = PL::EB, TBT = PL::TBT, RB = PL::RB;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int KP = ((a.K + CA - 1) / CA) * CA;          // padded row stride: chunks never overlap
+  cx<R>* tr = reinterpret_cast<cx<R>*>(smem);       // [M][KP] transpose buffer
+  cx<R>* xb = tr + (long)M * KP;                      // [RB][LSB] x-exchange area
+  int group, py;
+  xcd_member<D>(blockIdx.x, group, py);
+  if (group >= ngroups) return;
+  const int k = group % a.P, rc = group / a.P, rhs = rc / 3;
+  if (active && !active[rhs]) return;
+  const R Sr = S ? (R)S[rhs] : (R)0;
+  const cx<R>* xv = x + (long)rc * a.nd;
+  // phase A: columns i in chunks of CA, M-point DFT along y
+  for (int c0 = 0; c0 < a.K; c0 += CA) {
+    const int l = threadIdx.x % CA, t = threadIdx.x / CA;
+    const int i = c0 + l;
+    cx<R> v[EA];
+#pragma unroll
+    for (int m = 0; m < EA; ++m) {
+      const int j1 = t + TA * m;
+      cx<R> acc = mk((R)0, (R)0);
+      if (i < a.K) {
+        for (int j = j1; j < a.J; j += M) {
+          const int n = map[((long)k * a.J + j) * a.K + i];
+          if (n >= 0) {
+            cx<R> val = xv[n];
+            if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, n)) * val;
+            acc = acc + val * twy[(py * j) % NN];
+          }
+        }
+      }
+      v[m] = acc;
+    }
+    // exchange inside this chunk's own columns of the transpose buffer
+    fast_fft<R, false, M, 0, D>(v, t, tr + c0, KP, l, twy);
+#pragma unroll
+    for (int m = 0; m < EA; ++m) tr[(long)(t + TA * m) * KP + i] = v[m];
+  }
+  __syncthreads();
+  // phase B: rows q in chunks of RB, NN-point DFT along x (K non-zeros)
+  const int plane_row = a.Kpp;
+  cx<R>* g2 = G2 + ((long)rc * a.P + k) * a.Jpp * plane_row;
+  for (int r0 = 0; r0 < M; r0 += RB) {
+    const int rw = threadIdx.x / TBT, t = threadIdx.x % TBT;
+    const int q = r0 + rw;
+    cx<R> v[EB];
+#pragma unroll
+    for (int m = 0; m < EB; ++m) {
+      const int e = t + TBT * m;
+      v[m] = (q < M && e < a.K) ? tr[(long)q * KP + e] : mk((R)0, (R)0);
+    }
+    fast_fft<R, false, NN, 3>(v, t, xb, 1, rw * PL::LSB, twx);
+    if (q < M) {
+      cx<R>* dst = g2 + (long)(D * q + py) * plane_row;
+#pragma unroll
+      for (int m = 0; m < EB; ++m) dst[t + TBT * m] = v[m];
+    }
+  }
+}
+
+template <typename R, int NN, int D>
+__global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, const cx<R>* __restrict__ x,
+                                                cx<R>* __restrict__ y, const int* __restrict__ map,
+                                                const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
+                                                const double* __restrict__ S, const int* __restrict__ active,
+                                                VecArgs a, int ngroups, const cx<R>* __restrict__ twy,
+                                                const cx<R>* __restrict__ twx, DotArgs dt) {
+  using PL = XYPlan<R, NN, D>;
+  constexpr int M = PL::M;
+  // x inverse: M-point transforms on rows; y inverse: NN-point on columns
+  constexpr int EX = FastPlan<M>::E, TXT = FastPlan<M>::T, RX = 256 / TXT, LSX = M + M / 8 + 1;
+  constexpr int EY = FastPlan<NN>::E, TY = FastPlan<NN>::T, CY = 256 / TY;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Q = (a.K + D - 1) / D;                    // x outputs per residue (upper bound)
+  const int QP = ((Q + CY - 1) / CY) * CY;            // padded row stride: chunks never overlap
+  cx<R>* tr = reinterpret_cast<cx<R>*>(smem);       // [NN][QP] transpose buffer
+  cx<R>* xb = tr + (long)NN * QP;                     // [RX][LSX] x-exchange area
+  int group, rx;
+  xcd_member<D>(blockIdx.x, group, rx);
+  c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
+  if (group >= ngroups) return;
+  const int k = group % a.P, rc = group / a.P, rhs = rc / 3;
+  if (active && !active[rhs]) return;
+  const cx<R>* g2 = G2 + ((long)rc * a.P + k) * a.Jpp * a.Kpp;
+  // phase B': rows j'' in chunks of RX; fold, M-point inverse DFT along x
+  for (int r0 = 0; r0 < NN; r0 += RX) {
+    const int rw = threadIdx.x / TXT, t = threadIdx.x % TXT;
+    const int jr = r0 + rw;
+    cx<R> v[EX];
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+      const int k1 = t + TXT * m;
+      cx<R> acc = mk((R)0, (R)0);
+      if (jr < NN) {
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) {
+          const int kk = k1 + M * k2;
+          cx<R> w = twx[(kk * rx) % NN];
+          w.y = -w.y;
+          acc = acc + g2[(long)jr * a.Kpp + kk] * w;
+        }
+      }
+      v[m] = acc;
+    }
+    fast_fft<R, true, M, 3, D>(v, t, xb, 1, rw * LSX, twx);
+    if (jr < NN) {
+#pragma unroll
+      for (int m = 0; m < EX; ++m) {
+        const int q = t + TXT * m;
+        if (q < QP) tr[(long)jr * QP + q] = v[m];
+      }
+    }
+  }
+  __syncthreads();
+  // phase A': columns q in chunks of CY; NN-point inverse DFT along y
+  const R Sr = S ? (R)S[rhs] : (R)0;
+  const R sc = (R)a.scale;
+  const cx<R>* xv = x + (long)rc * a.nd;
+  cx<R>* yv = y + (long)rc * a.nd;
+  for (int c0 = 0; c0 < Q; c0 += CY) {
+    const int l = threadIdx.x % CY, t = threadIdx.x / CY;
+    const int q = c0 + l;
+    cx<R> v[EY];
+#pragma unroll
+    for (int m = 0; m < EY; ++m) v[m] = (q < Q) ? tr[(long)(t + TY * m) * QP + q] : mk((R)0, (R)0);
+    fast_fft<R, true, NN>(v, t, tr + c0, QP, l, twy);
+    const int i = D * q + rx;
+    if (q < Q && i < a.K) {
+#pragma unroll
+      for (int m = 0; m < EY; ++m) {
+        const int j = t + TY * m;
+        if (j >= a.J) continue;
+        const int n = map[((long)k * a.J + j) * a.K + i];
+        if (n < 0) continue;
+        const cx<R> conv = sc * v[m];
+        const cx<R> dg = diag_of(a0, a1, Sr, n);
+        const cx<R> xn = xv[n];
+        const cx<R> yn = a.jacobi ? xn + jacobi_scale(dg) * conv : dg * xn + conv;
+        yv[n] = yn;
+        dot_term(dt, xn, yn, (long)rc * a.nd + n, d0, d1);
+      }
+    }
+  }
+  if (dt.mode != DOT_NONE) {
+    block_sum2_any(d0, d1);
+    if (threadIdx.x == 0) {
+      const long nblk = 3L * a.P * D;
+      const long blk = ((long)(rc - 3 * rhs) * a.P + k) * D + rx;
+      dt.part[((long)rhs * nblk + blk) * 2] = d0;
+      dt.part[((long)rhs * nblk + blk) * 2 + 1] = d1;
     }
   }
 }

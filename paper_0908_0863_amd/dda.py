@@ -55,11 +55,13 @@ class dda_solve_info(ctypes.Structure):
 # Every symbol the header declares (tests check that the library exports them).
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
            "dda_set_permittivity", "dda_set_polarizability", "dda_build_spectrum", "dda_matvec", "dda_solve",
-           "dda_incident_field", "dda_cross_sections", "dda_grad_cabs_eps", "dda_target_info",
+           "dda_incident_field", "dda_cross_sections", "dda_grad_cabs_eps", "dda_target_set_option",
+           "dda_target_info",
            "dda_get_spectrum", "dda_profile_enable", "dda_profile_read", "dda_profile_reset",
            "dda_last_error"]
 
-PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse"]
+PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse", "xy_forward", "xy_inverse"]
+DDA_OPT_FIVE_PASS = 1
 
 _lib = None
 
@@ -88,6 +90,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_incident_field": (i, [vp, i, vp, vp, vp, vp]),
         "dda_cross_sections": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
         "dda_grad_cabs_eps": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp]),
+        "dda_target_set_option": (i, [vp, i, i]),
         "dda_target_info": (i, [vp, vp]),
         "dda_get_spectrum": (i, [vp, i, vp, vp]),
         "dda_profile_enable": (i, [vp, i]),
@@ -161,8 +164,9 @@ class Library:
 
     def profile_read(self) -> dict:
         """{(pass name, 'fp64'|'fp32'): (total ms, launches)} over the recorded launches."""
-        ms = np.zeros(10)
-        n = np.zeros(10, np.int64)
+        npass = len(PASS_NAMES)
+        ms = np.zeros(2 * npass)
+        n = np.zeros(2 * npass, np.int64)
         _check(load().dda_profile_read(self.h, _np_ptr(ms), _np_ptr(n)))
         keys = [(p, "fp64") for p in PASS_NAMES] + [(p, "fp32") for p in PASS_NAMES]
         return {k: (float(a), int(b)) for k, a, b in zip(keys, ms, n)}
@@ -219,6 +223,9 @@ class Target:
 
     def build_spectrum(self):
         _check(load().dda_build_spectrum(self.h, _stream()))
+
+    def set_option(self, option: int, value: int):
+        _check(load().dda_target_set_option(self.h, int(option), int(value)))
 
     def info(self) -> dict:
         dims = np.zeros(9, np.int64)

@@ -213,3 +213,31 @@ def test_graph_replay_matches_eager(lib, solver, precision):
         t.matvec(x)  # unrelated eager work between replays
         assert torch.equal(Pg, Pe)
         assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
+
+
+FUSED_SHAPES = [(16, 16, 16), (32, 30, 5), (45, 40, 3)]  # padded x = padded y: fused xy-plane passes apply
+
+
+@pytest.mark.parametrize("shape", FUSED_SHAPES)
+@pytest.mark.parametrize("five_pass", [False, True])
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_matvec_fused_and_five_pass_schedules(lib, shape, five_pass, jacobi):
+    from paper_0908_0863_amd import dda
+    K, J, P = shape
+    occ = inputs.sphere(16) if shape == (16, 16, 16) else _rand_occ((P, J, K), 12)
+    kd, eps = 0.42, 2.2 + 0.15j
+    t, nd = _target(lib, occ, kd, eps)
+    i = t.info()
+    assert i["Kpp"] == i["Jpp"]
+    t.set_option(dda.DDA_OPT_FIVE_PASS, int(five_pass))
+    sites = ora.sites_of(occ)
+    S = [0.0, 0.25]
+    x = inputs.complex_gaussian(13, (2, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", S[r])
+        s = 1.0 / np.sqrt(ainv) if jacobi else np.ones(nd)
+        yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
+        assert _rel(y[r], yo) < 1e-12, (shape, r)
+        assert _rel(y32[r], yo) < 2e-6, (shape, r)
