@@ -584,6 +584,8 @@ __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, co
     cx<R> v[EY];
 #pragma unroll
     for (int m = 0; m < EY; ++m) v[m] = (q < Q) ? tr[(long)(t + TY * m) * QP + q] : mk((R)0, (R)0);
+    // the transform exchanges through these same columns: every load first
+    __syncthreads();
     fast_fft<R, true, NN>(v, t, tr + c0, QP, l, twy);
     const int i = D * q + rx;
     if (q < Q && i < a.K) {
