@@ -160,7 +160,9 @@ def main():
         return
     w = inputs.workload(args.workload)
     K, J, P = w["K"], w["J"], w["P"]
-    lib = dda.Library(0)
+    import tempfile
+    tune_file = os.path.join(tempfile.mkdtemp(prefix="dda_tune_"), "tune.txt")
+    lib = dda.Library(0, tune_cache=tune_file)
     t = dda.Target(lib, K, J, P, w["kd"])
     nd = t.set_occupancy(w["occ"])
     eps = w["m"] ** 2
@@ -291,6 +293,7 @@ def main():
         "mixed_vs_fp64_speedup": round(value / fp64["solves_per_s"], 3) if fp64 else None,
         "matvec_fp32": {"us": round(mv_s * 1e6, 2), "B3_bytes": b3, "gbps_B3": round(b3 / mv_s / 1e9, 1)},
         "passes": passes,
+        "tuned_schedules": [ln.strip() for ln in open(tune_file)] if os.path.exists(tune_file) else [],
     }
     if not args.no_cpu:
         mv = fp64["matvecs"] if fp64 else infref[0]["matvecs"]

@@ -147,10 +147,12 @@ int dda_cross_sections(dda_target *t, int nrhs, const double *S, const void *ein
 int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *S, const void *p_dev,
                       void *grad_dev, void *hip_stream);
 
-/* Options of a target.  DDA_OPT_FIVE_PASS != 0 runs the matrix-vector product
- * as five separate passes (y, x, z with product, x inverse, y inverse) even
- * where the fused xy-plane passes apply (used to test both schedules). */
-enum { DDA_OPT_FIVE_PASS = 1 };
+/* Options of a target.  DDA_OPT_SCHEDULE selects the matrix-vector schedule:
+ * -1 (default) the autotuned choice, 0 five separate passes (y, x, z with
+ * product, x inverse, y inverse), D > 0 the fused xy-plane passes with the
+ * frequency range split into D residue classes (DDA_EINVAL if that schedule
+ * does not exist for the lattice). */
+enum { DDA_OPT_SCHEDULE = 1 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:

@@ -8,6 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -145,6 +148,7 @@ constexpr int PASS_COUNT = 2 * PASS_PER_PREC;  // second half: FP32 vectors
 struct dda_lib {
   int device = 0;
   std::string tune_path;
+  std::map<std::string, int> tuned;  // schedule per (lattice, padding, nrhs, precision)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (pass, start, stop)
@@ -209,7 +213,8 @@ struct dda_target {
   PrecBufs<double> p64;
   PrecBufs<float> p32;
   bool spec_ready = false;
-  bool force_5pass = false;  // testing: disable the fused xy-plane passes
+  int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
+  int sched_override = -1;   // autotuner: schedule under trial (-1: none)
   // per-solve scratch
   DevBuf S;       // double [cap]
   DevBuf active;  // int [cap]
@@ -240,6 +245,9 @@ template <>
 PrecBufs<double>& bufs<double>(dda_target* t) { return t->p64; }
 template <>
 PrecBufs<float>& bufs<float>(dda_target* t) { return t->p32; }
+
+template <typename R>
+static std::vector<int> xy_candidates(const dda_target* t);
 
 // ----------------------------------------------------------------------------
 // launch helpers
@@ -355,7 +363,16 @@ int dda_open(int hip_device, const char* tune_cache_path, dda_lib** out) {
   HIPCHK(hipSetDevice(hip_device));
   dda_lib* l = new dda_lib();
   l->device = hip_device;
-  if (tune_cache_path) l->tune_path = tune_cache_path;
+  if (tune_cache_path) {
+    l->tune_path = tune_cache_path;
+    std::ifstream f(tune_cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      const size_t eq = line.rfind(" = ");
+      if (eq == std::string::npos) continue;
+      l->tuned[line.substr(0, eq)] = std::atoi(line.c_str() + eq + 3);
+    }
+  }
   *out = l;
   return DDA_OK;
 }
@@ -430,9 +447,16 @@ void dda_target_destroy(dda_target* t) {
 int dda_target_set_option(dda_target* t, int option, int value) {
   if (!t) return fail(DDA_EINVAL, "dda_target_set_option: NULL target");
   switch (option) {
-    case DDA_OPT_FIVE_PASS:
-      t->force_5pass = value != 0;
+    case DDA_OPT_SCHEDULE: {
+      if (value > 0) {
+        const std::vector<int> c64c = xy_candidates<double>(t), c32c = xy_candidates<float>(t);
+        if (std::find(c64c.begin(), c64c.end(), value) == c64c.end() ||
+            std::find(c32c.begin(), c32c.end(), value) == c32c.end())
+          return fail(DDA_EINVAL, "dda_target_set_option: no fused schedule with split %d for this lattice", value);
+      }
+      t->forced_sched = value < 0 ? -1 : value;
       return DDA_OK;
+    }
     default:
       return fail(DDA_EINVAL, "dda_target_set_option: option %d", option);
   }
@@ -747,19 +771,18 @@ static size_t xy_inv_lds(int K) {
   return ((size_t)NN * QP + (size_t)RX * LSX) * sizeof(cx<R>);
 }
 
-// Smallest residue split D whose block fits the LDS budget (0: no fused path).
+// Residue splits D of the fused xy-plane passes that exist for this lattice
+// and fit the LDS budget (both directions).
 template <typename R>
-static void xy_plan(const dda_target* t, int& dfwd, int& dinv) {
-  dfwd = dinv = 0;
-  if (t->Kpp != t->Jpp || 2 * t->K > t->Kpp || 2 * t->J > t->Jpp) return;
-#define DDA_CASE(NN, D)                                                            \
-  if (t->Kpp == NN) {                                                              \
-    if (!dfwd && xy_fwd_lds<R, NN, D>(t->K) <= kXYLds) dfwd = D;                   \
-    if (!dinv && xy_inv_lds<R, NN, D>(t->K) <= kXYLds) dinv = D;                   \
-  }
+static std::vector<int> xy_candidates(const dda_target* t) {
+  std::vector<int> out;
+  if (t->Kpp != t->Jpp || 2 * t->K > t->Kpp || 2 * t->J > t->Jpp) return out;
+#define DDA_CASE(NN, D)                                                                              \
+  if (t->Kpp == NN && xy_fwd_lds<R, NN, D>(t->K) <= kXYLds && xy_inv_lds<R, NN, D>(t->K) <= kXYLds) \
+    out.push_back(D);
   DDA_XY_SIZES(DDA_CASE)
 #undef DDA_CASE
-  if (!dfwd || !dinv) dfwd = dinv = 0;
+  return out;
 }
 
 template <typename R, int NN, int D>
@@ -801,9 +824,11 @@ static int launch_xy_inv(dda_target* t, int nrhs, hipStream_t st, const cx<R>* G
 
 // blocks per right-hand side of the last matvec pass (fused-dot partials)
 template <typename R>
-static int yinv_blocks(const dda_target* t) {
-  int dfwd, dinv;
-  xy_plan<R>(t, dfwd, dinv);
+static int schedule_of(const dda_target* t, int nrhs);
+
+template <typename R>
+static int yinv_blocks(const dda_target* t, int nrhs) {
+  const int dinv = schedule_of<R>(t, nrhs);
   if (dinv) return 3 * t->P * dinv;
   int tx = 0;
   switch (t->Jpp) {
@@ -840,8 +865,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
-  int dfwd = 0, dinv = 0;
-  if (!t->force_5pass) xy_plan<R>(t, dfwd, dinv);
+  const int dfwd = schedule_of<R>(t, nrhs), dinv = dfwd;
   if (dfwd) {
     // fused: xy forward -> z with product -> xy inverse
     {
@@ -1004,6 +1028,79 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   return DDA_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Autotuner: the matrix-vector schedule (five passes, or fused xy-plane
+// passes with residue split D) is chosen per (lattice, padded sizes, number of
+// right-hand sides, precision) by timing each candidate on the first product
+// of that kind (HIP events, 2 warm-up + 3 timed products on the caller's
+// stream), the analogue of planning by measurement.  Choices are kept in the
+// library handle and appended to the tune-cache file when one was given.
+// ----------------------------------------------------------------------------
+template <typename R>
+static std::string tune_key(const dda_target* t, int nrhs) {
+  std::ostringstream k;
+  k << "mv " << t->K << "x" << t->J << "x" << t->P << " pad " << t->Kpp << "x" << t->Jpp << "x" << t->Ppp << " nrhs "
+    << nrhs << " " << (sizeof(R) == 4 ? "fp32" : "fp64");
+  return k.str();
+}
+
+template <typename R>
+static int schedule_of(const dda_target* t, int nrhs) {
+  if (t->sched_override >= 0) return t->sched_override;
+  if (t->forced_sched >= 0) return t->forced_sched;
+  auto it = t->lib->tuned.find(tune_key<R>(t, nrhs));
+  if (it != t->lib->tuned.end()) return it->second;
+  // untuned: smallest fitting split
+  std::vector<int> c = xy_candidates<R>(t);
+  return c.empty() ? 0 : c.front();
+}
+
+template <typename R>
+static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
+                    hipStream_t st) {
+  if (t->forced_sched >= 0) return DDA_OK;
+  const std::string key = tune_key<R>(t, nrhs);
+  if (t->lib->tuned.count(key)) return DDA_OK;
+  std::vector<int> cand = {0};
+  for (int d : xy_candidates<R>(t)) cand.push_back(d);
+  int best = 0;
+  if (cand.size() > 1) {
+    const bool prof = t->lib->prof;
+    t->lib->prof = false;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int rc = DDA_OK;
+    for (int c : cand) {
+      t->sched_override = c;
+      for (int w = 0; w < 2 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+      (void)hipEventRecord(e0, st);
+      for (int w = 0; w < 3 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rc == DDA_OK && ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    t->sched_override = -1;
+    t->matvecs -= 5 * (int)cand.size();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    t->lib->prof = prof;
+    CHK(rc);
+  }
+  t->lib->tuned[key] = best;
+  if (!t->lib->tune_path.empty()) {
+    std::ofstream f(t->lib->tune_path, std::ios::app);
+    if (f) f << key << " = " << best << "\n";
+  }
+  return DDA_OK;
+}
+
 static int check_ready(dda_target* t, const char* who) {
   if (!t) return fail(DDA_EINVAL, "%s: NULL target", who);
   if (t->nd <= 0) return fail(DDA_ESTATE, "%s: occupancy not set", who);
@@ -1026,10 +1123,16 @@ extern "C" int dda_matvec(dda_target* t, int precision, int nrhs, const double* 
     for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
   HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (precision == DDA_FP64)
+  if (precision == DDA_FP64) {
+    CHK(ensure_matvec_ws<double>(t, nrhs));
+    CHK(autotune<double>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c64*)x_dev, (c64*)y_dev, st));
     return matvec_T<double>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c64*)x_dev, (c64*)y_dev, nullptr, st);
-  if (precision == DDA_FP32)
+  }
+  if (precision == DDA_FP32) {
+    CHK(ensure_matvec_ws<float>(t, nrhs));
+    CHK(autotune<float>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, st));
     return matvec_T<float>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, nullptr, st);
+  }
   return fail(DDA_EINVAL, "dda_matvec: precision %d", precision);
 }
 
@@ -1098,8 +1201,10 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   const bool bcg = solver == DDA_BICGSTAB;
   const int mv_per_iter = bcg ? 2 : 1;
 
+  // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
+  CHK(autotune<R>(t, nrhs, dS, jacobi, slot(0), slot(4), st));
   // ---- initialisation (eager); state buffer 0 receives the initial state
-  const int nblk_mv = yinv_blocks<R>(t);
+  const int nblk_mv = yinv_blocks<R>(t, nrhs);
   CHK(t->part_mv.ensure((size_t)2 * nrhs * nblk_mv * 2 * sizeof(c64)));
   c64* M0 = t->part_mv.as<c64>();
   c64* M1 = M0 + (size_t)nrhs * nblk_mv * 2;
@@ -1166,6 +1271,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
                                   (uintptr_t)nrhs,
                                   (uintptr_t)jacobi,
                                   (uintptr_t)check,
+                                  (uintptr_t)schedule_of<R>(t, nrhs),
                                   (uintptr_t)V,
                                   (uintptr_t)part,
                                   (uintptr_t)t->part_mv.p,
@@ -1245,6 +1351,8 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
 // |E|^2 per right-hand side on the host.
 static int true_residual(dda_target* t, int nrhs, const c64* E, const c64* Pv, c64* r, c64* y, hipStream_t st,
                          std::vector<double>& rn2, std::vector<double>& en2) {
+  CHK(ensure_matvec_ws<double>(t, nrhs));
+  CHK(autotune<double>(t, nrhs, t->S.as<double>(), 0, Pv, y, st));
   CHK(matvec_T<double>(t, nrhs, t->S.as<double>(), 0, Pv, y, nullptr, st));
   SolverDims dm;
   dm.n3 = 3 * t->nd;

@@ -61,7 +61,7 @@ EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "
            "dda_last_error"]
 
 PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse", "xy_forward", "xy_inverse"]
-DDA_OPT_FIVE_PASS = 1
+DDA_OPT_SCHEDULE = 1
 
 _lib = None
 
