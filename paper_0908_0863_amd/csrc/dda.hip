@@ -190,6 +190,7 @@ struct PassTimer {
 template <typename R>
 struct PrecBufs {
   DevBuf Y;                 // spectrum [6][Ph][Jh][Kh]
+  DevBuf Yz;                // the same, z fastest: [6][Jh][Kh][Ph]
   DevBuf tw[3];             // twiddles for K'', J'', P''
   DevBuf a0, a1;            // diagonal alpha^{-1} = a0 + S a1
   DevBuf G1, G2;            // matvec workspaces
@@ -601,6 +602,8 @@ int dda_build_spectrum(dda_target* t, void* hip_stream) {
   CHK(S2.ensure(6L * P * Jh * Kh * sizeof(c64)));
   CHK(t->p64.Y.ensure(6L * Ph * Jh * Kh * sizeof(c64)));
   CHK(t->p32.Y.ensure(6L * Ph * Jh * Kh * sizeof(c32)));
+  CHK(t->p64.Yz.ensure(6L * Ph * Jh * Kh * sizeof(c64)));
+  CHK(t->p32.Yz.ensure(6L * Ph * Jh * Kh * sizeof(c32)));
   const long N = (long)K * J * P;
   hipLaunchKernelGGL(k_tensor_column, dim3((unsigned)std::min<long>((N + 255) / 256, 65535)), dim3(256), 0, st,
                      T.as<c64>(), K, J, P, t->kd);
@@ -639,6 +642,14 @@ int dda_build_spectrum(dda_target* t, void* hip_stream) {
   hipLaunchKernelGGL(k_round_to_f32, dim3((unsigned)std::min<long>((ny + 255) / 256, 65535)), dim3(256), 0, st,
                      t->p64.Y.as<c64>(), t->p32.Y.as<c32>(), ny);
   LAUNCHCHK();
+  {
+    const unsigned g = (unsigned)std::min<long>((ny + 255) / 256, 65535);
+    hipLaunchKernelGGL((k_spec_zfast<double>), dim3(g), dim3(256), 0, st, t->p64.Y.as<c64>(), t->p64.Yz.as<c64>(), Kh,
+                       Jh, Ph);
+    hipLaunchKernelGGL((k_spec_zfast<float>), dim3(g), dim3(256), 0, st, t->p32.Y.as<c32>(), t->p32.Yz.as<c32>(), Kh,
+                       Jh, Ph);
+    LAUNCHCHK();
+  }
   // temporaries are freed on return: wait for the kernels that use them
   HIPCHK(hipStreamSynchronize(st));
   t->spec_ready = true;
@@ -692,7 +703,8 @@ static int ensure_matvec_ws(dda_target* t, int nrhs) {
 template <int N>
 constexpr int fast_tx() {
   constexpr int T = FastPlan<N>::T;
-  constexpr int tx = 256 / T;
+  int tx = 256 / T;
+  if (tx < 16) tx = 512 / T < 16 ? 512 / T : 16;  // rows of >= 128 B where a 512-thread block allows
   return tx < 8 ? 8 : (tx > 64 ? 64 : tx);
 }
 template <typename R, int N>
@@ -710,6 +722,30 @@ constexpr int fast_rw() {
 
 template <typename R>
 struct FastLaunch {
+  template <int N>
+  static void xT(bool inv, int nrhs, hipStream_t st, const cx<R>* in, cx<R>* out, const dda_target* t,
+                 const int* act, const cx<R>* tw) {
+    constexpr int RK = xt_rows<R, N>();
+    dim3 grid((t->P + RK - 1) / RK, t->Jpp, nrhs * 3);
+    if (inv)
+      hipLaunchKernelGGL((k_xT_inv<R, N, RK>), grid, dim3(FastPlan<N>::T * RK), 0, st, in, out, t->K, t->P, t->Jpp,
+                         act, tw);
+    else
+      hipLaunchKernelGGL((k_xT_fwd<R, N, RK>), grid, dim3(FastPlan<N>::T * RK), 0, st, in, out, t->K, t->P, t->Jpp,
+                         act, tw);
+  }
+  template <int N>
+  static void zline(int nrhs, hipStream_t st, cx<R>* G2t, const cx<R>* Yz, const int* act, ZArgs za,
+                    const cx<R>* tw) {
+    constexpr int RL = zline_rows<R, N>();
+    ZMap zm;
+    zm.NX = (za.Kpp + RL - 1) / RL;
+    zm.ngx = (zm.NX + 1) / 2;
+    zm.ngy = za.Jpp / 2 + 1;
+    zm.ngroups = nrhs * zm.ngx * zm.ngy;
+    dim3 grid(32 * ((zm.ngroups + 7) / 8));
+    hipLaunchKernelGGL((k_zline<R, N, RL>), grid, dim3(FastPlan<N>::T * RL), 0, st, G2t, Yz, act, za, zm, tw);
+  }
   template <int N>
   static void yfwd(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, const int* map, const cx<R>* a0,
                    const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw) {
@@ -939,6 +975,54 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     LAUNCHCHK();
   }
   const long rows = (long)nrhs * 3 * P * Jpp;
+  if (fast_size(Kpp) && fast_size(Ppp)) {
+    // z-contiguous layout: x forward (transposed out) -> z lines -> x inverse (transposed in)
+    {
+      PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      switch (Kpp) {
+#define DDA_CASE(N)                                                                               \
+  case N:                                                                                         \
+    FastLaunch<R>::template xT<N>(false, nrhs, st, G1, G2, t, active, b.tw[0].template as<cx<R>>()); \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+      LAUNCHCHK();
+    }
+    {
+      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      ZArgs za;
+      za.Kpp = Kpp;
+      za.Jpp = Jpp;
+      za.P = P;
+      za.Ppp = Ppp;
+      za.Kh = t->Kh;
+      za.Jh = t->Jh;
+      za.Ph = t->Ph;
+      switch (Ppp) {
+#define DDA_CASE(N)                                                                                        \
+  case N:                                                                                                  \
+    FastLaunch<R>::template zline<N>(nrhs, st, G2, b.Yz.template as<cx<R>>(), active, za,                   \
+                                     b.tw[2].template as<cx<R>>());                                         \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+      LAUNCHCHK();
+    }
+    {
+      PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      switch (Kpp) {
+#define DDA_CASE(N)                                                                              \
+  case N:                                                                                        \
+    FastLaunch<R>::template xT<N>(true, nrhs, st, G2, G1, t, active, b.tw[0].template as<cx<R>>()); \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+      LAUNCHCHK();
+    }
+  } else {
   {
   PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
   if (fast_size(Kpp)) {
@@ -1002,6 +1086,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   } else {
     CHK(launch_contig<R>(G2, G1, rows, Kpp, K, Kpp, K, t->fx, b.tw[0].template as<cx<R>>(), true, false, 0, 0,
                          3L * P * Jpp, active, 1.0, st));
+  }
   }
   }
   {

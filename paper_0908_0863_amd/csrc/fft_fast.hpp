@@ -83,7 +83,8 @@ __device__ __forceinline__ void fast_stage(cx<R> (&v)[E], int t, cx<R>* __restri
                                            const cx<R>* __restrict__ tw) {
   constexpr int T = N / E, B = E / RR, TWS = TWM * (N / (P * RR));
   static_assert(E % RR == 0, "radix must divide the per-thread count");
-  cx<R> nv[E];
+  // butterfly u reads and (in the last stage) writes the slots u + j B: the
+  // slot sets of different u are disjoint, so the last stage works in place
 #pragma unroll
   for (int u = 0; u < B; ++u) {
     const int q = t + T * u;
@@ -102,17 +103,14 @@ __device__ __forceinline__ void fast_stage(cx<R> (&v)[E], int t, cx<R>* __restri
     dft_small<RR, R, INV>(a);
     if constexpr (LAST) {
 #pragma unroll
-      for (int j = 0; j < RR; ++j) nv[u + j * B] = a[j];
+      for (int j = 0; j < RR; ++j) v[u + j * B] = a[j];
     } else {
       const int base = (q - k) * RR + k;
 #pragma unroll
       for (int j = 0; j < RR; ++j) lds[padpos<PS>(base + j * P) * es + off] = a[j];
     }
   }
-  if constexpr (LAST) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = nv[m];
-  } else {
+  if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = lds[padpos<PS>(t + T * m) * es + off];
@@ -148,11 +146,10 @@ __device__ __forceinline__ void fast_fft(cx<R> (&v)[FastPlan<N>::E], int t, cx<R
 
 // Three interleaved transforms (the three vector components) sharing the
 // barriers: lds holds three [N][es] planes at offsets 0, cs, 2 cs.
-template <typename R, bool INV, int N, int E, int RR, int P, bool LAST>
+template <typename R, bool INV, int N, int E, int RR, int P, bool LAST, int PS = 0>
 __device__ __forceinline__ void fast_stage3(cx<R> (&v)[3][E], int t, cx<R>* __restrict__ lds, int es, int off,
                                             int cs, const cx<R>* __restrict__ tw) {
   constexpr int T = N / E, B = E / RR, TWS = N / (P * RR);
-  cx<R> nv[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -173,30 +170,25 @@ __device__ __forceinline__ void fast_stage3(cx<R> (&v)[3][E], int t, cx<R>* __re
       dft_small<RR, R, INV>(a);
       if constexpr (LAST) {
 #pragma unroll
-        for (int j = 0; j < RR; ++j) nv[c][u + j * B] = a[j];
+        for (int j = 0; j < RR; ++j) v[c][u + j * B] = a[j];
       } else {
         const int base = (q - k) * RR + k;
 #pragma unroll
-        for (int j = 0; j < RR; ++j) lds[c * cs + (base + j * P) * es + off] = a[j];
+        for (int j = 0; j < RR; ++j) lds[c * cs + padpos<PS>(base + j * P) * es + off] = a[j];
       }
     }
   }
-  if constexpr (LAST) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[c][m] = nv[c][m];
-  } else {
+  if constexpr (!LAST) {
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[c][m] = lds[c * cs + (t + T * m) * es + off];
+      for (int m = 0; m < E; ++m) v[c][m] = lds[c * cs + padpos<PS>(t + T * m) * es + off];
     __syncthreads();
   }
 }
 
-template <typename R, bool INV, int N, int S>
+template <typename R, bool INV, int N, int S, int PS = 0>
 struct FastStages3 {
   template <int s>
   __device__ __forceinline__ static void run(cx<R> (&v)[3][FastPlan<N>::E], int t, cx<R>* lds, int es, int off,
@@ -204,7 +196,7 @@ struct FastStages3 {
     if constexpr (s < S) {
       constexpr int RR = FastPlan<N>::radix(s);
       constexpr int P = FastPlan<N>::pbefore(s);
-      fast_stage3<R, INV, N, FastPlan<N>::E, RR, P, s == S - 1>(v, t, lds, es, off, cs, tw);
+      fast_stage3<R, INV, N, FastPlan<N>::E, RR, P, s == S - 1, PS>(v, t, lds, es, off, cs, tw);
       run<s + 1>(v, t, lds, es, off, cs, tw);
     }
   }
@@ -612,6 +604,192 @@ __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, co
       dt.part[((long)rhs * nblk + blk) * 2] = d0;
       dt.part[((long)rhs * nblk + blk) * 2 + 1] = d1;
     }
+  }
+}
+
+// ===========================================================================
+// Five-pass schedule with z-contiguous lines.
+//
+// The x-forward pass writes its output transposed, G2t[rhs][c][j''][i''][k]
+// (k = z fastest), through an LDS transpose, so that every z line of the
+// middle pass is one contiguous run of P values and the inverse x pass reads
+// it back the same way.  The z pass reads the spectrum in the matching
+// z-fastest copy Yz[c][j_h][i_h][k_h].
+// ===========================================================================
+template <typename R, int N>
+constexpr int xt_rows() {
+  constexpr int T = FastPlan<N>::T;
+  constexpr int want = sizeof(R) == 4 ? 16 : 8;  // 128-byte runs of k
+  return (T * want <= 512) ? want : (512 / T > 0 ? 512 / T : 1);
+}
+
+// x forward: G1 rows (k0..k0+RK, j'') of K values -> N-point DFT -> G2t.
+// grid = (ceil(P/RK), J'', nrhs*3); block RK*T, lane = row*T + t.
+template <typename R, int N, int RK>
+__global__ void __launch_bounds__(FastPlan<N>::T * RK) k_xT_fwd(const cx<R>* __restrict__ G1, cx<R>* __restrict__ G2t,
+                                                               int K, int P, int Jpp, const int* __restrict__ active,
+                                                               const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T, LS = N + N / 8 + 1, RKP = RK + 1;
+  static_assert(N * RKP <= RK * LS, "transpose stage must fit in the exchange area");
+  __shared__ cx<R> lds[RK * LS];
+  const int rc = blockIdx.z, jj = blockIdx.y, k0 = blockIdx.x * RK;
+  if (active && !active[rc / 3]) return;
+  const int rw = threadIdx.x / T, t = threadIdx.x % T;
+  const int k = k0 + rw;
+  const cx<R>* src = G1 + (((long)rc * P + k) * Jpp + jj) * K;
+  cx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    v[m] = (k < P && e < K) ? src[e] : mk((R)0, (R)0);
+  }
+  fast_fft<R, false, N, 3>(v, t, lds, 1, rw * LS, tw);
+  // registers -> [i''][row] in LDS -> coalesced runs of k
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[(t + T * m) * RKP + rw] = v[m];
+  __syncthreads();
+  cx<R>* dst = G2t + (((long)rc * Jpp + jj) * N) * P + k0;
+  for (int idx = threadIdx.x; idx < N * RK; idx += blockDim.x) {
+    const int r = idx % RK, i = idx / RK;
+    if (k0 + r < P) dst[(long)i * P + r] = lds[i * RKP + r];
+  }
+}
+
+// x inverse: G2t (N values per (j'', k) line, read as runs of k) -> N-point
+// inverse DFT -> first K values of G1 rows.
+template <typename R, int N, int RK>
+__global__ void __launch_bounds__(FastPlan<N>::T * RK) k_xT_inv(const cx<R>* __restrict__ G2t, cx<R>* __restrict__ G1,
+                                                               int K, int P, int Jpp, const int* __restrict__ active,
+                                                               const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T, LS = N + N / 8 + 1, RKP = RK + 1;
+  static_assert(N * RKP <= RK * LS, "transpose stage must fit in the exchange area");
+  __shared__ cx<R> lds[RK * LS];
+  const int rc = blockIdx.z, jj = blockIdx.y, k0 = blockIdx.x * RK;
+  if (active && !active[rc / 3]) return;
+  const cx<R>* src = G2t + (((long)rc * Jpp + jj) * N) * P + k0;
+  for (int idx = threadIdx.x; idx < N * RK; idx += blockDim.x) {
+    const int r = idx % RK, i = idx / RK;
+    lds[i * RKP + r] = (k0 + r < P) ? src[(long)i * P + r] : mk((R)0, (R)0);
+  }
+  __syncthreads();
+  const int rw = threadIdx.x / T, t = threadIdx.x % T;
+  cx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = lds[(t + T * m) * RKP + rw];
+  __syncthreads();  // the transform exchanges through the same LDS
+  fast_fft<R, true, N, 3>(v, t, lds, 1, rw * LS, tw);
+  const int k = k0 + rw;
+  if (k >= P) return;
+  cx<R>* dst = G1 + (((long)rc * P + k) * Jpp + jj) * K;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    if (e < K) dst[e] = v[m];
+  }
+}
+
+template <typename R, int N>
+constexpr int zline_rows() {
+  constexpr int T = FastPlan<N>::T, LS = N + N / 8 + 1;
+  int rl = 512 / T;
+  if (rl > 16) rl = 16;
+  while (rl > 1 && 3 * rl * LS * (int)sizeof(cx<R>) > 56 * 1024) rl /= 2;
+  return rl < 1 ? 1 : rl;
+}
+
+// z lines with the spectral product (Eqs. Q0-Q2; mirrored octant of the
+// z-fastest spectrum with Table 1 signs), in place on G2t.  Blocks take RL
+// consecutive lines i'' at one j''; mirror quadruples of line tiles share
+// spectrum rows and are dealt to one XCD in consecutive slots.
+template <typename R, int N, int RL>
+__global__ void __launch_bounds__(FastPlan<N>::T * RL) k_zline(cx<R>* __restrict__ G2t, const cx<R>* __restrict__ Yz,
+                                                              const int* __restrict__ active, ZArgs a, ZMap zm,
+                                                              const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T, LS = N + N / 8 + 1;
+  __shared__ cx<R> lds[3 * RL * LS];
+  const int b = blockIdx.x;
+  const int group = (b >> 5) * 8 + (b & 7);
+  const int member = (b >> 3) & 3;
+  if (group >= zm.ngroups) return;
+  const int per_rhs = zm.ngx * zm.ngy;
+  const int rhs = group / per_rhs;
+  const int rem = group - rhs * per_rhs;
+  const int gx = rem / zm.ngy, gy = rem - (rem / zm.ngy) * zm.ngy;
+  const int mxm = member & 1, mym = member >> 1;
+  const int xt = mxm ? zm.NX - 1 - gx : gx;
+  if (mxm && xt == gx) return;
+  const int jj = mym ? a.Jpp - gy : gy;
+  if (mym && (gy == 0 || jj == gy)) return;
+  if (active && !active[rhs]) return;
+  const int ln = threadIdx.x / T, t = threadIdx.x % T;
+  const int i = xt * RL + ln;
+  const bool ok = i < a.Kpp;
+  const long cstride = (long)a.Jpp * a.Kpp * a.P;  // one component of one right-hand side
+  const long line = ((long)jj * a.Kpp + i) * a.P;
+  cx<R> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<R>* src = G2t + (long)(rhs * 3 + c) * cstride + line;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      v[c][m] = (ok && e < a.P) ? src[e] : mk((R)0, (R)0);
+    }
+  }
+  FastStages3<R, false, N, FastPlan<N>::S, 3>::template run<0>(v, t, lds, 1, ln * LS, RL * LS, tw);
+  if (ok) {
+    const int jm = min(jj, a.Jpp - jj);
+    const bool my = jj > a.Jpp - jj;
+    const int im = min(i, a.Kpp - i);
+    const bool mx = i > a.Kpp - i;
+    int sxy[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sxy[c] = (mx ? c_sign[0][c] : 1) * (my ? c_sign[1][c] : 1);
+    const long cs = (long)a.Ph * a.Jh * a.Kh;
+    const cx<R>* yrow = Yz + ((long)jm * a.Kh + im) * a.Ph;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      const int km = min(e, N - e);
+      const bool mz = e > N - e;
+      cx<R> yv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int sg = sxy[c] * (mz ? c_sign[2][c] : 1);
+        const cx<R> w = yrow[c * cs + km];
+        yv[c] = sg < 0 ? mk(-w.x, -w.y) : w;
+      }
+      const cx<R> x0 = v[0][m], x1 = v[1][m], x2 = v[2][m];
+      v[0][m] = yv[0] * x0 + yv[1] * x1 + yv[2] * x2;
+      v[1][m] = yv[1] * x0 + yv[3] * x1 + yv[4] * x2;
+      v[2][m] = yv[2] * x0 + yv[4] * x1 + yv[5] * x2;
+    }
+  }
+  FastStages3<R, true, N, FastPlan<N>::S, 3>::template run<0>(v, t, lds, 1, ln * LS, RL * LS, tw);
+  if (!ok) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R>* dst = G2t + (long)(rhs * 3 + c) * cstride + line;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      if (e < a.P) dst[e] = v[c][m];
+    }
+  }
+}
+
+// z-fastest copy of the spectrum: Yz[c][j][i][k] = Y[c][k][j][i]
+template <typename R>
+__global__ void k_spec_zfast(const cx<R>* __restrict__ Y, cx<R>* __restrict__ Yz, int Kh, int Jh, int Ph) {
+  const long n = 6L * Ph * Jh * Kh;
+  for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < n; g += (long)gridDim.x * blockDim.x) {
+    const int k = (int)(g % Ph);
+    const long r = g / Ph;
+    const int i = (int)(r % Kh);
+    const long r2 = r / Kh;
+    const int j = (int)(r2 % Jh);
+    const int c = (int)(r2 / Jh);
+    Yz[g] = Y[(((long)c * Ph + k) * Jh + j) * Kh + i];
   }
 }
 
