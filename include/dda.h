@@ -148,10 +148,12 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
                       void *grad_dev, void *hip_stream);
 
 /* Options of a target.  DDA_OPT_SCHEDULE selects the matrix-vector schedule:
- * -1 (default) the autotuned choice, 0 five separate passes (y, x, z with
- * product, x inverse, y inverse), D > 0 the fused xy-plane passes with the
- * frequency range split into D residue classes (DDA_EINVAL if that schedule
- * does not exist for the lattice). */
+ * -1 (default) the autotuned choice; 0 five separate passes (y, x, z with
+ * product, x inverse, y inverse) with the z lines read as strided tiles;
+ * 1 five passes with the x passes transposing so that z lines are contiguous;
+ * D in {2, 4, 8} the fused xy-plane passes with the frequency range split
+ * into D residue classes.  DDA_EINVAL if that schedule does not exist for the
+ * lattice. */
 enum { DDA_OPT_SCHEDULE = 1 };
 int dda_target_set_option(dda_target *t, int option, int value);
 

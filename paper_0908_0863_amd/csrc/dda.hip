@@ -449,7 +449,9 @@ int dda_target_set_option(dda_target* t, int option, int value) {
   if (!t) return fail(DDA_EINVAL, "dda_target_set_option: NULL target");
   switch (option) {
     case DDA_OPT_SCHEDULE: {
-      if (value > 0) {
+      if (value == 1 && !(fast_size(t->Kpp) && fast_size(t->Ppp)))
+        return fail(DDA_EINVAL, "dda_target_set_option: no z-contiguous schedule for this lattice");
+      if (value >= 2) {
         const std::vector<int> c64c = xy_candidates<double>(t), c32c = xy_candidates<float>(t);
         if (std::find(c64c.begin(), c64c.end(), value) == c64c.end() ||
             std::find(c32c.begin(), c32c.end(), value) == c32c.end())
@@ -864,8 +866,8 @@ static int schedule_of(const dda_target* t, int nrhs);
 
 template <typename R>
 static int yinv_blocks(const dda_target* t, int nrhs) {
-  const int dinv = schedule_of<R>(t, nrhs);
-  if (dinv) return 3 * t->P * dinv;
+  const int sc = schedule_of<R>(t, nrhs);
+  if (sc >= 2) return 3 * t->P * sc;
   int tx = 0;
   switch (t->Jpp) {
 #define DDA_CASE(N) \
@@ -901,7 +903,8 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
-  const int dfwd = schedule_of<R>(t, nrhs), dinv = dfwd;
+  const int sched = schedule_of<R>(t, nrhs);
+  const int dfwd = sched >= 2 ? sched : 0, dinv = dfwd;
   if (dfwd) {
     // fused: xy forward -> z with product -> xy inverse
     {
@@ -975,7 +978,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     LAUNCHCHK();
   }
   const long rows = (long)nrhs * 3 * P * Jpp;
-  if (fast_size(Kpp) && fast_size(Ppp)) {
+  if (sched == 1) {
     // z-contiguous layout: x forward (transposed out) -> z lines -> x inverse (transposed in)
     {
       PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
@@ -1135,9 +1138,8 @@ static int schedule_of(const dda_target* t, int nrhs) {
   if (t->forced_sched >= 0) return t->forced_sched;
   auto it = t->lib->tuned.find(tune_key<R>(t, nrhs));
   if (it != t->lib->tuned.end()) return it->second;
-  // untuned: smallest fitting split
-  std::vector<int> c = xy_candidates<R>(t);
-  return c.empty() ? 0 : c.front();
+  // untuned: the strided five-pass schedule
+  return 0;
 }
 
 template <typename R>
@@ -1147,6 +1149,7 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   const std::string key = tune_key<R>(t, nrhs);
   if (t->lib->tuned.count(key)) return DDA_OK;
   std::vector<int> cand = {0};
+  if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {

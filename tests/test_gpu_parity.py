@@ -219,7 +219,7 @@ FUSED_SHAPES = [(16, 16, 16), (32, 30, 5), (45, 40, 3)]  # padded x = padded y: 
 
 
 @pytest.mark.parametrize("shape", FUSED_SHAPES)
-@pytest.mark.parametrize("sched", [0, 2, 4, 8, -1])
+@pytest.mark.parametrize("sched", [0, 1, 2, 4, 8, -1])
 @pytest.mark.parametrize("jacobi", [False, True])
 def test_matvec_fused_and_five_pass_schedules(lib, shape, sched, jacobi):
     from paper_0908_0863_amd import dda
@@ -232,8 +232,8 @@ def test_matvec_fused_and_five_pass_schedules(lib, shape, sched, jacobi):
     try:
         t.set_option(dda.DDA_OPT_SCHEDULE, sched)
     except dda.DDAError:
-        assert sched > 0  # that split does not exist for this lattice
-        pytest.skip(f"no fused split {sched} for {shape}")
+        assert sched > 0  # that schedule does not exist for this lattice
+        pytest.skip(f"no schedule {sched} for {shape}")
     sites = ora.sites_of(occ)
     S = [0.0, 0.25]
     x = inputs.complex_gaussian(13, (2, 3, nd))
