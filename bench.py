@@ -106,16 +106,18 @@ def cpu_baseline(w, nd, matvecs_per_solve, budget_s=12.0):
     except Exception:
         pass
     cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
-    rows = 16
-    t = 0.0
-    while True:
+    # calibrate on a few rows, then time one run sized to about budget_s
+    rows = 32
+    sel = np.linspace(0, nd - 1, rows).astype(np.int64)
+    t0 = time.perf_counter()
+    ora.dense_matvec(sites, w["kd"], ainv, x, rows=sel, nthreads=cores)
+    t = time.perf_counter() - t0
+    if t < budget_s and rows < nd:
+        rows = int(min(nd, max(rows, rows * budget_s / max(t, 1e-4))))
         sel = np.linspace(0, nd - 1, rows).astype(np.int64)
         t0 = time.perf_counter()
         ora.dense_matvec(sites, w["kd"], ainv, x, rows=sel, nthreads=cores)
         t = time.perf_counter() - t0
-        if t > budget_s / 4 or rows >= nd:
-            break
-        rows = min(nd, int(rows * max(2.0, min(8.0, (budget_s / 4) / max(t, 1e-3)))))
     t_matvec = t * nd / rows
     t_solve = t_matvec * matvecs_per_solve
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",

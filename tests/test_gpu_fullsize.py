@@ -1,0 +1,179 @@
+"""Full-size checks of the HIP path at the paper-scale workloads.
+
+* Matrix-vector product at the full lattices (64^3 cube, 96^3 ellipsoid,
+  128^3 sphere) in the configuration the solver runs it (Jacobi-scaled, tuned
+  schedule), on seeded sampled rows that the dense oracle forms one by one.
+* The paper's validation cube (Sec. 5): 100^3 dipoles, efficiencies against
+  the published table.
+* The adjoint gradient at the 128^3 sphere against central finite differences
+  of C_abs, each perturbed C_abs obtained from unperturbed solves by an exact
+  rank-3 update (difference solves), so no large-number cancellation occurs.
+* The torch.autograd wrapper against torch.autograd.gradcheck (10^3 sphere).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_0908_0863_amd import inputs
+from tests.conftest import read_golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# FP32 FFT passes: the FFT's relative rounding error grows like
+# u32 * c * log2(K''J''P''); with u32 = 6e-8, c ~ 1 and log2 up to 24 (256^3)
+# the product is below 2e-6, and the spectrum's own rounding adds u32.  The
+# bound is taken with a factor ~2 margin.
+FP32_FULL_TOL = 4e-6
+ROWS = {"cube64": 4096, "ellipsoid96": 4096, "sphere128": 2048}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0908_0863_amd import dda
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return dda.Library(0)
+
+
+def _target(lib, w, eps=None, presc="ldr"):
+    from paper_0908_0863_amd import dda
+    t = dda.Target(lib, w["K"], w["J"], w["P"], w["kd"])
+    nd = t.set_occupancy(w["occ"])
+    t.set_permittivity(np.full(nd, w["m"] ** 2) if eps is None else eps, presc)
+    t.build_spectrum()
+    return t, nd
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("name", ["cube64", "ellipsoid96", "sphere128"])
+def test_matvec_full_size_sampled_rows(lib, name):
+    w = inputs.workload(name)
+    t, nd = _target(lib, w)
+    sites = ora.sites_of(w["occ"])
+    S = ora.ldr_S(w["khat"][0], w["ehat"][0])
+    rows = np.sort(np.random.default_rng(0).choice(nd, ROWS[name], replace=False))
+    # FP32-representable input, so the FP64 and FP32 runs share one oracle result
+    x = inputs.complex_gaussian(0, (1, 3, nd)).astype(np.complex64).astype(np.complex128)
+    ainv = ora.alpha_inv(np.full(nd, w["m"] ** 2), w["kd"], "ldr", S)
+    s = 1.0 / np.sqrt(ainv)
+    yo = s[rows] * ora.dense_matvec(sites, w["kd"], ainv, s * x[0], rows=rows)
+    for dt in (np.complex128, np.complex64):
+        y = t.matvec(torch.from_numpy(x.astype(dt)).cuda(), S=[S], jacobi=True).cpu().numpy()[0][:, rows]
+        err = _rel(y, yo)
+        print(f"{name} {np.dtype(dt).name}: rel err on {rows.size} rows = {err:.3e}", flush=True)
+        assert err < (1e-12 if dt == np.complex128 else FP32_FULL_TOL), (name, dt, err)
+
+
+def test_validation_cube100_efficiencies(lib):
+    w = inputs.workload("cube100")
+    t, nd = _target(lib, w)
+    assert nd == 10 ** 6
+    P, info = t.solve(khat=w["khat"], ehat=w["ehat"], solver="qmr", precision="fp64", tol=1e-8)
+    assert info[0]["converged"]
+    E = t.incident_field(w["khat"], w["ehat"])
+    ce, ca, cs = t.cross_sections(E, P, S=[0.0])
+    area = math.pi * ora.a_eff(nd) ** 2
+    got = {"Q_ext": ce[0] / area, "Q_abs": ca[0] / area, "Q_sca": cs[0] / area}
+    print("cube100", got, info[0], flush=True)
+    for name, val in read_golden("validation_cube100.txt"):
+        assert got[name] == pytest.approx(float(val), abs=0.002), (name, got[name])
+
+
+N_FD_DIPOLES = 32
+FD_CHUNK = 8
+
+
+@pytest.mark.timeout(900)
+def test_gradient_vs_difference_solve_fd_sphere128(lib):
+    """Central FD of C_abs in Re and Im eps_n at 32 seeded dipoles of the 128^3
+    sphere.  Changing eps_n changes A by delta (e_n e_n^T) x I3, so with
+    Z = A^{-1} U (three unit right-hand sides at dipole n)
+        dP = -Z (I/delta + U^T Z)^{-1} P_n                (Woodbury, exact)
+        dC = sum_m w_m (2 Re(P_m^H dP_m) + |dP_m|^2) + dw_n |P_n + dP_n|^2,
+    evaluated through the Gram sums a_j = sum_m w_m P_m^H Z_j,m and
+    B_jk = sum_m w_m Z_j,m^H Z_k,m."""
+    w = inputs.workload("sphere128")
+    kd = w["kd"]
+    t, nd = _target(lib, w)
+    eps = w["m"] ** 2
+    kw = dict(solver="qmr", precision="fp64", tol=1e-10)
+    E = t.incident_field(w["khat"], w["ehat"])
+    P, info = t.solve(einc=E, S=[0.0], **kw)
+    g = t.grad_cabs_eps(P, S=[0.0], **kw)[0].cpu().numpy()
+    dip = np.sort(np.random.default_rng(5).choice(nd, N_FD_DIPOLES, replace=False))
+    ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0)
+    wgt = 4 * math.pi * kd * (-np.imag(ainv) - (2.0 / 3.0) * kd ** 3)
+    wd = torch.from_numpy(wgt).cuda()
+    P0 = P[0]                                                  # [3][nd]
+    Znn, a, B = [], [], []
+    for c0 in range(0, dip.size, FD_CHUNK):
+        ch = dip[c0:c0 + FD_CHUNK]
+        U = torch.zeros((3 * ch.size, 3, nd), dtype=torch.complex128, device="cuda")
+        for q, n in enumerate(ch):
+            for c in range(3):
+                U[3 * q + c, c, int(n)] = 1.0
+        Z, zinfo = t.solve(einc=U, S=[0.0] * U.shape[0], solver="qmr", precision="mixed", tol=1e-10,
+                           inner_tol=1e-4)
+        assert all(i["converged"] for i in zinfo)
+        del U
+        Z = Z.reshape(ch.size, 3, 3, nd)                       # [dipole][column j][component][site]
+        for q, n in enumerate(ch):
+            Zq = Z[q]
+            Znn.append(Zq[:, :, int(n)].T.cpu().numpy())      # [component][column]
+            a.append(torch.sum(Zq * (wd * P0.conj())[None], dim=(1, 2)).cpu().numpy())
+            Zf = Zq.reshape(3, 3 * nd)
+            wz = (Zq * wd).reshape(3, 3 * nd)
+            B.append((Zf.conj() @ wz.T.contiguous()).cpu().numpy())
+        del Z
+    P0n = P0.cpu().numpy()
+
+    def dC(q, n, de):
+        a2 = ora.alpha_inv(np.array([eps + de]), kd, "ldr", 0.0)[0]
+        delta = a2 - ainv[n]
+        core = np.linalg.solve(np.eye(3) / delta + Znn[q], P0n[:, n])
+        dPn = -(Znn[q] @ core)
+        base = -2 * np.real(a[q] @ core) + np.real(np.conj(core) @ B[q] @ core)
+        w2 = 4 * math.pi * kd * (-np.imag(a2) - (2.0 / 3.0) * kd ** 3)
+        return base + (w2 - wgt[n]) * np.sum(np.abs(P0n[:, n] + dPn) ** 2)
+
+    h = 1e-4 * abs(eps)
+    fd = np.array([(dC(q, n, h) - dC(q, n, -h)) / (2 * h) + 1j * (dC(q, n, 1j * h) - dC(q, n, -1j * h)) / (2 * h)
+                   for q, n in enumerate(dip)])
+    err = np.abs(fd - g[dip]) / np.abs(g[dip]).max()
+    print(f"sphere128 FD vs adjoint on {dip.size} dipoles: max err {err.max():.3e} "
+          f"(scale {np.abs(g[dip]).max():.3e})", flush=True)
+    assert err.max() < 1e-6
+
+
+def test_autograd_gradcheck_sphere10(lib):
+    from paper_0908_0863_amd import autograd as dag
+    w = inputs.workload("sphere10")
+    t, nd = _target(lib, w)
+    rng = np.random.default_rng(11)
+    base = torch.from_numpy(w["m"] ** 2 + 0.05 * (rng.random(nd) + 1j * rng.random(nd)))
+    idx = torch.from_numpy(rng.choice(nd, 6, replace=False))
+    kh, eh = [[0.0, 0.0, 1.0], [0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]
+
+    def f(sub):
+        eps = base.clone().to(sub.dtype)
+        eps = eps.index_put((idx,), sub)
+        return dag.cabs(eps, t, kh, eh, "ldr", tol=1e-12)
+
+    # step 1e-4: truncation O(h^2) ~ 1e-8 relative, solve noise 1e-12 / h ~ 1e-8
+    sub = base[idx].clone().requires_grad_(True)
+    assert torch.autograd.gradcheck(f, (sub,), eps=1e-4, atol=1e-5, rtol=1e-4)
+    # full gradient against the oracle's dense adjoint on the same permittivities
+    eps = base.clone().requires_grad_(True)
+    c = dag.cabs(eps, t, kh, eh, "ldr", tol=1e-12)
+    c.sum().backward()
+    sites = ora.sites_of(w["occ"])
+    go = sum(ora.grad_cabs_adjoint_dense(sites, w["kd"], base.numpy(), "ldr", 0.0,
+                                         ora.einc(sites, w["kd"], k, e))[0] for k, e in zip(kh, eh))
+    assert _rel(eps.grad.numpy(), go) < 1e-9
