@@ -1241,7 +1241,7 @@ template <typename R>
 static int ensure_solver_ws(dda_target* t, int nrhs) {
   PrecBufs<R>& b = bufs<R>(t);
   if (nrhs <= b.vec_cap) return DDA_OK;
-  CHK(b.vec.ensure((size_t)7 * nrhs * 3 * t->nd * sizeof(cx<R>)));
+  CHK(b.vec.ensure((size_t)8 * nrhs * 3 * t->nd * sizeof(cx<R>)));
   b.vec_cap = nrhs;
   return DDA_OK;
 }
@@ -1303,9 +1303,9 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, R3, dm.nblk, S0, act, tolv);
   } else {
     QmrState* S0 = t->state.as<QmrState>();
-    // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring
-    hipLaunchKernelGGL((k_qmr_init<R>), vg, dim3(256), 0, st, b, u, slot(2), slot(3), slot(5), slot(6), act, dm,
-                       R1);
+    // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring, slot 7 = QMR residual
+    hipLaunchKernelGGL((k_qmr_init<R>), vg, dim3(256), 0, st, b, u, slot(2), slot(3), slot(5), slot(6), slot(7),
+                       act, dm, R1);
     hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, R1, dm.nblk, S0, act, tolv);
   }
   LAUNCHCHK();
@@ -1344,8 +1344,8 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       d.part = M0;
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, vn, w, act, s, d));
       // vt_{n+1} lands in vp's slot and p_{n-1} in p2's: roles swap next time
-      hipLaunchKernelGGL((k_qmr_step<R>), vg, dim3(256), 0, s, w, vn, vp, p1, p2, u, pn_in, M0, nblk_mv, SA, SB, act,
-                         dm, pn_out);
+      hipLaunchKernelGGL((k_qmr_step<R>), vg, dim3(256), 0, s, w, vn, vp, p1, p2, u, slot(7), pn_in, M0, nblk_mv, SA,
+                         SB, act, dm, pn_out);
     }
     LAUNCHCHK();
     return DDA_OK;
@@ -1494,7 +1494,12 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   c64* r64 = t->outer.as<c64>() + (size_t)nrhs * n3;
   c64* y64 = r64 + (size_t)nrhs * n3;
   const bool mixed = o.precision == DDA_SOLVE_MIXED;
-  if (mixed) CHK(ensure_solver_ws<float>(t, nrhs));
+  // FP32 inner solves while they make progress; a refinement step that cuts
+  // the true residual of some right-hand side by less than 4x (FP32 Krylov
+  // recurrences can stagnate, e.g. QMR_sym on point sources) switches the
+  // remaining steps to FP64 inner solves.
+  bool lo = mixed;
+  if (lo) CHK(ensure_solver_ws<float>(t, nrhs));
   else CHK(ensure_solver_ws<double>(t, nrhs));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
   const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
@@ -1526,7 +1531,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       hsc[q] = rn2[q] > 0 ? 1.0 / std::sqrt(rn2[q]) : 0.0;
       // solve only as far as the outer target needs: ||r_new|| <= tol ||E|| / 2
       const double need = rn2[q] > 0 ? 0.5 * tol * std::sqrt(en2[q] / rn2[q]) : 1.0;
-      htol[q] = std::min(0.5, std::max(tol_in, need));
+      htol[q] = std::min(0.5, std::max(lo ? tol_in : tol, need));
     }
     if (n_left == 0) break;
     int budget = 0;
@@ -1539,7 +1544,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
     const unsigned gx = (unsigned)std::min<long>((n3 + 255) / 256, 4096);
     const c64* a0 = t->p64.a0.as<c64>();
     const c64* a1 = t->has_a1 ? t->p64.a1.as<c64>() : nullptr;
-    if (mixed) {
+    if (lo) {
       hipLaunchKernelGGL((k_scale_rhs<float>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p32.vec.as<c32>(), a0, a1,
                          t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
       LAUNCHCHK();
@@ -1555,7 +1560,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
     // P += |r| D^{-1/2} u
     for (int q = 0; q < nrhs; ++q) hsc[q] = std::sqrt(rn2[q]);
     HIPCHK(hipMemcpyAsync(t->scal.p, hsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    if (mixed) {
+    if (lo) {
       const size_t vsz = (size_t)nrhs * n3;
       hipLaunchKernelGGL((k_accumulate<float>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p32.vec.as<c32>() + vsz, a0,
                          a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
@@ -1572,7 +1577,15 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
         iters[q] += ir.iters[q];
         outer[q] += 1;
       }
+    const std::vector<double> prev = rn2;
     CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
+    if (lo)
+      for (int q = 0; q < nrhs; ++q)
+        if (hact[q] && rn2[q] > tol * tol * en2[q] && rn2[q] > prev[q] / 16.0) {
+          lo = false;
+          CHK(ensure_solver_ws<double>(t, nrhs));
+          break;
+        }
   }
   bool all = true;
   for (int q = 0; q < nrhs; ++q) {

@@ -82,9 +82,16 @@ struct SolverDims {
 // ============================================================================
 
 // Iterations without a 2% improvement of the best residual after which an
-// inner solve is declared stagnated (FP32 vectors stall near their rounding
-// level); the refinement loop then restarts from the true residual.
+// inner solve is declared stagnated; the refinement loop then restarts from
+// the FP64 true residual.  FP32 vectors lose the Lanczos/BiCG relations early
+// (a restart is cheaper than a long plateau), so an FP32 solve may stall at
+// any level; an FP64 solve only near its rounding level, since plateaus above
+// it are ordinary Krylov behaviour at large size parameters.
 constexpr int kStallWindow = 64;
+template <typename R>
+__device__ __forceinline__ double stall_level2() {
+  return sizeof(R) == 4 ? 2.0 : 1e-22;  // relative |r|^2 below which a stall counts
+}
 
 // Reduce the partials of right-hand side `rhs` and broadcast to every thread.
 template <int ND>
@@ -237,7 +244,7 @@ __global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R
     } else if (s.rnorm2 < 0.98 * s.best2) {
       s.best2 = s.rnorm2;
       s.best_it = s.iters;
-    } else if (s.iters - s.best_it > kStallWindow) {
+    } else if (s.iters - s.best_it > kStallWindow && s.rnorm2 < stall_level2<R>() * s.bnorm2) {
       s.breakdown = 2;  // stagnated
       stop = 1;
     }
@@ -360,13 +367,13 @@ struct QmrState {
   int ver;  // incremented by every kernel that writes the state
 };
 
-// u = 0; vt_1 = b; vt_0 = 0; p ring = 0; partials [|b|^2, b^T b]
+// u = 0; vt_1 = b; vt_0 = 0; p ring = 0; r = b; partials [(|b|^2, |r|^2), b^T b]
 template <typename R>
 __global__ void __launch_bounds__(256) k_qmr_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ u,
                                                   cx<R>* __restrict__ v1, cx<R>* __restrict__ v0,
                                                   cx<R>* __restrict__ pa, cx<R>* __restrict__ pb,
-                                                  const int* __restrict__ active, SolverDims dm,
-                                                  c64* __restrict__ part) {
+                                                  cx<R>* __restrict__ r, const int* __restrict__ active,
+                                                  SolverDims dm, c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   if (active[rhs]) {
@@ -379,8 +386,10 @@ __global__ void __launch_bounds__(256) k_qmr_init(const cx<R>* __restrict__ b, c
       v0[o + i] = z;
       pa[o + i] = z;
       pb[o + i] = z;
+      r[o + i] = bv;
       const c64 bd = up(bv);
       acc[0].x += abs2(bd);
+      acc[0].y += abs2(bd);
       acc[1] = acc[1] + bd * bd;
     }
   }
@@ -422,27 +431,55 @@ __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState*
   }
 }
 
-// Iteration n (after w~ = A vt_n).  pnorm_in: partials [|vt_n|^2, vt_n^T vt_n]
-// (dm.nblk blocks); pdot: vt_n^T w~ from the matrix-vector product (nblk_mv
-// blocks, stride 2).  vn = vt_n, vp = vt_{n-1} (overwritten by vt_{n+1}),
-// p1 = p_{n-2}, p2 = p_{n-3} (overwritten by p_{n-1}).
+// Iteration n (after w~ = A vt_n).  pnorm_in: partials [(|vt_n|^2, |r_{n-2}|^2),
+// vt_n^T vt_n] (dm.nblk blocks); pdot: vt_n^T w~ from the matrix-vector
+// product (nblk_mv blocks, stride 2).  vn = vt_n, vp = vt_{n-1} (overwritten
+// by vt_{n+1}), p1 = p_{n-2}, p2 = p_{n-3} (overwritten by p_{n-1}).
+//
+// Stopping uses the QMR residual itself, carried by the recurrence
+//   r_{n-1} = |s_{n-1}|^2 r_{n-2} + c_{n-1} tau_n vt_n / |vt_n|
+// (the residual is tau_n V_{n+1} Q^H e_{n+1} and the last column of Q^H
+// changes by one rotation per step), not the quasi-residual |tau_n|, which can
+// sit far below the residual when the Lanczos vectors are far from
+// orthogonal.  The norm of r_{n-2} arrives with this step's partials, when u
+// still holds u_{n-2}; a converged right-hand side stops here unchanged.
 template <typename R>
 __global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, const cx<R>* __restrict__ vn,
                                                   cx<R>* __restrict__ vp, const cx<R>* __restrict__ p1,
                                                   cx<R>* __restrict__ p2, cx<R>* __restrict__ u,
-                                                  const c64* __restrict__ pnorm_in, const c64* __restrict__ pdot,
-                                                  int nblk_mv, const QmrState* __restrict__ sin,
-                                                  QmrState* __restrict__ sout, int* __restrict__ active,
-                                                  SolverDims dm, c64* __restrict__ pnorm_out) {
+                                                  cx<R>* __restrict__ r, const c64* __restrict__ pnorm_in,
+                                                  const c64* __restrict__ pdot, int nblk_mv,
+                                                  const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
+                                                  int* __restrict__ active, SolverDims dm,
+                                                  c64* __restrict__ pnorm_out) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
   c64 rn[2], rd[2];
   reduce_all<2>(pnorm_in, dm.nblk, rhs, rn);
-  reduce_all<2>(pdot, nblk_mv, rhs, rd);
   QmrState s = sin[rhs];
   const int n = s.n;
+  // residual of the current iterate u_{n-2}
+  const double r2 = rn[0].y;
+  s.rnorm2 = r2;
+  if (r2 <= s.tol2 || !isfinite(r2)) {
+    if (r2 <= s.tol2) s.converged = 1;
+    else s.breakdown = 1;
+    s.iters = n >= 2 ? n - 2 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      s.ver += 1;
+      sout[rhs] = s;
+      active[rhs] = 0;
+    }
+    return;
+  }
+  if (r2 < 0.98 * s.best2) {
+    s.best2 = r2;
+    s.best_it = n;
+  } else if (n - s.best_it > kStallWindow && r2 < stall_level2<R>() * s.bnorm2) {
+    s.breakdown = 2;  // stagnated
+  }
+  reduce_all<2>(pdot, nblk_mv, rhs, rd);
   const double rho = sqrt(rn[0].x);
-  int stop = 0;
   // Lanczos scalars of step n
   c64 alpha = mk(0.0, 0.0), beta = mk(0.0, 0.0), delta = mk(0.0, 0.0);
   double sig = 0.0;
@@ -459,7 +496,8 @@ __global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, c
   if (n == 1) s.tau = mk(rho, 0.0);
   // column n-1 of the tridiagonal matrix: (beta_{n-1}, alpha_{n-1}, rho_n)
   const bool upd = n >= 2;
-  c64 ep = mk(0.0, 0.0), fpp = mk(0.0, 0.0), rinv = mk(0.0, 0.0), coef = mk(0.0, 0.0);
+  c64 ep = mk(0.0, 0.0), fpp = mk(0.0, 0.0), rinv = mk(0.0, 0.0), coef = mk(0.0, 0.0), rc = mk(0.0, 0.0);
+  double rs = 1.0;
   if (upd) {
     const double h = rho;
     const c64 f = s.beta_prev, g = s.alpha_prev;
@@ -484,6 +522,8 @@ __global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, c
       rinv = cdiv(mk(1.0, 0.0), rnn);
       coef = c * s.tau;
       s.tau = (-1.0) * (conjg(sn) * s.tau);
+      rs = abs2(sn);
+      rc = (c * sig) * s.tau;
     } else {
       s.breakdown = 1;
     }
@@ -492,19 +532,10 @@ __global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, c
     s.c1 = c;
     s.s1 = sn;
     s.iters = n - 1;
-    s.rnorm2 = abs2(s.tau);
-    if (s.rnorm2 <= s.tol2) {
-      s.converged = 1;
-    } else if (s.rnorm2 < 0.98 * s.best2) {
-      s.best2 = s.rnorm2;
-      s.best_it = s.iters;
-    } else if (s.iters - s.best_it > kStallWindow) {
-      s.breakdown = 2;  // stagnated
-    }
   }
   if (!(rho > 0.0)) s.converged = 1;  // vt_n = 0: the Krylov space is invariant
-  if (!isfinite(rho) || !isfinite(s.rnorm2)) s.breakdown = 1;
-  stop = s.converged || s.breakdown;
+  if (!isfinite(rho)) s.breakdown = 1;
+  const int stop = s.converged || s.breakdown;
   const double sigp = 1.0 / s.rho_prev;
   s.alpha_prev = alpha;
   s.beta_prev = beta;
@@ -516,23 +547,30 @@ __global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, c
     sout[rhs] = s;
     if (stop) active[rhs] = 0;
   }
-  const R sgp = (R)sigp, sg = (R)sig;
-  const cx<R> fppr = cvt<R>(fpp), epr = cvt<R>(ep), rir = cvt<R>(rinv), cf = cvt<R>(coef);
+  const R sgp = (R)sigp, sg = (R)sig, rsr = (R)rs;
+  const cx<R> fppr = cvt<R>(fpp), epr = cvt<R>(ep), rir = cvt<R>(rinv), cf = cvt<R>(coef), rcr = cvt<R>(rc);
   const cx<R> al = cvt<R>(alpha), bs = cvt<R>((double)sigp * beta);
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
   DDA_RANGE(dm, i) {
     const cx<R> vpi = vp[o + i];
+    const cx<R> vni = vn[o + i];
     if (upd) {
       const cx<R> pn = rir * (sgp * vpi - fppr * p1[o + i] - epr * p2[o + i]);
       p2[o + i] = pn;
       u[o + i] = u[o + i] + cf * pn;
     }
     if (!stop) {
-      const cx<R> t = sg * (w[o + i] - al * vn[o + i]) - bs * vpi;
+      cx<R> ri = r[o + i];
+      if (upd) {
+        ri = rsr * ri + rcr * vni;
+        r[o + i] = ri;
+      }
+      const cx<R> t = sg * (w[o + i] - al * vni) - bs * vpi;
       vp[o + i] = t;
       const c64 td = up(t);
       acc[0].x += abs2(td);
+      acc[0].y += abs2(up(ri));
       acc[1] = acc[1] + td * td;
     }
   }

@@ -119,7 +119,7 @@ def test_gradient_vs_difference_solve_fd_sphere128(lib):
         for q, n in enumerate(ch):
             for c in range(3):
                 U[3 * q + c, c, int(n)] = 1.0
-        Z, zinfo = t.solve(einc=U, S=[0.0] * U.shape[0], solver="qmr", precision="mixed", tol=1e-10,
+        Z, zinfo = t.solve(einc=U, S=[0.0] * U.shape[0], solver="bicgstab", precision="mixed", tol=1e-10,
                            inner_tol=1e-4)
         assert all(i["converged"] for i in zinfo)
         del U
