@@ -128,6 +128,32 @@ typedef struct {
 int dda_solve(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *khat, const double *ehat,
               const double *S, const void *einc_dev, void *p_dev, dda_solve_info *info, void *hip_stream);
 
+/* One target's share of a batch: the arguments dda_solve takes for it. */
+typedef struct {
+  dda_target *target;       /* distinct per item, opened on the batch's library */
+  int nrhs;                 /* >= 1                                            */
+  const double *khat;       /* host [3*nrhs] or NULL (then einc_dev is used)    */
+  const double *ehat;       /* host [6*nrhs] (re, im) or NULL                   */
+  const double *S;          /* host [nrhs] or NULL, as for dda_solve            */
+  const void *einc_dev;     /* [nrhs][3][N_d] complex128 or NULL                */
+  void *p_dev;              /* out [nrhs][3][N_d] complex128                    */
+  dda_solve_info *info;     /* host out [nrhs] (nullable)                       */
+} dda_batch_item;
+
+/* Solve many targets (uneven lattices and right-hand-side counts, e.g. an
+ * ensemble of aggregates or orientations) as one call: the items are ordered
+ * longest first (FFT grid volume x nrhs) and drawn from a shared queue by
+ * nworkers host workers (<= 0: 4, the HIP hardware queues per process), each
+ * enqueueing on its own library-owned stream of default priority, so that
+ * the solves of small targets overlap on the device.  Work starts after what
+ * is already enqueued on hip_stream; the call returns when every item is
+ * solved.  Each item behaves as dda_solve on it.  DDA_EINVAL for a repeated
+ * target or an item of another library; DDA_ENOTCONV if some right-hand side
+ * missed tol (all items are still solved); any other error stops the queue and
+ * is returned with the failing item's message. */
+int dda_batch_solve(dda_lib *lib, const dda_solve_opts *opts, int nitems, const dda_batch_item *items,
+                    int nworkers, void *hip_stream);
+
 /* Incident plane waves at the dipoles, E[r][c][n] = ehat_r[c] exp(i kd khat_r . r_n)
  * (Sec. 1; |E0| = 1): khat[3*nrhs] real unit vectors, ehat[6*nrhs] (re, im).
  * e_dev: out [nrhs][3][N_d] complex128. */

@@ -10,6 +10,10 @@
 #include <algorithm>
 #include <fstream>
 #include <map>
+#include <mutex>
+#include <numeric>
+#include <thread>
+#include <atomic>
 #include <sstream>
 #include <cmath>
 #include <cstdarg>
@@ -149,6 +153,8 @@ struct dda_lib {
   int device = 0;
   std::string tune_path;
   std::map<std::string, int> tuned;  // schedule per (lattice, padding, nrhs, precision)
+  std::mutex tune_mu;                // guards `tuned` and the tune file (batch workers)
+  std::vector<hipStream_t> workers;  // streams of dda_batch_solve's workers
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (pass, start, stop)
@@ -387,6 +393,7 @@ void dda_close(dda_lib* lib) {
     lib->ev_pool.push_back(pe.second.second);
   }
   for (hipEvent_t e : lib->ev_pool) (void)hipEventDestroy(e);
+  for (hipStream_t w : lib->workers) (void)hipStreamDestroy(w);
   delete lib;
 }
 
@@ -827,8 +834,8 @@ template <typename R, int NN, int D>
 static int launch_xy_fwd(dda_target* t, int nrhs, hipStream_t st, const cx<R>* x, cx<R>* G2, const cx<R>* a0,
                          const cx<R>* a1, const double* dS, const int* act, const VecArgs& va) {
   const size_t lds = xy_fwd_lds<R, NN, D>(t->K);
-  static bool attr = false;
-  if (!attr) {
+  static std::atomic<bool> attr{false};  // set once per process (idempotent)
+  if (!attr.load()) {
     HIPCHK(hipFuncSetAttribute((const void*)k_xy_fwd<R, NN, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kXYLds));
     attr = true;
@@ -846,8 +853,8 @@ static int launch_xy_inv(dda_target* t, int nrhs, hipStream_t st, const cx<R>* G
                          const cx<R>* a0, const cx<R>* a1, const double* dS, const int* act, const VecArgs& va,
                          DotArgs dot) {
   const size_t lds = xy_inv_lds<R, NN, D>(t->K);
-  static bool attr = false;
-  if (!attr) {
+  static std::atomic<bool> attr{false};  // set once per process (idempotent)
+  if (!attr.load()) {
     HIPCHK(hipFuncSetAttribute((const void*)k_xy_inv<R, NN, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kXYLds));
     attr = true;
@@ -1136,7 +1143,9 @@ template <typename R>
 static int schedule_of(const dda_target* t, int nrhs) {
   if (t->sched_override >= 0) return t->sched_override;
   if (t->forced_sched >= 0) return t->forced_sched;
-  auto it = t->lib->tuned.find(tune_key<R>(t, nrhs));
+  const std::string key = tune_key<R>(t, nrhs);
+  std::lock_guard<std::mutex> g(t->lib->tune_mu);
+  auto it = t->lib->tuned.find(key);
   if (it != t->lib->tuned.end()) return it->second;
   // untuned: the strided five-pass schedule
   return 0;
@@ -1147,14 +1156,17 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
                     hipStream_t st) {
   if (t->forced_sched >= 0) return DDA_OK;
   const std::string key = tune_key<R>(t, nrhs);
-  if (t->lib->tuned.count(key)) return DDA_OK;
+  {
+    std::lock_guard<std::mutex> g(t->lib->tune_mu);
+    if (t->lib->tuned.count(key)) return DDA_OK;
+  }
   std::vector<int> cand = {0};
   if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {
     const bool prof = t->lib->prof;
-    t->lib->prof = false;
+    if (prof) t->lib->prof = false;  // (profiling runs single-threaded)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1178,9 +1190,11 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
     t->matvecs -= 5 * (int)cand.size();
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    t->lib->prof = prof;
+    if (prof) t->lib->prof = prof;
     CHK(rc);
   }
+  std::lock_guard<std::mutex> g(t->lib->tune_mu);
+  if (t->lib->tuned.count(key)) return DDA_OK;  // another worker tuned it meanwhile
   t->lib->tuned[key] = best;
   if (!t->lib->tune_path.empty()) {
     std::ofstream f(t->lib->tune_path, std::ios::app);
@@ -1614,15 +1628,13 @@ static int check_opts(const dda_solve_opts* opts, const char* who) {
   return DDA_OK;
 }
 
-extern "C" int dda_solve(dda_target* t, const dda_solve_opts* opts, int nrhs, const double* khat, const double* ehat,
-                         const double* S, const void* einc_dev, void* p_dev, dda_solve_info* info, void* hip_stream) {
+static int solve_one(dda_target* t, const dda_solve_opts* opts, int nrhs, const double* khat, const double* ehat,
+                     const double* S, const void* einc_dev, void* p_dev, dda_solve_info* info, hipStream_t st) {
   CHK(check_ready(t, "dda_solve"));
-  CHK(check_opts(opts, "dda_solve"));
   if (nrhs < 1) return fail(DDA_EINVAL, "dda_solve: nrhs = %d", nrhs);
   if (!p_dev) return fail(DDA_EINVAL, "dda_solve: p_dev is NULL");
   if (!einc_dev && (!khat || !ehat)) return fail(DDA_EINVAL, "dda_solve: need einc_dev or khat and ehat");
   HIPCHK(hipSetDevice(t->lib->device));
-  hipStream_t st = (hipStream_t)hip_stream;
   CHK(ensure_scratch(t, nrhs));
   CHK(ensure_outer(t, nrhs));
   std::vector<double> hs;
@@ -1640,6 +1652,92 @@ extern "C" int dda_solve(dda_target* t, const dda_solve_opts* opts, int nrhs, co
   }
   HIPCHK(hipStreamSynchronize(st));
   return solve_core(t, *opts, nrhs, E, (c64*)p_dev, info, st);
+}
+
+extern "C" int dda_solve(dda_target* t, const dda_solve_opts* opts, int nrhs, const double* khat, const double* ehat,
+                         const double* S, const void* einc_dev, void* p_dev, dda_solve_info* info, void* hip_stream) {
+  CHK(check_opts(opts, "dda_solve"));
+  return solve_one(t, opts, nrhs, khat, ehat, S, einc_dev, p_dev, info, (hipStream_t)hip_stream);
+}
+
+// Batch of targets: a longest-first queue drained by host workers, one HIP
+// stream each.  Targets own all their workspaces, graphs and solver state, so
+// workers share only the library's tuning table (locked).
+extern "C" int dda_batch_solve(dda_lib* lib, const dda_solve_opts* opts, int nitems, const dda_batch_item* items,
+                               int nworkers, void* hip_stream) {
+  if (!lib) return fail(DDA_EINVAL, "dda_batch_solve: lib is NULL");
+  CHK(check_opts(opts, "dda_batch_solve"));
+  if (nitems < 0 || (nitems > 0 && !items)) return fail(DDA_EINVAL, "dda_batch_solve: %d items", nitems);
+  if (nitems == 0) return DDA_OK;
+  for (int i = 0; i < nitems; ++i) {
+    const dda_target* t = items[i].target;
+    if (!t) return fail(DDA_EINVAL, "dda_batch_solve: item %d has no target", i);
+    if (t->lib != lib) return fail(DDA_EINVAL, "dda_batch_solve: item %d belongs to another library", i);
+    for (int j = 0; j < i; ++j)
+      if (items[j].target == t) return fail(DDA_EINVAL, "dda_batch_solve: items %d and %d share a target", j, i);
+    if (items[i].nrhs < 1) return fail(DDA_EINVAL, "dda_batch_solve: item %d nrhs = %d", i, items[i].nrhs);
+  }
+  std::vector<int> order(nitems);
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](int i) {
+    const dda_target* t = items[i].target;
+    return (double)t->Kpp * t->Jpp * t->Ppp * items[i].nrhs;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  int nw = nworkers > 0 ? nworkers : 4;
+  nw = std::min(nw, nitems);
+  if (lib->prof) nw = 1;  // the pass timers are not shared between threads
+  HIPCHK(hipSetDevice(lib->device));
+  while ((int)lib->workers.size() < nw) {
+    hipStream_t w = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+    lib->workers.push_back(w);
+  }
+  hipEvent_t ready = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ready, (hipStream_t)hip_stream));
+  std::atomic<int> next{0};
+  std::atomic<bool> stop{false};
+  std::atomic<bool> notconv{false};
+  std::mutex emu;
+  int err_code = DDA_OK;
+  std::string err_msg;
+  auto worker = [&](int w) {
+    hipStream_t st = lib->workers[w];
+    int rc = hipSetDevice(lib->device) == hipSuccess && hipStreamWaitEvent(st, ready, 0) == hipSuccess
+                 ? DDA_OK
+                 : fail(DDA_EDEVICE, "dda_batch_solve: worker %d could not start", w);
+    while (rc == DDA_OK && !stop.load()) {
+      const int k = next.fetch_add(1);
+      if (k >= nitems) break;
+      const dda_batch_item& it = items[order[k]];
+      rc = solve_one(it.target, opts, it.nrhs, it.khat, it.ehat, it.S, it.einc_dev, it.p_dev, it.info, st);
+      if (rc == DDA_ENOTCONV) {
+        notconv = true;
+        rc = DDA_OK;
+      } else if (rc != DDA_OK) {
+        char buf[64];
+        snprintf(buf, sizeof buf, " (batch item %d)", order[k]);
+        g_err += buf;
+      }
+    }
+    if (rc != DDA_OK) {
+      stop = true;
+      std::lock_guard<std::mutex> g(emu);
+      if (err_code == DDA_OK) {
+        err_code = rc;
+        err_msg = g_err;
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(worker, w);
+  worker(0);
+  for (auto& th : pool) th.join();
+  (void)hipEventDestroy(ready);
+  if (err_code != DDA_OK) return fail(err_code, "%s", err_msg.c_str());
+  if (notconv) return fail(DDA_ENOTCONV, "dda_batch_solve: a right-hand side missed tol %g", opts->tol);
+  return DDA_OK;
 }
 
 extern "C" int dda_incident_field(dda_target* t, int nrhs, const double* khat, const double* ehat, void* e_dev,

@@ -52,9 +52,16 @@ class dda_solve_info(ctypes.Structure):
                 ("matvecs", ctypes.c_int), ("rel_residual", ctypes.c_double)]
 
 
+class dda_batch_item(ctypes.Structure):
+    _fields_ = [("target", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("khat", ctypes.c_void_p),
+                ("ehat", ctypes.c_void_p), ("S", ctypes.c_void_p), ("einc_dev", ctypes.c_void_p),
+                ("p_dev", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
 # Every symbol the header declares (tests check that the library exports them).
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
            "dda_set_permittivity", "dda_set_polarizability", "dda_build_spectrum", "dda_matvec", "dda_solve",
+           "dda_batch_solve",
            "dda_incident_field", "dda_cross_sections", "dda_grad_cabs_eps", "dda_target_set_option",
            "dda_target_info",
            "dda_get_spectrum", "dda_profile_enable", "dda_profile_read", "dda_profile_reset",
@@ -87,6 +94,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_build_spectrum": (i, [vp, vp]),
         "dda_matvec": (i, [vp, i, i, vp, i, vp, vp, vp]),
         "dda_solve": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp, vp, vp, vp]),
+        "dda_batch_solve": (i, [vp, P(dda_solve_opts), i, vp, i, vp]),
         "dda_incident_field": (i, [vp, i, vp, vp, vp, vp]),
         "dda_cross_sections": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
         "dda_grad_cabs_eps": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp]),
@@ -170,6 +178,44 @@ class Library:
         _check(load().dda_profile_read(self.h, _np_ptr(ms), _np_ptr(n)))
         keys = [(p, "fp64") for p in PASS_NAMES] + [(p, "fp32") for p in PASS_NAMES]
         return {k: (float(a), int(b)) for k, a, b in zip(keys, ms, n)}
+
+    def batch_solve(self, items, nworkers: int = 0, raise_on_fail: bool = True, **kw):
+        """Solve several targets in one dda_batch_solve call.
+
+        items: list of dicts with key ``target`` and either ``khat``/``ehat``
+        (optionally ``S``) or ``einc`` (a device tensor, with ``S``).
+        Returns a list of (P, infos) in the order of ``items``."""
+        opts = Target.make_opts(**kw)
+        arr = (dda_batch_item * len(items))()
+        keep, out = [], []
+        for k, it in enumerate(items):
+            t = it["target"]
+            kh = eh = None
+            if it.get("einc") is None:
+                kh = np.ascontiguousarray(np.asarray(it["khat"], np.float64).reshape(-1, 3))
+                eh = np.ascontiguousarray(np.asarray(it["ehat"], np.complex128).reshape(-1, 3))
+                nrhs = kh.shape[0]
+            else:
+                nrhs = it["einc"].shape[0]
+            Sa, Sp = _opt_np(it.get("S"), np.float64, nrhs)
+            P = torch.empty((nrhs, 3, t.nd), dtype=torch.complex128, device=t.dev)
+            info = (dda_solve_info * nrhs)()
+            keep += [kh, eh, Sa, info]
+            arr[k].target = t.h.value
+            arr[k].nrhs = nrhs
+            arr[k].khat = kh.ctypes.data if kh is not None else None
+            arr[k].ehat = eh.ctypes.data if eh is not None else None
+            arr[k].S = Sa.ctypes.data if Sa is not None else None
+            arr[k].einc_dev = _dptr(it["einc"]).value if it.get("einc") is not None else None
+            arr[k].p_dev = P.data_ptr()
+            arr[k].info = ctypes.addressof(info)
+            out.append((P, info))
+        rc = load().dda_batch_solve(self.h, ctypes.byref(opts), len(items), ctypes.cast(arr, ctypes.c_void_p),
+                                    int(nworkers), _stream())
+        if rc != DDA_ENOTCONV or raise_on_fail:
+            _check(rc)
+        return [(P, [dict(converged=i.converged, iterations=i.iterations, outer_iterations=i.outer_iterations,
+                          matvecs=i.matvecs, rel_residual=i.rel_residual) for i in info]) for P, info in out]
 
     def __del__(self):
         try:

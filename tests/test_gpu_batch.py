@@ -1,0 +1,87 @@
+"""Multi-target batch solve (dda_batch_solve): uneven targets drained from one
+queue by several workers give the same answers as solving them one by one,
+and the smallest ones match the oracle's dense LU solution."""
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_0908_0863_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0908_0863_amd import dda
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return dda.Library(0)
+
+
+def _rand_occ(shape, seed, frac=0.7):
+    rng = np.random.default_rng(seed)
+    occ = (rng.random(shape) < frac).astype(np.uint8)
+    occ.flat[0] = 1
+    return occ
+
+
+def _targets(lib):
+    """Six targets of uneven lattices, materials and right-hand-side counts."""
+    from paper_0908_0863_amd import dda
+    agg, _ = inputs.aggregate(np.random.default_rng(4), 12, min_lattice=16)
+    specs = [
+        (_rand_occ((7, 3, 5), 1), 0.5, 2.4 + 0.3j, 1),
+        (inputs.sphere(16), 0.3, 1.77 + 0.02j, 2),
+        (agg, 2 * np.pi / 25, (1.5 + 0.1j) ** 2, 2),
+        (_rand_occ((9, 10, 12), 2), 0.4, 2.0 + 0.5j, 3),
+        (_rand_occ((6, 20, 24), 3, 0.5), 0.35, 1.9 + 0.05j, 1),
+        (inputs.sphere(10), 0.3124, (1.6 + 0.05j) ** 2, 2),
+    ]
+    out = []
+    rng = np.random.default_rng(7)
+    for occ, kd, eps, nrhs in specs:
+        P, J, K = occ.shape
+        t = dda.Target(lib, K, J, P, kd)
+        nd = t.set_occupancy(occ)
+        t.set_permittivity(np.full(nd, eps), "ldr")
+        t.build_spectrum()
+        kh, e1, e2 = inputs.directions(int(rng.integers(1 << 30)), nrhs)
+        out.append(dict(target=t, occ=occ, kd=kd, eps=eps, khat=kh, ehat=e1.astype(np.complex128)))
+    return out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("precision,use_graph", [("fp64", False), ("mixed", True)])
+def test_batch_matches_individual_solves(lib, precision, use_graph):
+    items = _targets(lib)
+    kw = dict(solver="qmr", precision=precision, tol=1e-10, inner_tol=1e-4, use_graph=use_graph, check_every=8)
+    single = [it["target"].solve(khat=it["khat"], ehat=it["ehat"], **kw) for it in items]
+    batch = lib.batch_solve([dict(target=it["target"], khat=it["khat"], ehat=it["ehat"]) for it in items],
+                            nworkers=3, **kw)
+    for it, (Ps, infs), (Pb, infb) in zip(items, single, batch):
+        assert all(i["converged"] for i in infb)
+        assert _rel(Pb.cpu().numpy(), Ps.cpu().numpy()) < 1e-8
+    # the smallest target against the dense LU solution
+    it = items[0]
+    sites = ora.sites_of(it["occ"])
+    nd = sites.shape[0]
+    Pb = batch[0][0].cpu().numpy()
+    for r in range(Pb.shape[0]):
+        S = ora.ldr_S(it["khat"][r], it["ehat"][r])
+        ainv = ora.alpha_inv(np.full(nd, it["eps"]), it["kd"], "ldr", S)
+        E = ora.einc(sites, it["kd"], it["khat"][r], it["ehat"][r])
+        assert _rel(Pb[r], ora.solve_dense(sites, it["kd"], ainv, E)) < 1e-8
+
+
+def test_batch_rejects_repeated_target(lib):
+    from paper_0908_0863_amd import dda
+    items = _targets(lib)[:2]
+    t = items[0]["target"]
+    with pytest.raises(dda.DDAError) as e:
+        lib.batch_solve([dict(target=t, khat=items[0]["khat"], ehat=items[0]["ehat"])] * 2, tol=1e-6)
+    assert e.value.code == dda.DDA_EINVAL
