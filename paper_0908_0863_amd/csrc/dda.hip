@@ -1247,7 +1247,7 @@ struct InnerResult {
 };
 
 static int nblocks_for(long n3) {
-  long b = (n3 + 4L * kRedThreads - 1) / (4L * kRedThreads);
+  long b = (n3 + 2L * kRedThreads - 1) / (2L * kRedThreads);
   return (int)std::max(1L, std::min(b, 256L));
 }
 
@@ -1312,15 +1312,15 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   c64* M1 = M0 + (size_t)nrhs * nblk_mv * 2;
   if (bcg) {
     BcgState* S0 = t->state.as<BcgState>();
-    hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(256), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
+    hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
                        R3);
-    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(256), 0, st, R3, dm.nblk, S0, act, tolv);
+    hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
   } else {
     QmrState* S0 = t->state.as<QmrState>();
     // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring, slot 7 = QMR residual
-    hipLaunchKernelGGL((k_qmr_init<R>), vg, dim3(256), 0, st, b, u, slot(2), slot(3), slot(5), slot(6), slot(7),
+    hipLaunchKernelGGL((k_qmr_init<R>), vg, dim3(kRedThreads), 0, st, b, u, slot(2), slot(3), slot(5), slot(6), slot(7),
                        act, dm, R1);
-    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(256), 0, st, R1, dm.nblk, S0, act, tolv);
+    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(kRedThreads), 0, st, R1, dm.nblk, S0, act, tolv);
   }
   LAUNCHCHK();
 
@@ -1330,18 +1330,18 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       BcgState* SA = t->state.as<BcgState>() + (par ? nrhs : 0);
       BcgState* SB = t->state.as<BcgState>() + (par ? 0 : nrhs);
       cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
-      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(256), 0, s, r, p, v, R3, SA, SB, act, dm);
+      hipLaunchKernelGGL((k_bcg_p<R>), vg, dim3(kRedThreads), 0, s, r, p, v, R3, SA, SB, act, dm);
       DotArgs d1;
       d1.mode = DOT_HA;
       d1.a = rhat;
       d1.part = M0;
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, s, d1));
-      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(256), 0, s, r, v, M0, nblk_mv, SB, SA, act, dm, R1);
+      hipLaunchKernelGGL((k_bcg_s<R>), vg, dim3(kRedThreads), 0, s, r, v, M0, nblk_mv, SB, SA, act, dm, R1);
       DotArgs d2;
       d2.mode = DOT_TS;
       d2.part = M1;
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s, d2));
-      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(256), 0, s, u, r, p, tt, rhat, R1, M1, nblk_mv, SA, SB, act, dm,
+      hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(kRedThreads), 0, s, u, r, p, tt, rhat, R1, M1, nblk_mv, SA, SB, act, dm,
                          R3);
     } else {
       QmrState* SA = t->state.as<QmrState>() + (par ? nrhs : 0);
@@ -1358,7 +1358,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       d.part = M0;
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, vn, w, act, s, d));
       // vt_{n+1} lands in vp's slot and p_{n-1} in p2's: roles swap next time
-      hipLaunchKernelGGL((k_qmr_step<R>), vg, dim3(256), 0, s, w, vn, vp, p1, p2, u, slot(7), pn_in, M0, nblk_mv, SA,
+      hipLaunchKernelGGL((k_qmr_step<R>), vg, dim3(kRedThreads), 0, s, w, vn, vp, p1, p2, u, slot(7), pn_in, M0, nblk_mv, SA,
                          SB, act, dm, pn_out);
     }
     LAUNCHCHK();
@@ -1460,7 +1460,7 @@ static int true_residual(dda_target* t, int nrhs, const c64* E, const c64* Pv, c
   dm.n3 = 3 * t->nd;
   dm.nblk = nblocks_for(dm.n3);
   CHK(t->part.ensure((size_t)nrhs * dm.nblk * 2 * sizeof(c64)));
-  hipLaunchKernelGGL(k_residual, dim3(dm.nblk, nrhs), dim3(256), 0, st, E, y, r, dm, t->part.as<c64>());
+  hipLaunchKernelGGL(k_residual, dim3(dm.nblk, nrhs), dim3(kRedThreads), 0, st, E, y, r, dm, t->part.as<c64>());
   LAUNCHCHK();
   std::vector<c64> hp((size_t)nrhs * dm.nblk * 2);
   HIPCHK(hipMemcpyAsync(hp.data(), t->part.p, hp.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
@@ -1772,7 +1772,7 @@ extern "C" int dda_cross_sections(dda_target* t, int nrhs, const double* S, cons
   dm.n3 = 3 * t->nd;
   dm.nblk = nblocks_for(dm.n3);
   CHK(t->part.ensure((size_t)nrhs * dm.nblk * 2 * sizeof(c64)));
-  hipLaunchKernelGGL(k_cross_sums, dim3(dm.nblk, nrhs), dim3(256), 0, st, (const c64*)einc_dev, (const c64*)p_dev,
+  hipLaunchKernelGGL(k_cross_sums, dim3(dm.nblk, nrhs), dim3(kRedThreads), 0, st, (const c64*)einc_dev, (const c64*)p_dev,
                      t->p64.a0.as<c64>(), t->has_a1 ? t->p64.a1.as<c64>() : nullptr, t->S.as<double>(), (long)t->nd,
                      t->kd, dm, t->part.as<c64>());
   LAUNCHCHK();

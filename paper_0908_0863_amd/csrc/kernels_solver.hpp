@@ -11,7 +11,7 @@
 
 namespace dda {
 
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;
 
 // Sum of ND complex values over a 256-thread block, in a fixed order.
 // Result valid in thread 0.
@@ -108,7 +108,7 @@ __device__ __forceinline__ bool tiny(c64 a, double scale) { return !(abs2(a) > 1
 
 // partials of a^H b (ND = 1) or of a^H b and a^H a (ND = 2)
 template <typename R, int ND>
-__global__ void __launch_bounds__(256) k_dots(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
+__global__ void __launch_bounds__(kRedThreads) k_dots(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
                                               const int* __restrict__ active, SolverDims dm,
                                               c64* __restrict__ part) {
   const int rhs = blockIdx.y;
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_dots(const cx<R>* __restrict__ a, const
 
 // partials of v^T w (bilinear)
 template <typename R>
-__global__ void __launch_bounds__(256) k_bil_dot(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
+__global__ void __launch_bounds__(kRedThreads) k_bil_dot(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
                                                  const int* __restrict__ active, SolverDims dm,
                                                  c64* __restrict__ part) {
   const int rhs = blockIdx.y;
@@ -156,7 +156,7 @@ struct BcgState {
 
 // r = b, rhat = b, p = v = u = 0; partials |b|^2 (slot 0) and rhat^H r = |b|^2 (slot 1)
 template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
+__global__ void __launch_bounds__(kRedThreads) k_bcg_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
                                                   cx<R>* __restrict__ rhat, cx<R>* __restrict__ p,
                                                   cx<R>* __restrict__ v, cx<R>* __restrict__ u,
                                                   const int* __restrict__ active, SolverDims dm,
@@ -216,7 +216,7 @@ __global__ void k_bcg_fin_init(const c64* __restrict__ part, int nblk, BcgState*
 // decide convergence / stagnation / breakdown, then beta and
 // p = r + beta (p - omega v).
 template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R>* __restrict__ p,
+__global__ void __launch_bounds__(kRedThreads) k_bcg_p(const cx<R>* __restrict__ r, cx<R>* __restrict__ p,
                                                const cx<R>* __restrict__ v, const c64* __restrict__ pupd,
                                                const BcgState* __restrict__ sin, BcgState* __restrict__ sout,
                                                int* __restrict__ active, SolverDims dm) {
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) k_bcg_p(const cx<R>* __restrict__ r, cx<R
 
 // alpha = rho / (rhat^H v);  s = r - alpha v (stored in r); partials |s|^2
 template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_s(cx<R>* __restrict__ r, const cx<R>* __restrict__ v,
+__global__ void __launch_bounds__(kRedThreads) k_bcg_s(cx<R>* __restrict__ r, const cx<R>* __restrict__ v,
                                                const c64* __restrict__ pdot, int nblk_mv,
                                                const BcgState* __restrict__ sin, BcgState* __restrict__ sout,
                                                int* __restrict__ active, SolverDims dm, c64* __restrict__ part) {
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) k_bcg_s(cx<R>* __restrict__ r, const cx<R
 // u += alpha p + omega s;  r = s - omega t;  partials [|r|^2, rhat^H r]
 // (if |s| already met the tolerance: u += alpha p and stop next iteration).
 template <typename R>
-__global__ void __launch_bounds__(256) k_bcg_update(cx<R>* __restrict__ u, cx<R>* __restrict__ r,
+__global__ void __launch_bounds__(kRedThreads) k_bcg_update(cx<R>* __restrict__ u, cx<R>* __restrict__ r,
                                                     const cx<R>* __restrict__ p, const cx<R>* __restrict__ t,
                                                     const cx<R>* __restrict__ rhat, const c64* __restrict__ ps,
                                                     const c64* __restrict__ pts, int nblk_mv,
@@ -369,7 +369,7 @@ struct QmrState {
 
 // u = 0; vt_1 = b; vt_0 = 0; p ring = 0; r = b; partials [(|b|^2, |r|^2), b^T b]
 template <typename R>
-__global__ void __launch_bounds__(256) k_qmr_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ u,
+__global__ void __launch_bounds__(kRedThreads) k_qmr_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ u,
                                                   cx<R>* __restrict__ v1, cx<R>* __restrict__ v0,
                                                   cx<R>* __restrict__ pa, cx<R>* __restrict__ pb,
                                                   cx<R>* __restrict__ r, const int* __restrict__ active,
@@ -444,7 +444,7 @@ __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState*
 // orthogonal.  The norm of r_{n-2} arrives with this step's partials, when u
 // still holds u_{n-2}; a converged right-hand side stops here unchanged.
 template <typename R>
-__global__ void __launch_bounds__(256) k_qmr_step(const cx<R>* __restrict__ w, const cx<R>* __restrict__ vn,
+__global__ void __launch_bounds__(kRedThreads) k_qmr_step(const cx<R>* __restrict__ w, const cx<R>* __restrict__ vn,
                                                   cx<R>* __restrict__ vp, const cx<R>* __restrict__ p1,
                                                   cx<R>* __restrict__ p2, cx<R>* __restrict__ u,
                                                   cx<R>* __restrict__ r, const c64* __restrict__ pnorm_in,
@@ -648,7 +648,7 @@ __global__ void k_accumulate(c64* __restrict__ P, const cx<R>* __restrict__ d, c
 }
 
 // r = E - y; partials |r|^2 and |E|^2
-__global__ void __launch_bounds__(256) k_residual(const c64* __restrict__ E, const c64* __restrict__ y,
+__global__ void __launch_bounds__(kRedThreads) k_residual(const c64* __restrict__ E, const c64* __restrict__ y,
                                                   c64* __restrict__ r, SolverDims dm, c64* __restrict__ part) {
   const int rhs = blockIdx.y;
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
@@ -670,7 +670,7 @@ __global__ void __launch_bounds__(256) k_residual(const c64* __restrict__ E, con
 // Sums for the cross sections (Draine 1988, |E0| = 1):
 //   [0] sum Im(E^* . P)              -> C_ext = 4 pi k [0]
 //   [1] sum |P|^2 (-Im a_n - 2k^3/3)  -> C_abs = 4 pi k [1]
-__global__ void __launch_bounds__(256) k_cross_sums(const c64* __restrict__ E, const c64* __restrict__ P,
+__global__ void __launch_bounds__(kRedThreads) k_cross_sums(const c64* __restrict__ E, const c64* __restrict__ P,
                                                     const c64* __restrict__ a0, const c64* __restrict__ a1,
                                                     const double* __restrict__ S, long nd, double k,
                                                     SolverDims dm, c64* __restrict__ part) {
