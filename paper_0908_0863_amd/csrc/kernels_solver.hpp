@@ -106,41 +106,6 @@ __device__ __forceinline__ void reduce_all(const c64* __restrict__ part, int nbl
 
 __device__ __forceinline__ bool tiny(c64 a, double scale) { return !(abs2(a) > 1e-300 * scale); }
 
-// partials of a^H b (ND = 1) or of a^H b and a^H a (ND = 2)
-template <typename R, int ND>
-__global__ void __launch_bounds__(kRedThreads) k_dots(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
-                                              const int* __restrict__ active, SolverDims dm,
-                                              c64* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  c64 acc[ND];
-#pragma unroll
-  for (int q = 0; q < ND; ++q) acc[q] = mk(0.0, 0.0);
-  const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) {
-    const c64 av = up(a[o + i]);
-    acc[0] = acc[0] + cmulc(av, up(b[o + i]));
-    if (ND > 1) acc[1].x += abs2(av);
-  }
-  block_sum<ND>(acc);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < ND; ++q) part[((long)rhs * dm.nblk + blockIdx.x) * ND + q] = acc[q];
-}
-
-// partials of v^T w (bilinear)
-template <typename R>
-__global__ void __launch_bounds__(kRedThreads) k_bil_dot(const cx<R>* __restrict__ a, const cx<R>* __restrict__ b,
-                                                 const int* __restrict__ active, SolverDims dm,
-                                                 c64* __restrict__ part) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  c64 acc[1] = {mk(0.0, 0.0)};
-  const long o = (long)rhs * dm.n3;
-  DDA_RANGE(dm, i) { acc[0] = acc[0] + up(a[o + i]) * up(b[o + i]); }
-  block_sum<1>(acc);
-  if (threadIdx.x == 0) part[(long)rhs * dm.nblk + blockIdx.x] = acc[0];
-}
-
 // ============================================================================
 // BiCGSTAB (van der Vorst 1992), complex, Hermitian inner products
 //   p = r + beta (p - omega v);  v = A p;  alpha = rho / rhat^H v;  s = r - alpha v;
