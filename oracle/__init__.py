@@ -325,6 +325,56 @@ def c_sca_double_sum(sites, k, P) -> float:
     return float(_lib().ora_csca_double_sum(nd, _p(sites), float(k), _p(P)))
 
 
+def far_field(sites, k, P, dirs) -> np.ndarray:
+    """Far-field amplitude of the dipole array, F(n) = k^2 (I - n n) sum_m
+    e^{-i k n . r_m} P_m, so that the scattered field is e^{ikr}/r F(n) as
+    r -> infinity (Gaussian units, |E0| = 1; Draine 1988).  dirs [ndir][3]
+    unit vectors; P [3][N_d].  Returns [ndir][3] complex."""
+    s = np.asarray(sites, dtype=np.float64)
+    n = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    P = np.asarray(P, dtype=np.complex128).reshape(3, -1)
+    phase = np.exp(-1j * k * (n @ s.T))                 # [ndir][N_d]
+    A = phase @ P.T                                      # [ndir][3]
+    return k * k * (A - n * np.sum(n * A, axis=1, keepdims=True))
+
+
+def amplitude_matrix_z(Fx, Fy, theta, phi, k) -> np.ndarray:
+    """Amplitude scattering matrix (S1, S2, S3, S4) of Bohren & Huffman (Sec. 3.2)
+    for incidence along +z, from the far fields Fx, Fy [ndir][3] of the solves
+    with polarisation x and y.  Basis: e_par,i = cos(phi) x + sin(phi) y,
+    e_perp,i = sin(phi) x - cos(phi) y, e_par,s = theta-hat, e_perp,s = -phi-hat;
+    [E_par,s, E_perp,s] = e^{ikr}/(-ikr) [[S2, S3], [S4, S1]] [E_par,i, E_perp,i]."""
+    th = np.asarray(theta, np.float64)[:, None]
+    ph = np.asarray(phi, np.float64)[:, None]
+    that = np.concatenate([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)], axis=1)
+    phat = np.concatenate([-np.sin(ph), np.cos(ph), np.zeros_like(ph)], axis=1)
+    Fpar = np.cos(ph) * Fx + np.sin(ph) * Fy          # response to unit E_par,i
+    Fperp = np.sin(ph) * Fx - np.cos(ph) * Fy         # response to unit E_perp,i
+    c = -1j * k
+    S2 = c * np.sum(that * Fpar, axis=1)
+    S3 = c * np.sum(that * Fperp, axis=1)
+    S4 = c * np.sum(-phat * Fpar, axis=1)
+    S1 = c * np.sum(-phat * Fperp, axis=1)
+    return np.stack([S1, S2, S3, S4], axis=1)
+
+
+def mueller_from_amplitude(S) -> np.ndarray:
+    """4x4 Mueller matrix from (S1, S2, S3, S4) by its definition: the Stokes
+    vector (I, Q, U, V) of a field (E_par, E_perp) is A (E kron E^*) with
+    A = [[1,0,0,1],[1,0,0,-1],[0,1,1,0],[0,i,-i,0]] (Bohren & Huffman Sec. 2.11),
+    the field maps by the Jones matrix J = [[S2, S3], [S4, S1]], so
+    M = A (J kron J^*) A^{-1}.  Returns [ndir][4][4] real."""
+    S = np.asarray(S, np.complex128).reshape(-1, 4)
+    A = np.array([[1, 0, 0, 1], [1, 0, 0, -1], [0, 1, 1, 0], [0, 1j, -1j, 0]], dtype=np.complex128)
+    Ai = np.linalg.inv(A)
+    out = np.empty((S.shape[0], 4, 4))
+    for d in range(S.shape[0]):
+        Jm = np.array([[S[d, 1], S[d, 2]], [S[d, 3], S[d, 0]]])
+        M = A @ np.kron(Jm, np.conj(Jm)) @ Ai
+        out[d] = np.real(M)
+    return out
+
+
 def a_eff(nd: int) -> float:
     """Radius of the sphere of equal volume (Sec. 5), in units of d."""
     return (3.0 * nd / (4.0 * math.pi)) ** (1.0 / 3.0)

@@ -289,3 +289,73 @@ def test_gradient_adjoint_matches_exact_finite_differences():
     brute = (vals[0] - vals[1]) / (2 * h) + 1j * (vals[2] - vals[3]) / (2 * h)
     assert brute.real == pytest.approx(g[n].real, rel=1e-6, abs=1e-9)
     assert brute.imag == pytest.approx(g[n].imag, rel=1e-6, abs=1e-9)
+
+
+# --- far field, amplitude and Mueller matrices (next step after the solve) --
+
+def test_far_field_is_the_limit_of_the_dipole_field():
+    """R e^{-ikR} E(R n) of a dipole p at r0 (Jackson's exact field) tends to the
+    oracle's F(n) as R grows; the O(1/R) remainder shrinks tenfold per decade."""
+    k = 0.6
+    r0 = np.array([2.0, -1.0, 3.0])
+    p = np.array([0.3 + 0.2j, -0.1 + 0.5j, 0.4 - 0.3j])
+    n = np.array([0.48, -0.6, 0.64])
+    n = n / np.linalg.norm(n)
+    F = ora.far_field(np.array([r0], np.int32), k, p.reshape(3, 1), n.reshape(1, 3))[0]
+    errs = []
+    for R in (1e4, 1e5):
+        E = _dipole_field(k, R * n - r0, p)
+        errs.append(np.linalg.norm(R * np.exp(-1j * k * R) * E - F) / np.linalg.norm(F))
+    assert errs[1] < 2e-3 and errs[1] < 0.2 * errs[0]
+
+
+def test_optical_theorem_from_forward_amplitude():
+    """C_ext = (4 pi / k) Im(e^* . F(k-hat)) = (4 pi / k^2) Re S2(0) for a solved
+    cluster, against the extinction sum C_ext = 4 pi k sum Im(E^* . P)."""
+    sites = _cluster(20, seed=3)
+    k = 0.8
+    ainv = ora.alpha_inv(np.full(20, 2.2 + 0.4j), k, "rr")
+    Ex = ora.einc(sites, k, [0, 0, 1], [1, 0, 0])
+    Ey = ora.einc(sites, k, [0, 0, 1], [0, 1, 0])
+    Px = ora.solve_dense(sites, k, ainv, Ex)
+    Py = ora.solve_dense(sites, k, ainv, Ey)
+    fwd = np.array([[0.0, 0.0, 1.0]])
+    Fx = ora.far_field(sites, k, Px, fwd)[0]
+    assert 4 * math.pi / k * np.imag(Fx[0]) == pytest.approx(ora.c_ext(k, Ex, Px), rel=1e-12)
+    S = ora.amplitude_matrix_z(ora.far_field(sites, k, Px, fwd), ora.far_field(sites, k, Py, fwd), [0.0], [0.0], k)
+    assert 4 * math.pi / k ** 2 * np.real(S[0, 1]) == pytest.approx(ora.c_ext(k, Ex, Px), rel=1e-12)
+
+
+def test_rayleigh_dipole_amplitude_and_mueller():
+    """A single isotropic dipole (P = alpha E0): S1 = -i k^3 alpha, S2 = S1 cos(theta),
+    S3 = S4 = 0 (Bohren & Huffman Sec. 5.2), so M11 = |S1|^2 (1 + cos^2)/2,
+    M12 = -|S1|^2 sin^2 / 2, M33 = M44 = |S1|^2 cos, all others 0."""
+    k, alpha = 0.7, 0.3 + 0.1j
+    th = np.array([0.2, 0.9, 1.6, 2.5])
+    ph = np.array([0.3, 2.0, 4.1, 5.5])
+    dirs = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
+    origin = np.zeros((1, 3), np.int32)
+    Fx = ora.far_field(origin, k, np.array([[alpha], [0], [0]]), dirs)
+    Fy = ora.far_field(origin, k, np.array([[0], [alpha], [0]]), dirs)
+    S = ora.amplitude_matrix_z(Fx, Fy, th, ph, k)
+    s1 = -1j * k ** 3 * alpha
+    np.testing.assert_allclose(S[:, 0], s1, rtol=1e-14)
+    np.testing.assert_allclose(S[:, 1], s1 * np.cos(th), rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(S[:, 2:], 0, atol=1e-16)
+    M = ora.mueller_from_amplitude(S)
+    a2 = abs(s1) ** 2
+    ref = np.zeros((4, 4, 4))
+    ref[:, 0, 0] = ref[:, 1, 1] = a2 * (1 + np.cos(th) ** 2) / 2
+    ref[:, 0, 1] = ref[:, 1, 0] = -a2 * np.sin(th) ** 2 / 2
+    ref[:, 2, 2] = ref[:, 3, 3] = a2 * np.cos(th)
+    np.testing.assert_allclose(M, ref, atol=1e-14 * a2)
+
+
+def test_mueller_of_a_pure_amplitude_matrix():
+    """A Mueller matrix from one amplitude matrix is non-depolarising:
+    sum_ij M_ij^2 = 4 M11^2; the identity Jones matrix gives the identity."""
+    rng = np.random.default_rng(2)
+    S = rng.normal(size=(6, 4)) + 1j * rng.normal(size=(6, 4))
+    M = ora.mueller_from_amplitude(S)
+    np.testing.assert_allclose(np.sum(M ** 2, axis=(1, 2)), 4 * M[:, 0, 0] ** 2, rtol=1e-12)
+    np.testing.assert_allclose(ora.mueller_from_amplitude([[1, 1, 0, 0]])[0], np.eye(4), atol=1e-15)
