@@ -166,6 +166,36 @@ int dda_incident_field(dda_target *t, int nrhs, const double *khat, const double
 int dda_cross_sections(dda_target *t, int nrhs, const double *S, const void *einc_dev, const void *p_dev,
                        double *cext, double *cabs, double *csca, void *hip_stream);
 
+/* Far-field amplitude of the solved dipoles (the step after the solve; the
+ * paper reports Q_sca from it, Sec. 5): F(n) = kd^2 (I - n n) sum_m
+ * exp(-i kd n . r_m) P_m, so that the scattered field is exp(i kd r)/r F(n) as
+ * r -> infinity (Gaussian units, |E0| = 1; Draine 1988).  dirs: host
+ * [ndir][3] unit vectors (DDA_EINVAL otherwise).  p_dev [nrhs][3][N_d]
+ * complex128; f_dev out [nrhs][ndir][3] complex128.  Synchronises the stream. */
+int dda_far_field(dda_target *t, int nrhs, const void *p_dev, int ndir, const double *dirs, void *f_dev,
+                  void *hip_stream);
+
+/* C_sca = integral of |F|^2 over the sphere by Gauss-Legendre quadrature in
+ * cos(theta) (ntheta nodes) times a uniform azimuth grid (nphi nodes); the
+ * integrand is band-limited by kd D (D the target's diameter), so the default
+ * (ntheta <= 0: ceil(kd (D + 1)) + 16, nphi = 2 ntheta) converges to rounding.
+ * Independent of dda_cross_sections' C_ext - C_abs: the two agree to the
+ * solve's residual (optical theorem).  csca: host out [nrhs]. */
+int dda_csca_quadrature(dda_target *t, int nrhs, const void *p_dev, int ntheta, int nphi, double *csca,
+                        void *hip_stream);
+
+/* Amplitude scattering matrix and Mueller matrix for incidence along +z
+ * (Bohren & Huffman 1983, Sec. 3.2-3.3).  p_dev holds the two solves
+ * [2][3][N_d] complex128 for polarisation x (first) and y (second).
+ * theta_phi: host [ndir][2] scattering angles.  Basis: e_par,i =
+ * cos(phi) x + sin(phi) y, e_perp,i = sin(phi) x - cos(phi) y, e_par,s =
+ * theta-hat, e_perp,s = -phi-hat, [E_par,s, E_perp,s] = exp(i kd r)/(-i kd r)
+ * [[S2, S3], [S4, S1]] [E_par,i, E_perp,i].  s_dev out [ndir][4] complex128
+ * (S1, S2, S3, S4), m_dev out [ndir][4][4] float64 row-major (either may be
+ * NULL, not both).  Synchronises the stream. */
+int dda_mueller(dda_target *t, const void *p_dev, int ndir, const double *theta_phi, void *s_dev, void *m_dev,
+                void *hip_stream);
+
 /* dC_abs/d eps_n for every dipole and right-hand side by one adjoint solve
  * with the same matrix (A is complex symmetric: A mu = W conj(P)).
  * grad_dev: out [nrhs][N_d] complex128 = dC/dRe eps + i dC/dIm eps.

@@ -26,6 +26,7 @@
 #include "kernels_fft.hpp"
 #include "kernels_solver.hpp"
 #include "fft_fast.hpp"
+#include "kernels_farfield.hpp"
 
 using namespace dda;
 
@@ -233,6 +234,8 @@ struct dda_target {
   DevBuf tolv;    // double [cap] inner tolerances
   DevBuf outer;   // FP64 outer vectors: E, r, y  (3 x [cap][3][nd])
   DevBuf khat, ehat;
+  DevBuf far_dirs, far_part, far_F, far_w, far_tp;  // far-field scratch
+  double extent = 0;  // diameter of the occupied sites' bounding box (units of d)
   int scap = 0;
   std::vector<int> h_active;
   int matvecs = 0;
@@ -510,6 +513,19 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   HIPCHK(hipMemcpy(t->sites.p, sites.data(), sites.size() * sizeof(int), hipMemcpyHostToDevice));
   t->nd = (int64_t)sites.size();
   t->have_alpha = t->have_eps = false;
+  {
+    int lo[3] = {t->K, t->J, t->P}, hi[3] = {-1, -1, -1};
+    for (int sv : sites) {
+      const int c[3] = {sv % t->K, (sv / t->K) % t->J, sv / (t->K * t->J)};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], c[a]);
+        hi[a] = std::max(hi[a], c[a]);
+      }
+    }
+    double e2 = 0;
+    for (int a = 0; a < 3; ++a) e2 += (double)(hi[a] - lo[a]) * (hi[a] - lo[a]);
+    t->extent = std::sqrt(e2);
+  }
   if (nd_out) *nd_out = t->nd;
   return DDA_OK;
 }
@@ -1790,6 +1806,158 @@ extern "C" int dda_cross_sections(dda_target* t, int nrhs, const double* S, cons
     if (cabs) cabs[q] = fk * sa;
     if (csca) csca[q] = fk * (se - sa);
   }
+  return DDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// far field
+// ---------------------------------------------------------------------------
+
+// F = k^2 (I - n n) sum_m e^{-i k n.r_m} P_m for ndir device directions.
+static int far_field_dev(dda_target* t, int nrhs, const c64* P, int ndir, const double* dirs_dev, c64* F,
+                         hipStream_t st) {
+  const int ntile = (ndir + kFarDirs - 1) / kFarDirs;
+  // enough blocks to fill the chip: split the dipoles into chunks
+  long nchunk = std::max<long>(1, std::min<long>(256, (2048 + (long)ntile * nrhs - 1) / ((long)ntile * nrhs)));
+  nchunk = std::min<long>(nchunk, std::max<long>(1, t->nd / kRedThreads));
+  CHK(t->far_part.ensure((size_t)nrhs * ntile * nchunk * kFarDirs * 3 * sizeof(c64)));
+  const size_t lds = (size_t)kFarDirs * (t->K + t->J + t->P) * sizeof(c64);
+  if (lds > 64 * 1024) return fail(DDA_EINVAL, "far field: lattice %dx%dx%d too long for the phase tables", t->K, t->J, t->P);
+  hipLaunchKernelGGL(k_far_partial, dim3(ntile, (unsigned)nchunk, nrhs), dim3(kRedThreads), lds, st, P,
+                     t->sites.as<int>(), (long)t->nd, t->K, t->J, t->P, t->kd, dirs_dev, ndir, (int)nchunk,
+                     t->far_part.as<c64>());
+  LAUNCHCHK();
+  const long nt = (long)nrhs * ndir;
+  hipLaunchKernelGGL(k_far_finish, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, t->far_part.as<c64>(), ntile,
+                     (int)nchunk, dirs_dev, ndir, nrhs, t->kd, F);
+  LAUNCHCHK();
+  return DDA_OK;
+}
+
+extern "C" int dda_far_field(dda_target* t, int nrhs, const void* p_dev, int ndir, const double* dirs, void* f_dev,
+                             void* hip_stream) {
+  if (!t || !p_dev || !dirs || !f_dev || nrhs < 1 || ndir < 1)
+    return fail(DDA_EINVAL, "dda_far_field: bad arguments");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_far_field: occupancy not set");
+  for (int d = 0; d < ndir; ++d) {
+    const double n2 = dirs[3 * d] * dirs[3 * d] + dirs[3 * d + 1] * dirs[3 * d + 1] + dirs[3 * d + 2] * dirs[3 * d + 2];
+    if (!(std::fabs(n2 - 1.0) < 1e-9)) return fail(DDA_EINVAL, "dda_far_field: direction %d is not a unit vector", d);
+  }
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(t->far_dirs.ensure((size_t)ndir * 3 * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(t->far_dirs.p, dirs, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(far_field_dev(t, nrhs, (const c64*)p_dev, ndir, t->far_dirs.as<double>(), (c64*)f_dev, st));
+  HIPCHK(hipStreamSynchronize(st));  // the host direction array may be reused at return
+  return DDA_OK;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n from the
+// Chebyshev-like first guesses; weights 2 / ((1 - x^2) P_n'(x)^2)).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+extern "C" int dda_csca_quadrature(dda_target* t, int nrhs, const void* p_dev, int ntheta, int nphi, double* csca,
+                                   void* hip_stream) {
+  if (!t || !p_dev || !csca || nrhs < 1) return fail(DDA_EINVAL, "dda_csca_quadrature: bad arguments");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_csca_quadrature: occupancy not set");
+  if (ntheta <= 0) {
+    ntheta = (int)std::ceil(t->kd * (t->extent + 1.0)) + 16;
+    nphi = 2 * ntheta;
+  }
+  if (nphi <= 0) nphi = 2 * ntheta;
+  if ((long)ntheta * nphi > (1L << 24)) return fail(DDA_EINVAL, "dda_csca_quadrature: %d x %d nodes", ntheta, nphi);
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<double> gx, gw;
+  gauss_legendre(ntheta, gx, gw);
+  const int ndir = ntheta * nphi;
+  std::vector<double> dirs((size_t)ndir * 3), wts(ndir);
+  for (int a = 0; a < ntheta; ++a) {
+    const double ct = gx[a], stv = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+    for (int b = 0; b < nphi; ++b) {
+      const double ph = 2.0 * M_PI * b / nphi;
+      const int d = a * nphi + b;
+      dirs[3 * d] = stv * std::cos(ph);
+      dirs[3 * d + 1] = stv * std::sin(ph);
+      dirs[3 * d + 2] = ct;
+      wts[d] = gw[a] * (2.0 * M_PI / nphi);
+    }
+  }
+  CHK(t->far_dirs.ensure((size_t)ndir * 3 * sizeof(double)));
+  CHK(t->far_w.ensure((size_t)ndir * sizeof(double)));
+  CHK(t->far_F.ensure((size_t)nrhs * ndir * 3 * sizeof(c64)));
+  HIPCHK(hipMemcpyAsync(t->far_dirs.p, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(t->far_w.p, wts.data(), wts.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(far_field_dev(t, nrhs, (const c64*)p_dev, ndir, t->far_dirs.as<double>(), t->far_F.as<c64>(), st));
+  const int nb = std::max(1, std::min(64, (ndir + kRedThreads - 1) / kRedThreads));
+  CHK(t->part.ensure((size_t)nrhs * nb * sizeof(c64)));
+  hipLaunchKernelGGL(k_far_power, dim3(nb, nrhs), dim3(kRedThreads), 0, st, t->far_F.as<c64>(), t->far_w.as<double>(),
+                     ndir, t->part.as<c64>());
+  LAUNCHCHK();
+  std::vector<c64> hp((size_t)nrhs * nb);
+  HIPCHK(hipMemcpyAsync(hp.data(), t->part.p, hp.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int q = 0; q < nrhs; ++q) {
+    double sum = 0.0;
+    for (int b = 0; b < nb; ++b) sum += hp[(size_t)q * nb + b].x;
+    csca[q] = sum;  // F already carries k^2, so |F|^2 carries k^4
+  }
+  return DDA_OK;
+}
+
+extern "C" int dda_mueller(dda_target* t, const void* p_dev, int ndir, const double* theta_phi, void* s_dev,
+                           void* m_dev, void* hip_stream) {
+  if (!t || !p_dev || !theta_phi || ndir < 1 || (!s_dev && !m_dev))
+    return fail(DDA_EINVAL, "dda_mueller: bad arguments");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_mueller: occupancy not set");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<double> dirs((size_t)ndir * 3);
+  for (int d = 0; d < ndir; ++d) {
+    const double th = theta_phi[2 * d], ph = theta_phi[2 * d + 1];
+    dirs[3 * d] = std::sin(th) * std::cos(ph);
+    dirs[3 * d + 1] = std::sin(th) * std::sin(ph);
+    dirs[3 * d + 2] = std::cos(th);
+  }
+  CHK(t->far_dirs.ensure((size_t)ndir * 3 * sizeof(double)));
+  CHK(t->far_tp.ensure((size_t)ndir * 2 * sizeof(double)));
+  CHK(t->far_F.ensure((size_t)2 * ndir * 3 * sizeof(c64)));
+  HIPCHK(hipMemcpyAsync(t->far_dirs.p, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(t->far_tp.p, theta_phi, (size_t)ndir * 2 * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(far_field_dev(t, 2, (const c64*)p_dev, ndir, t->far_dirs.as<double>(), t->far_F.as<c64>(), st));
+  const c64* F = t->far_F.as<c64>();
+  hipLaunchKernelGGL(k_mueller, dim3((ndir + 255) / 256), dim3(256), 0, st, F, F + (size_t)ndir * 3,
+                     t->far_tp.as<double>(), ndir, t->kd, (c64*)s_dev, (double*)m_dev);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));  // the host angle array may be reused at return
   return DDA_OK;
 }
 

@@ -62,7 +62,8 @@ class dda_batch_item(ctypes.Structure):
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
            "dda_set_permittivity", "dda_set_polarizability", "dda_build_spectrum", "dda_matvec", "dda_solve",
            "dda_batch_solve",
-           "dda_incident_field", "dda_cross_sections", "dda_grad_cabs_eps", "dda_target_set_option",
+           "dda_incident_field", "dda_cross_sections", "dda_far_field", "dda_csca_quadrature", "dda_mueller",
+           "dda_grad_cabs_eps", "dda_target_set_option",
            "dda_target_info",
            "dda_get_spectrum", "dda_profile_enable", "dda_profile_read", "dda_profile_reset",
            "dda_last_error"]
@@ -97,6 +98,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_batch_solve": (i, [vp, P(dda_solve_opts), i, vp, i, vp]),
         "dda_incident_field": (i, [vp, i, vp, vp, vp, vp]),
         "dda_cross_sections": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
+        "dda_far_field": (i, [vp, i, vp, i, vp, vp, vp]),
+        "dda_csca_quadrature": (i, [vp, i, vp, i, i, vp, vp]),
+        "dda_mueller": (i, [vp, vp, i, vp, vp, vp, vp]),
         "dda_grad_cabs_eps": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp]),
         "dda_target_set_option": (i, [vp, i, i]),
         "dda_target_info": (i, [vp, vp]),
@@ -343,6 +347,33 @@ class Target:
         _check(load().dda_cross_sections(self.h, nrhs, Sp, _dptr(einc), _dptr(P), _np_ptr(ce), _np_ptr(ca),
                                          _np_ptr(cs), _stream()))
         return ce, ca, cs
+
+    def far_field(self, P: torch.Tensor, dirs) -> torch.Tensor:
+        """F(n) [nrhs, ndir, 3] complex128 for unit directions dirs [ndir, 3]."""
+        d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 3))
+        F = torch.empty((P.shape[0], d.shape[0], 3), dtype=torch.complex128, device=self.dev)
+        _check(load().dda_far_field(self.h, P.shape[0], _dptr(P), d.shape[0], _np_ptr(d), _dptr(F), _stream()))
+        return F
+
+    def csca_quadrature(self, P: torch.Tensor, ntheta: int = 0, nphi: int = 0) -> np.ndarray:
+        """C_sca per right-hand side by far-field quadrature."""
+        out = np.zeros(P.shape[0])
+        _check(load().dda_csca_quadrature(self.h, P.shape[0], _dptr(P), int(ntheta), int(nphi), _np_ptr(out),
+                                          _stream()))
+        return out
+
+    def mueller(self, P_xy: torch.Tensor, theta, phi):
+        """(S [ndir, 4] complex128 = S1..S4, M [ndir, 4, 4] float64) for incidence
+        along +z from the x- and y-polarised solves P_xy [2, 3, N_d]."""
+        if P_xy.shape[0] != 2:
+            raise ValueError("P_xy must hold the x- and y-polarised solves")
+        tp = np.ascontiguousarray(np.stack([np.asarray(theta, np.float64).ravel(),
+                                            np.asarray(phi, np.float64).ravel()], 1))
+        n = tp.shape[0]
+        S = torch.empty((n, 4), dtype=torch.complex128, device=self.dev)
+        M = torch.empty((n, 4, 4), dtype=torch.float64, device=self.dev)
+        _check(load().dda_mueller(self.h, _dptr(P_xy), n, _np_ptr(tp), _dptr(S), _dptr(M), _stream()))
+        return S, M
 
     def grad_cabs_eps(self, P: torch.Tensor, S=None, **kw) -> torch.Tensor:
         opts = self.make_opts(**kw)
