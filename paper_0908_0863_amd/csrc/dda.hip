@@ -706,7 +706,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
-  CHK(t->state.ensure(2 * cap * std::max(sizeof(BcgState), sizeof(QmrState))));
+  CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState)})));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
   CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
   t->h_active.resize(cap);
@@ -1186,24 +1186,34 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    float best_ms = 1e30f;
+    // candidates timed round-robin (three rounds of three matvecs after two
+    // warm-ups each); each keeps its fastest round, so a cold start or a
+    // disturbance in one round does not decide
+    std::vector<float> best_c(cand.size(), 1e30f);
     int rc = DDA_OK;
-    for (int c : cand) {
-      t->sched_override = c;
+    for (size_t ci = 0; ci < cand.size() && rc == DDA_OK; ++ci) {
+      t->sched_override = cand[ci];
       for (int w = 0; w < 2 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
-      (void)hipEventRecord(e0, st);
-      for (int w = 0; w < 3 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rc == DDA_OK && ms < best_ms) {
-        best_ms = ms;
-        best = c;
-      }
     }
+    for (int round = 0; round < 3 && rc == DDA_OK; ++round)
+      for (size_t ci = 0; ci < cand.size() && rc == DDA_OK; ++ci) {
+        t->sched_override = cand[ci];
+        (void)hipEventRecord(e0, st);
+        for (int w = 0; w < 3 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best_c[ci] = std::min(best_c[ci], ms);
+      }
+    float best_ms = 1e30f;
+    for (size_t ci = 0; ci < cand.size(); ++ci)
+      if (best_c[ci] < best_ms) {
+        best_ms = best_c[ci];
+        best = cand[ci];
+      }
     t->sched_override = -1;
-    t->matvecs -= 5 * (int)cand.size();
+    t->matvecs -= 11 * (int)cand.size();
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (prof) t->lib->prof = prof;
@@ -1317,6 +1327,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   if (check % 2) ++check;  // vector rings and state buffers have period 2
   int n_active = 0;
   const bool bcg = solver == DDA_BICGSTAB;
+  const bool cgs = solver == DDA_BICG_SYM;
   const int mv_per_iter = bcg ? 2 : 1;
 
   // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
@@ -1331,6 +1342,11 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
                        R3);
     hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
+  } else if (cgs) {
+    // slot 2 = r, 3 = p, 4 = q
+    CgState* S0 = t->state.as<CgState>();
+    hipLaunchKernelGGL((k_cg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), u, act, dm, R3);
+    hipLaunchKernelGGL(k_cg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
   } else {
     QmrState* S0 = t->state.as<QmrState>();
     // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring, slot 7 = QMR residual
@@ -1359,6 +1375,17 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s, d2));
       hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(kRedThreads), 0, s, u, r, p, tt, rhat, R1, M1, nblk_mv, SA, SB, act, dm,
                          R3);
+    } else if (cgs) {
+      // two state writes per iteration: the newest state is back in SA
+      CgState* SA = t->state.as<CgState>();
+      CgState* SB = t->state.as<CgState>() + nrhs;
+      cx<R>*r = slot(2), *p = slot(3), *q = slot(4);
+      hipLaunchKernelGGL((k_cg_p<R>), vg, dim3(kRedThreads), 0, s, r, p, R3, SA, SB, act, dm);
+      DotArgs d;
+      d.mode = DOT_BIL;
+      d.part = M0;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, q, act, s, d));
+      hipLaunchKernelGGL((k_cg_update<R>), vg, dim3(kRedThreads), 0, s, u, r, p, q, M0, nblk_mv, SB, SA, act, dm, R3);
     } else {
       QmrState* SA = t->state.as<QmrState>() + (par ? nrhs : 0);
       QmrState* SB = t->state.as<QmrState>() + (par ? 0 : nrhs);
@@ -1462,6 +1489,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     return DDA_OK;
   };
   if (bcg) return collect(t->state.as<BcgState>(), BcgState{});
+  if (cgs) return collect(t->state.as<CgState>(), CgState{});
   return collect(t->state.as<QmrState>(), QmrState{});
 }
 
@@ -1636,7 +1664,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
 
 static int check_opts(const dda_solve_opts* opts, const char* who) {
   if (!opts) return fail(DDA_EINVAL, "%s: opts is NULL", who);
-  if (opts->solver != DDA_BICGSTAB && opts->solver != DDA_QMR_SYM)
+  if (opts->solver != DDA_BICGSTAB && opts->solver != DDA_QMR_SYM && opts->solver != DDA_BICG_SYM)
     return fail(DDA_EINVAL, "%s: solver %d", who, opts->solver);
   if (opts->precision != DDA_SOLVE_FP64 && opts->precision != DDA_SOLVE_MIXED)
     return fail(DDA_EINVAL, "%s: precision %d", who, opts->precision);

@@ -312,6 +312,164 @@ __global__ void __launch_bounds__(kRedThreads) k_bcg_update(cx<R>* __restrict__ 
 }
 
 // ============================================================================
+// BiCG for complex-symmetric matrices, BiCG_sym (Freund 1992a; also known as
+// COCG): the BiCG recurrences with the shadow vectors equal to the conjugate
+// iterates, so one matrix-vector product per iteration and the bilinear form
+//   p = r + beta p;  q = A p;  alpha = rho / p^T q;  u += alpha p;  r -= alpha q;
+//   rho' = r^T r;  beta = rho' / rho.
+// Stopping on ||r|| (Hermitian norm of the recursive residual).
+// ============================================================================
+struct CgState {
+  c64 rho, rho_old, alpha, beta;
+  double bnorm2, rnorm2, tol2, best2;
+  int converged, breakdown, iters, best_it;
+  int ver;  // incremented by every kernel that writes the state
+};
+
+// r = b, p = u = 0; partials [|b|^2, b^T b]
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cg_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
+                                                         cx<R>* __restrict__ p, cx<R>* __restrict__ u,
+                                                         const int* __restrict__ active, SolverDims dm,
+                                                         c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  if (active[rhs]) {
+    const long o = (long)rhs * dm.n3;
+    DDA_RANGE(dm, i) {
+      const cx<R> bv = b[o + i];
+      r[o + i] = bv;
+      p[o + i] = mk((R)0, (R)0);
+      u[o + i] = mk((R)0, (R)0);
+      const c64 bd = up(bv);
+      acc[0].x += abs2(bd);
+      acc[1] = acc[1] + bd * bd;
+    }
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+__global__ void k_cg_fin_init(const c64* __restrict__ part, int nblk, CgState* __restrict__ st,
+                              int* __restrict__ active, const double* __restrict__ tolv) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    CgState s;
+    s.bnorm2 = v[0].x;
+    s.rnorm2 = v[0].x;
+    const double tol = tolv[rhs];
+    s.tol2 = tol * tol * v[0].x;
+    s.best2 = v[0].x;
+    s.best_it = 0;
+    s.rho = mk(0.0, 0.0);  // the first p kernel moves rho' = b^T b into rho
+    s.rho_old = mk(1.0, 0.0);
+    s.alpha = mk(0.0, 0.0);
+    s.beta = mk(0.0, 0.0);
+    s.converged = v[0].x == 0.0;
+    s.breakdown = 0;
+    s.iters = -1;
+    s.ver = 0;
+    st[rhs] = s;
+    if (s.converged) active[rhs] = 0;
+  }
+}
+
+// From the previous update's partials [|r|^2, r^T r]: convergence,
+// stagnation, breakdown; then beta = rho'/rho and p = r + beta p.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cg_p(const cx<R>* __restrict__ r, cx<R>* __restrict__ p,
+                                                      const c64* __restrict__ pupd,
+                                                      const CgState* __restrict__ sin, CgState* __restrict__ sout,
+                                                      int* __restrict__ active, SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[2];
+  reduce_all<2>(pupd, dm.nblk, rhs, red);
+  CgState s = sin[rhs];
+  s.iters += 1;
+  s.rnorm2 = red[0].x;
+  s.rho_old = s.rho;
+  s.rho = red[1];
+  int stop = 0;
+  if (!isfinite(red[0].x)) {
+    s.breakdown = 1;
+    stop = 1;
+  } else if (s.rnorm2 <= s.tol2) {
+    s.converged = 1;
+    stop = 1;
+  } else if (s.rnorm2 < 0.98 * s.best2) {
+    s.best2 = s.rnorm2;
+    s.best_it = s.iters;
+  } else if (s.iters - s.best_it > kStallWindow && s.rnorm2 < stall_level2<R>() * s.bnorm2) {
+    s.breakdown = 2;  // stagnated
+    stop = 1;
+  }
+  if (!stop) {
+    if (tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32)) {
+      s.breakdown = 1;  // r^T r = 0 with r != 0: restart from the current iterate
+      stop = 1;
+    } else {
+      s.beta = s.iters > 0 ? cdiv(s.rho, s.rho_old) : mk(0.0, 0.0);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+    if (stop) active[rhs] = 0;
+  }
+  if (stop) return;
+  const cx<R> beta = cvt<R>(s.beta);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) { p[o + i] = r[o + i] + beta * p[o + i]; }
+}
+
+// alpha = rho / p^T q (partials from the matrix-vector product, nblk_mv blocks,
+// stride 2); u += alpha p; r -= alpha q; partials [|r|^2, r^T r]
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cg_update(cx<R>* __restrict__ u, cx<R>* __restrict__ r,
+                                                           const cx<R>* __restrict__ p, const cx<R>* __restrict__ q,
+                                                           const c64* __restrict__ pdot, int nblk_mv,
+                                                           const CgState* __restrict__ sin,
+                                                           CgState* __restrict__ sout, int* __restrict__ active,
+                                                           SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[2];
+  reduce_all<2>(pdot, nblk_mv, rhs, red);
+  CgState s = sin[rhs];
+  const bool bad = tiny(red[0], s.bnorm2 * s.bnorm2 * 1e-32) || !isfinite(red[0].x);
+  if (bad) s.breakdown = 1;
+  else s.alpha = cdiv(s.rho, red[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+    if (bad) active[rhs] = 0;
+  }
+  if (bad) return;
+  const cx<R> al = cvt<R>(s.alpha);
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    u[o + i] = u[o + i] + al * p[o + i];
+    const cx<R> rn = r[o + i] - al * q[o + i];
+    r[o + i] = rn;
+    const c64 rd = up(rn);
+    acc[0].x += abs2(rd);
+    acc[1] = acc[1] + rd * rd;
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+// ============================================================================
 // QMR for complex-symmetric matrices (Freund 1992): Lanczos with the bilinear
 // form x^T y and Euclidean-normalised vectors v_n = vt_n / rho_n, the
 // tridiagonal matrix reduced by Givens rotations, iterate u_n updated through
@@ -407,43 +565,42 @@ __global__ void k_qmr_fin_init(const c64* __restrict__ part, int nblk, QmrState*
 // changes by one rotation per step), not the quasi-residual |tau_n|, which can
 // sit far below the residual when the Lanczos vectors are far from
 // orthogonal.  The norm of r_{n-2} arrives with this step's partials, when u
-// still holds u_{n-2}; a converged right-hand side stops here unchanged.
-template <typename R>
-__global__ void __launch_bounds__(kRedThreads) k_qmr_step(const cx<R>* __restrict__ w, const cx<R>* __restrict__ vn,
-                                                  cx<R>* __restrict__ vp, const cx<R>* __restrict__ p1,
-                                                  cx<R>* __restrict__ p2, cx<R>* __restrict__ u,
-                                                  cx<R>* __restrict__ r, const c64* __restrict__ pnorm_in,
-                                                  const c64* __restrict__ pdot, int nblk_mv,
-                                                  const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
-                                                  int* __restrict__ active, SolverDims dm,
-                                                  c64* __restrict__ pnorm_out) {
-  const int rhs = blockIdx.y;
-  if (!active[rhs]) return;
-  c64 rn[2], rd[2];
-  reduce_all<2>(pnorm_in, dm.nblk, rhs, rn);
-  QmrState s = sin[rhs];
+// still holds u_{n-2}; a right-hand side that stops (converged, stagnated or
+// broken down) stops here with u = u_{n-2} and no vector written, so every
+// block agrees whether or not it saw the cleared `active` flag.
+//
+// One wave reduces the partials (fixed order: identical in every block) and
+// one lane runs the scalar recurrences; the vector coefficients reach the
+// block through LDS.
+
+// Scalar part of a QMR_sym step: from the reduced partials and the state,
+// the next state and the coefficients of the vector update.
+struct QmrCoef {
+  double sgp, sg, rs;
+  c64 fpp, ep, rinv, coef, rc, alpha, bs;
+  int upd, stop;
+};
+
+__device__ inline void qmr_scalars(const c64 (&rn)[2], const c64 (&rd)[2], QmrState& s, QmrCoef& q) {
   const int n = s.n;
   // residual of the current iterate u_{n-2}
   const double r2 = rn[0].y;
   s.rnorm2 = r2;
+  q.upd = 0;
+  q.stop = 0;
   if (r2 <= s.tol2 || !isfinite(r2)) {
     if (r2 <= s.tol2) s.converged = 1;
     else s.breakdown = 1;
     s.iters = n >= 2 ? n - 2 : 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      s.ver += 1;
-      sout[rhs] = s;
-      active[rhs] = 0;
-    }
+    q.stop = 1;
     return;
   }
   if (r2 < 0.98 * s.best2) {
     s.best2 = r2;
     s.best_it = n;
-  } else if (n - s.best_it > kStallWindow && r2 < stall_level2<R>() * s.bnorm2) {
-    s.breakdown = 2;  // stagnated
+  } else if (n - s.best_it > kStallWindow) {
+    s.breakdown = 2;  // stagnated (kept only where the rule applies, see below)
   }
-  reduce_all<2>(pdot, nblk_mv, rhs, rd);
   const double rho = sqrt(rn[0].x);
   // Lanczos scalars of step n
   c64 alpha = mk(0.0, 0.0), beta = mk(0.0, 0.0), delta = mk(0.0, 0.0);
@@ -500,51 +657,109 @@ __global__ void __launch_bounds__(kRedThreads) k_qmr_step(const cx<R>* __restric
   }
   if (!(rho > 0.0)) s.converged = 1;  // vt_n = 0: the Krylov space is invariant
   if (!isfinite(rho)) s.breakdown = 1;
-  const int stop = s.converged || s.breakdown;
   const double sigp = 1.0 / s.rho_prev;
   s.alpha_prev = alpha;
   s.beta_prev = beta;
   s.delta_prev = delta;
   s.rho_prev = rho > 0.0 ? rho : 1.0;
   s.n = n + 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    s.ver += 1;
-    sout[rhs] = s;
-    if (stop) active[rhs] = 0;
+  q.stop = s.converged || s.breakdown;
+  q.upd = upd;
+  q.sgp = sigp;
+  q.sg = sig;
+  q.rs = rs;
+  q.fpp = fpp;
+  q.ep = ep;
+  q.rinv = rinv;
+  q.coef = coef;
+  q.rc = rc;
+  q.alpha = alpha;
+  q.bs = sigp * beta;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_qmr_step(const cx<R>* __restrict__ w, const cx<R>* __restrict__ vn,
+                                                  cx<R>* __restrict__ vp, const cx<R>* __restrict__ p1,
+                                                  cx<R>* __restrict__ p2, cx<R>* __restrict__ u,
+                                                  cx<R>* __restrict__ r, const c64* __restrict__ pnorm_in,
+                                                  const c64* __restrict__ pdot, int nblk_mv,
+                                                  const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
+                                                  int* __restrict__ active, SolverDims dm,
+                                                  c64* __restrict__ pnorm_out) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  __shared__ QmrCoef cq;
+  if (threadIdx.x < 64) {
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < dm.nblk; b += 64) {
+      const c64* pp = pnorm_in + ((long)rhs * dm.nblk + b) * 2;
+      v[0] += pp[0].x;
+      v[1] += pp[0].y;
+      v[2] += pp[1].x;
+      v[3] += pp[1].y;
+    }
+    for (int b = threadIdx.x; b < nblk_mv; b += 64) {
+      const c64* pp = pdot + ((long)rhs * nblk_mv + b) * 2;
+      v[4] += pp[0].x;
+      v[5] += pp[0].y;
+      v[6] += pp[1].x;
+      v[7] += pp[1].y;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    if (threadIdx.x == 0) {
+      const c64 rn[2] = {mk(v[0], v[1]), mk(v[2], v[3])};
+      const c64 rd[2] = {mk(v[4], v[5]), mk(v[6], v[7])};
+      QmrState s = sin[rhs];
+      QmrCoef q;
+      qmr_scalars(rn, rd, s, q);
+      // the stagnation rule applies to FP64 vectors only near their rounding level
+      if (s.breakdown == 2 && !(s.rnorm2 < stall_level2<R>() * s.bnorm2)) {
+        s.breakdown = 0;
+        q.stop = s.converged;
+      }
+      cq = q;
+      if (blockIdx.x == 0) {
+        s.ver += 1;
+        sout[rhs] = s;
+        if (q.stop) active[rhs] = 0;
+      }
+    }
   }
-  const R sgp = (R)sigp, sg = (R)sig, rsr = (R)rs;
-  const cx<R> fppr = cvt<R>(fpp), epr = cvt<R>(ep), rir = cvt<R>(rinv), cf = cvt<R>(coef), rcr = cvt<R>(rc);
-  const cx<R> al = cvt<R>(alpha), bs = cvt<R>((double)sigp * beta);
+  __syncthreads();
+  const QmrCoef q = cq;
+  if (q.stop) return;
+  const bool upd = q.upd;
+  const R sgp = (R)q.sgp, sg = (R)q.sg, rsr = (R)q.rs;
+  const cx<R> fppr = cvt<R>(q.fpp), epr = cvt<R>(q.ep), rir = cvt<R>(q.rinv), cf = cvt<R>(q.coef),
+              rcr = cvt<R>(q.rc);
+  const cx<R> al = cvt<R>(q.alpha), bs = cvt<R>(q.bs);
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
   DDA_RANGE(dm, i) {
     const cx<R> vpi = vp[o + i];
     const cx<R> vni = vn[o + i];
+    cx<R> ri = r[o + i];
     if (upd) {
       const cx<R> pn = rir * (sgp * vpi - fppr * p1[o + i] - epr * p2[o + i]);
       p2[o + i] = pn;
       u[o + i] = u[o + i] + cf * pn;
+      ri = rsr * ri + rcr * vni;
+      r[o + i] = ri;
     }
-    if (!stop) {
-      cx<R> ri = r[o + i];
-      if (upd) {
-        ri = rsr * ri + rcr * vni;
-        r[o + i] = ri;
-      }
-      const cx<R> t = sg * (w[o + i] - al * vni) - bs * vpi;
-      vp[o + i] = t;
-      const c64 td = up(t);
-      acc[0].x += abs2(td);
-      acc[0].y += abs2(up(ri));
-      acc[1] = acc[1] + td * td;
-    }
+    const cx<R> t = sg * (w[o + i] - al * vni) - bs * vpi;
+    vp[o + i] = t;
+    const c64 td = up(t);
+    acc[0].x += abs2(td);
+    acc[0].y += abs2(up(ri));
+    acc[1] = acc[1] + td * td;
   }
-  if (!stop) {
-    block_sum<2>(acc);
-    if (threadIdx.x == 0) {
-      pnorm_out[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
-      pnorm_out[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
-    }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    pnorm_out[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    pnorm_out[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
   }
 }
 

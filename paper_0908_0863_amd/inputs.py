@@ -177,6 +177,13 @@ def workload(name: str) -> dict:
         big = sphere_count(128)
         return dict(name=name, occ=occ, K=10, J=10, P=10, m=1.6 + 0.05j,
                     kd=kd_from_size_parameter(20.0, big), khat=[zhat], ehat=[xh])
+    if name == "sphere200":    # the paper's benchmark sphere (Sec. 5, Table 3): same optics as cube100
+        occ = sphere(200)
+        nd = int(occ.sum())
+        lam, a = 3.175, 0.5
+        x = 2.0 * math.pi * a / lam
+        return dict(name=name, occ=occ, K=200, J=200, P=200, m=1.63631 + 0.372j,
+                    kd=kd_from_size_parameter(x, nd), khat=[zhat], ehat=[xh])
     if name == "cube100":      # the paper's validation cube (Sec. 5): x = 0.989478
         occ = cube(100)
         lam, a = 3.175, 0.5

@@ -177,3 +177,21 @@ def test_autograd_gradcheck_sphere10(lib):
     go = sum(ora.grad_cabs_adjoint_dense(sites, w["kd"], base.numpy(), "ldr", 0.0,
                                          ora.einc(sites, w["kd"], k, e))[0] for k, e in zip(kh, eh))
     assert _rel(eps.grad.numpy(), go) < 1e-9
+
+
+@pytest.mark.timeout(600)
+def test_iteration_counts_sphere200_table3(lib):
+    """The paper's benchmark solve (Table 3): iteration counts of BiCG_sym,
+    BiCGSTAB and QMR_sym within 50% of the printed ones (the paper leaves the
+    stopping rule and the polarisability unstated, so only the scale is
+    fixed)."""
+    w = inputs.workload("sphere200")
+    t, nd = _target(lib, w)
+    assert nd == 4188896
+    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "qmr_sym": "qmr"}
+    for solver, ni in read_golden("table3_iterations.txt"):
+        P, info = t.solve(khat=w["khat"], ehat=w["ehat"], solver=name[solver], precision="fp64", tol=1e-10)
+        it = info[0]["iterations"]
+        print(f"sphere200 {solver}: {it} iterations (paper {ni}), residual {info[0]['rel_residual']:.2e}", flush=True)
+        assert info[0]["converged"]
+        assert 0.5 * int(ni) <= it <= 1.5 * int(ni), (solver, it, ni)
