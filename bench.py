@@ -229,6 +229,49 @@ def bench_batch_targets(args):
           iterations_max=max(i["iterations"] for _, inf in res for i in inf))
 
 
+def bench_paper200(args):
+    """The paper's benchmark solve (Sec. 5, Table 3): 200^3 sphere, N_d =
+    4,188,896, lambda = 3.175 um, a_eff = 0.5 um, m = 1.63631 + 0.372i,
+    polarisation x, FP64, tol 1e-10, zero initial guess, Point-Jacobi.  The
+    paper's times (NEMO, 2x dual-core Opteron 275; serial / OpenMP on 4
+    cores) are quoted as context."""
+    import torch
+
+    from paper_0908_0863_amd import dda, inputs
+    w = inputs.workload("sphere200")
+    lib = dda.Library(0)
+    t = dda.Target(lib, 200, 200, 200, w["kd"])
+    nd = t.set_occupancy(w["occ"])
+    t.set_permittivity(w["m"] ** 2, "ldr")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t.build_spectrum()
+    torch.cuda.synchronize()
+    t_spec = time.perf_counter() - t0
+    paper = {"bicg_sym": (21, 741.5, 212.7), "bicgstab": (12, 846.6, 234.7), "qmr_sym": (21, 759.6, 216.7)}
+    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "qmr_sym": "qmr"}
+    out = {}
+    for solver, (ni, ser, omp) in paper.items():
+        kw = dict(khat=w["khat"], ehat=w["ehat"], solver=name[solver], precision="fp64", tol=1e-10, check_every=4,
+                  use_graph=True)
+        t.solve(**kw)  # tuning, workspaces, graph
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 5))
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            P, info = t.solve(**kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t1) / steps
+        out[solver] = dict(iterations=info[0]["iterations"], seconds=round(el, 4), paper_iterations=ni,
+                           paper_serial_s=ser, paper_openmp4_s=omp, speedup_vs_openmp4=round(omp / el, 1))
+    total = sum(v["seconds"] for v in out.values())
+    _line("Table 3 benchmark solves/sec (200^3 sphere, FP64, tol 1e-10)", len(out) / total, "solves/s", args,
+          total, len(out), "f64", {"workload": f"sphere200: 200^3 lattice, {nd} dipoles, m=1.63631+0.372i, "
+                                               f"kd={w['kd']:.6f}, FFT grid {t.info()['Kpp']}^3, tol 1e-10, Jacobi"},
+          solvers=out, spectrum_build_s=round(t_spec, 4),
+          paper_spectrum_build_s={"serial": 13.4, "openmp4": 3.8})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,10 +286,11 @@ def main():
                     help="only run this many FP32 matrix-vector products (for rocprofv3 counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
-    ap.add_argument("--mode", choices=["single", "batch-rhs", "batch-targets"], default="single",
+    ap.add_argument("--mode", choices=["single", "batch-rhs", "batch-targets", "paper200"], default="single",
                     help="single: one right-hand side of --workload (the headline line); batch-rhs: all "
                          "orientations of --workload in one multi-RHS solve; batch-targets: 40 seeded "
-                         "aggregates through the multi-target batch solve")
+                         "aggregates through the multi-target batch solve; paper200: the paper's Table 3 "
+                         "benchmark solve (200^3 sphere, FP64, tol 1e-10) with BiCG_sym, BiCGSTAB, QMR_sym")
     ap.add_argument("--nrhs", type=int, default=0, help="batch-rhs: right-hand sides (default: all)")
     ap.add_argument("--workers", type=int, default=0, help="batch-targets: host workers (default 4)")
     args = ap.parse_args()
@@ -274,6 +318,8 @@ def main():
         return bench_batch_targets(args)
     if args.mode == "batch-rhs":
         return bench_batch_rhs(args)
+    if args.mode == "paper200":
+        return bench_paper200(args)
     w = inputs.workload(args.workload)
     K, J, P = w["K"], w["J"], w["P"]
     import tempfile
