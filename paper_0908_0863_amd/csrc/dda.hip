@@ -706,7 +706,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
-  CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState)})));
+  CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState), sizeof(CgsState)})));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
   CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
   t->h_active.resize(cap);
@@ -1281,7 +1281,7 @@ template <typename R>
 static int ensure_solver_ws(dda_target* t, int nrhs) {
   PrecBufs<R>& b = bufs<R>(t);
   if (nrhs <= b.vec_cap) return DDA_OK;
-  CHK(b.vec.ensure((size_t)8 * nrhs * 3 * t->nd * sizeof(cx<R>)));
+  CHK(b.vec.ensure((size_t)9 * nrhs * 3 * t->nd * sizeof(cx<R>)));
   b.vec_cap = nrhs;
   return DDA_OK;
 }
@@ -1328,7 +1328,8 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   int n_active = 0;
   const bool bcg = solver == DDA_BICGSTAB;
   const bool cgs = solver == DDA_BICG_SYM;
-  const int mv_per_iter = bcg ? 2 : 1;
+  const bool sq = solver == DDA_CGS;
+  const int mv_per_iter = (bcg || sq) ? 2 : 1;
 
   // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
   CHK(autotune<R>(t, nrhs, dS, jacobi, slot(0), slot(4), st));
@@ -1342,6 +1343,12 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
                        R3);
     hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
+  } else if (sq) {
+    // slot 2 = r, 3 = rt, 4 = p, 5 = q, 6 = uu, 7 = v and t, 8 = w
+    CgsState* S0 = t->state.as<CgsState>();
+    hipLaunchKernelGGL((k_cgs_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act,
+                       dm, R3);
+    hipLaunchKernelGGL(k_cgs_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
   } else if (cgs) {
     // slot 2 = r, 3 = p, 4 = q
     CgState* S0 = t->state.as<CgState>();
@@ -1375,6 +1382,20 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s, d2));
       hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(kRedThreads), 0, s, u, r, p, tt, rhat, R1, M1, nblk_mv, SA, SB, act, dm,
                          R3);
+    } else if (sq) {
+      // two state writes per iteration: the newest state is back in SA
+      CgsState* SA = t->state.as<CgsState>();
+      CgsState* SB = t->state.as<CgsState>() + nrhs;
+      cx<R>*r = slot(2), *rt = slot(3), *p = slot(4), *q = slot(5), *uu = slot(6), *v = slot(7), *w = slot(8);
+      hipLaunchKernelGGL((k_cgs_p<R>), vg, dim3(kRedThreads), 0, s, r, q, uu, p, R3, SA, SB, act, dm);
+      DotArgs d1;
+      d1.mode = DOT_HA;
+      d1.a = rt;
+      d1.part = M0;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, v, act, s, d1));
+      hipLaunchKernelGGL((k_cgs_q<R>), vg, dim3(kRedThreads), 0, s, uu, v, q, w, u, M0, nblk_mv, SB, SA, act, dm);
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, w, v, act, s, DotArgs{}));
+      hipLaunchKernelGGL((k_cgs_update<R>), vg, dim3(kRedThreads), 0, s, r, v, rt, SA, act, dm, R3);
     } else if (cgs) {
       // two state writes per iteration: the newest state is back in SA
       CgState* SA = t->state.as<CgState>();
@@ -1490,6 +1511,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   };
   if (bcg) return collect(t->state.as<BcgState>(), BcgState{});
   if (cgs) return collect(t->state.as<CgState>(), CgState{});
+  if (sq) return collect(t->state.as<CgsState>(), CgsState{});
   return collect(t->state.as<QmrState>(), QmrState{});
 }
 
@@ -1664,7 +1686,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
 
 static int check_opts(const dda_solve_opts* opts, const char* who) {
   if (!opts) return fail(DDA_EINVAL, "%s: opts is NULL", who);
-  if (opts->solver != DDA_BICGSTAB && opts->solver != DDA_QMR_SYM && opts->solver != DDA_BICG_SYM)
+  if (opts->solver < DDA_BICGSTAB || opts->solver > DDA_CGS)
     return fail(DDA_EINVAL, "%s: solver %d", who, opts->solver);
   if (opts->precision != DDA_SOLVE_FP64 && opts->precision != DDA_SOLVE_MIXED)
     return fail(DDA_EINVAL, "%s: precision %d", who, opts->precision);

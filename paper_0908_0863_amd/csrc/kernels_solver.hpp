@@ -470,6 +470,192 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_update(cx<R>* __restrict__ u
   }
 }
 // ============================================================================
+// CGS, conjugate gradients squared (Sonneveld 1989): transpose-free, two
+// products per iteration, Hermitian shadow inner products with rt = r_0
+//   rho = rt^H r;  beta = rho / rho_old;  uu = r + beta q;
+//   p = uu + beta (q + beta p);  v = A p;  alpha = rho / rt^H v;
+//   q = uu - alpha v;  w = uu + q;  u += alpha w;  r -= alpha A w
+// ============================================================================
+struct CgsState {
+  c64 rho, rho_old, alpha, beta;
+  double bnorm2, rnorm2, tol2, best2;
+  int converged, breakdown, iters, best_it;
+  int ver;  // incremented by every kernel that writes the state
+};
+
+// r = rt = b, p = q = u = 0; partials [|b|^2, rt^H r = |b|^2]
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cgs_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ r,
+                                                          cx<R>* __restrict__ rt, cx<R>* __restrict__ p,
+                                                          cx<R>* __restrict__ q, cx<R>* __restrict__ u,
+                                                          const int* __restrict__ active, SolverDims dm,
+                                                          c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[1] = {mk(0.0, 0.0)};
+  if (active[rhs]) {
+    const long o = (long)rhs * dm.n3;
+    const cx<R> z = mk((R)0, (R)0);
+    DDA_RANGE(dm, i) {
+      const cx<R> bv = b[o + i];
+      r[o + i] = bv;
+      rt[o + i] = bv;
+      p[o + i] = z;
+      q[o + i] = z;
+      u[o + i] = z;
+      acc[0].x += abs2(up(bv));
+    }
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[0];
+  }
+}
+
+__global__ void k_cgs_fin_init(const c64* __restrict__ part, int nblk, CgsState* __restrict__ st,
+                               int* __restrict__ active, const double* __restrict__ tolv) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    CgsState s;
+    s.bnorm2 = v[0].x;
+    s.rnorm2 = v[0].x;
+    const double tol = tolv[rhs];
+    s.tol2 = tol * tol * v[0].x;
+    s.best2 = v[0].x;
+    s.best_it = 0;
+    s.rho = mk(0.0, 0.0);
+    s.rho_old = mk(1.0, 0.0);
+    s.alpha = mk(0.0, 0.0);
+    s.beta = mk(0.0, 0.0);
+    s.converged = v[0].x == 0.0;
+    s.breakdown = 0;
+    s.iters = -1;
+    s.ver = 0;
+    st[rhs] = s;
+    if (s.converged) active[rhs] = 0;
+  }
+}
+
+// From the previous update's partials [|r|^2, rt^H r]: stopping tests, beta,
+// uu = r + beta q and p = uu + beta (q + beta p).
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cgs_p(const cx<R>* __restrict__ r, const cx<R>* __restrict__ q,
+                                                       cx<R>* __restrict__ uu, cx<R>* __restrict__ p,
+                                                       const c64* __restrict__ pupd,
+                                                       const CgsState* __restrict__ sin,
+                                                       CgsState* __restrict__ sout, int* __restrict__ active,
+                                                       SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[2];
+  reduce_all<2>(pupd, dm.nblk, rhs, red);
+  CgsState s = sin[rhs];
+  s.iters += 1;
+  s.rnorm2 = red[0].x;
+  s.rho_old = s.rho;
+  s.rho = red[1];
+  int stop = 0;
+  if (!isfinite(red[0].x)) {
+    s.breakdown = 1;
+    stop = 1;
+  } else if (s.rnorm2 <= s.tol2) {
+    s.converged = 1;
+    stop = 1;
+  } else if (s.rnorm2 < 0.98 * s.best2) {
+    s.best2 = s.rnorm2;
+    s.best_it = s.iters;
+  } else if (s.iters - s.best_it > kStallWindow && s.rnorm2 < stall_level2<R>() * s.bnorm2) {
+    s.breakdown = 2;  // stagnated
+    stop = 1;
+  }
+  if (!stop) {
+    if (tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32)) {
+      s.breakdown = 1;  // rt^H r = 0: restart from the current iterate
+      stop = 1;
+    } else {
+      s.beta = s.iters > 0 ? cdiv(s.rho, s.rho_old) : mk(0.0, 0.0);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+    if (stop) active[rhs] = 0;
+  }
+  if (stop) return;
+  const cx<R> be = cvt<R>(s.beta);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> qi = q[o + i];
+    const cx<R> ui = r[o + i] + be * qi;
+    uu[o + i] = ui;
+    p[o + i] = ui + be * (qi + be * p[o + i]);
+  }
+}
+
+// alpha = rho / rt^H v (partials from the product, nblk_mv blocks, stride 2);
+// q = uu - alpha v;  w = uu + q;  u += alpha w
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cgs_q(const cx<R>* __restrict__ uu, const cx<R>* __restrict__ v,
+                                                       cx<R>* __restrict__ q, cx<R>* __restrict__ w,
+                                                       cx<R>* __restrict__ u, const c64* __restrict__ pdot,
+                                                       int nblk_mv, const CgsState* __restrict__ sin,
+                                                       CgsState* __restrict__ sout, int* __restrict__ active,
+                                                       SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[2];
+  reduce_all<2>(pdot, nblk_mv, rhs, red);
+  CgsState s = sin[rhs];
+  const bool bad = tiny(red[0], s.bnorm2 * s.bnorm2 * 1e-32) || !isfinite(red[0].x);
+  if (bad) s.breakdown = 1;
+  else s.alpha = cdiv(s.rho, red[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+    if (bad) active[rhs] = 0;
+  }
+  if (bad) return;
+  const cx<R> al = cvt<R>(s.alpha);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> ui = uu[o + i];
+    const cx<R> qi = ui - al * v[o + i];
+    q[o + i] = qi;
+    const cx<R> wi = ui + qi;
+    w[o + i] = wi;
+    u[o + i] = u[o + i] + al * wi;
+  }
+}
+
+// r -= alpha t (t = A w); partials [|r|^2, rt^H r]
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_cgs_update(cx<R>* __restrict__ r, const cx<R>* __restrict__ t,
+                                                            const cx<R>* __restrict__ rt,
+                                                            const CgsState* __restrict__ sin,
+                                                            const int* __restrict__ active, SolverDims dm,
+                                                            c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const cx<R> al = cvt<R>(sin[rhs].alpha);
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> rn = r[o + i] - al * t[o + i];
+    r[o + i] = rn;
+    const c64 rd = up(rn);
+    acc[0].x += abs2(rd);
+    acc[1] = acc[1] + conjg(up(rt[o + i])) * rd;
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+// ============================================================================
 // QMR for complex-symmetric matrices (Freund 1992): Lanczos with the bilinear
 // form x^T y and Euclidean-normalised vectors v_n = vt_n / rho_n, the
 // tridiagonal matrix reduced by Givens rotations, iterate u_n updated through
