@@ -249,8 +249,8 @@ def bench_paper200(args):
     torch.cuda.synchronize()
     t_spec = time.perf_counter() - t0
     paper = {"bicg_sym": (21, 741.5, 212.7), "bicgstab": (12, 846.6, 234.7), "cgs": (13, 911.3, 257.4),
-             "qmr_sym": (21, 759.6, 216.7)}
-    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "cgs": "cgs", "qmr_sym": "qmr"}
+             "qmr_sym": (21, 759.6, 216.7), "tfqmr": (13, 1850.3, 524.7)}
+    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "cgs": "cgs", "qmr_sym": "qmr", "tfqmr": "tfqmr"}
     out = {}
     for solver, (ni, ser, omp) in paper.items():
         kw = dict(khat=w["khat"], ehat=w["ehat"], solver=name[solver], precision="fp64", tol=1e-10, check_every=4,
@@ -291,7 +291,7 @@ def main():
                     help="single: one right-hand side of --workload (the headline line); batch-rhs: all "
                          "orientations of --workload in one multi-RHS solve; batch-targets: 40 seeded "
                          "aggregates through the multi-target batch solve; paper200: the paper's Table 3 "
-                         "benchmark solve (200^3 sphere, FP64, tol 1e-10) with BiCG_sym, BiCGSTAB, CGS, QMR_sym")
+                         "benchmark solve (200^3 sphere, FP64, tol 1e-10) with BiCG_sym, BiCGSTAB, CGS, QMR_sym, TFQMR")
     ap.add_argument("--nrhs", type=int, default=0, help="batch-rhs: right-hand sides (default: all)")
     ap.add_argument("--workers", type=int, default=0, help="batch-targets: host workers (default 4)")
     args = ap.parse_args()

@@ -49,11 +49,11 @@ enum {
 
 enum { DDA_FP64 = 0, DDA_FP32 = 1 };                       /* vector precision   */
 enum { DDA_POL_CM = 0, DDA_POL_RR = 1, DDA_POL_LDR = 2 };  /* polarisability     */
-/* Krylov solvers (schemes of Sec. 4): BiCGSTAB (van der Vorst 1992) and CGS
- * (Sonneveld 1989), two products per iteration; QMR_sym and BiCG_sym
- * (Freund 1992a; complex-symmetric, one product per iteration, bilinear form
- * x^T y). */
-enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1, DDA_BICG_SYM = 2, DDA_CGS = 3 };
+/* Krylov solvers (schemes of Sec. 4): BiCGSTAB (van der Vorst 1992), CGS
+ * (Sonneveld 1989) and TFQMR (Freund 1993), two products per iteration;
+ * QMR_sym and BiCG_sym (Freund 1992a; complex-symmetric, one product per
+ * iteration, bilinear form x^T y). */
+enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1, DDA_BICG_SYM = 2, DDA_CGS = 3, DDA_TFQMR = 4 };
 enum { DDA_SOLVE_FP64 = 0, DDA_SOLVE_MIXED = 1 };          /* solve precision    */
 
 typedef struct dda_lib dda_lib;
@@ -104,7 +104,7 @@ int dda_matvec(dda_target *t, int precision, int nrhs, const double *S, int jaco
                void *y_dev, void *hip_stream);
 
 typedef struct {
-  int solver;        /* DDA_BICGSTAB, DDA_QMR_SYM, DDA_BICG_SYM or DDA_CGS        */
+  int solver;        /* DDA_BICGSTAB, DDA_QMR_SYM, DDA_BICG_SYM, DDA_CGS, DDA_TFQMR */
   int precision;     /* DDA_SOLVE_FP64, or DDA_SOLVE_MIXED (FP32 inner, FP64 outer) */
   int max_iter;      /* total inner iterations per right-hand side (<= 0: 10000)  */
   int max_outer;     /* refinement steps (<= 0: 20)                               */

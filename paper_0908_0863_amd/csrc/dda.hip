@@ -706,7 +706,8 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
-  CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState), sizeof(CgsState)})));
+  CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState), sizeof(CgsState),
+                                             sizeof(TfqState)})));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
   CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
   t->h_active.resize(cap);
@@ -1281,7 +1282,7 @@ template <typename R>
 static int ensure_solver_ws(dda_target* t, int nrhs) {
   PrecBufs<R>& b = bufs<R>(t);
   if (nrhs <= b.vec_cap) return DDA_OK;
-  CHK(b.vec.ensure((size_t)9 * nrhs * 3 * t->nd * sizeof(cx<R>)));
+  CHK(b.vec.ensure((size_t)10 * nrhs * 3 * t->nd * sizeof(cx<R>)));
   b.vec_cap = nrhs;
   return DDA_OK;
 }
@@ -1329,7 +1330,8 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   const bool bcg = solver == DDA_BICGSTAB;
   const bool cgs = solver == DDA_BICG_SYM;
   const bool sq = solver == DDA_CGS;
-  const int mv_per_iter = (bcg || sq) ? 2 : 1;
+  const bool tf = solver == DDA_TFQMR;
+  const int mv_per_iter = (bcg || sq || tf) ? 2 : 1;
 
   // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
   CHK(autotune<R>(t, nrhs, dS, jacobi, slot(0), slot(4), st));
@@ -1343,6 +1345,18 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
                        R3);
     hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
+  } else if (tf) {
+    // slot 2 = rt, 3 = w, 4 = ue, 5 = uo, 6 = v, 7 = d, 8 = A ue, 9 = A uo;
+    // the first product A ue (with rt^H A ue) completes the initialisation
+    TfqState* S0 = t->state.as<TfqState>();
+    hipLaunchKernelGGL((k_tfq_init<R>), vg, dim3(kRedThreads), 0, st, b, u, slot(2), slot(3), slot(4), slot(5),
+                       slot(6), slot(7), slot(9), act, dm, R3);
+    hipLaunchKernelGGL(k_tfq_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
+    DotArgs d0;
+    d0.mode = DOT_HA;
+    d0.a = slot(2);
+    d0.part = M1;
+    CHK(matvec_T<R>(t, nrhs, dS, jacobi, slot(4), slot(8), act, st, d0));
   } else if (sq) {
     // slot 2 = r, 3 = rt, 4 = p, 5 = q, 6 = uu, 7 = v and t, 8 = w
     CgsState* S0 = t->state.as<CgsState>();
@@ -1382,6 +1396,26 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, r, tt, act, s, d2));
       hipLaunchKernelGGL((k_bcg_update<R>), vg, dim3(kRedThreads), 0, s, u, r, p, tt, rhat, R1, M1, nblk_mv, SA, SB, act, dm,
                          R3);
+    } else if (tf) {
+      TfqState* SA = t->state.as<TfqState>() + (par ? nrhs : 0);
+      TfqState* SB = t->state.as<TfqState>() + (par ? 0 : nrhs);
+      cx<R>*rt = slot(2), *w = slot(3), *ue = slot(4), *uo = slot(5), *v = slot(6), *d = slot(7), *aue = slot(8),
+           *auo = slot(9);
+      hipLaunchKernelGGL((k_tfq_a<R>), vg, dim3(kRedThreads), 0, s, ue, aue, auo, v, uo, w, d, M1, nblk_mv, SA, SB,
+                         act, dm, R1);
+      DotArgs d1;
+      d1.mode = DOT_HA;
+      d1.a = rt;
+      d1.part = M0;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, uo, auo, act, s, d1));
+      hipLaunchKernelGGL((k_tfq_b<R>), vg, dim3(kRedThreads), 0, s, u, uo, auo, rt, w, d, R1, M0, nblk_mv, SB, SA,
+                         act, dm, R3);
+      hipLaunchKernelGGL((k_tfq_c<R>), vg, dim3(kRedThreads), 0, s, u, d, w, uo, ue, R3, SA, SB, act, dm);
+      DotArgs d2;
+      d2.mode = DOT_HA;
+      d2.a = rt;
+      d2.part = M1;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, ue, aue, act, s, d2));
     } else if (sq) {
       // two state writes per iteration: the newest state is back in SA
       CgsState* SA = t->state.as<CgsState>();
@@ -1512,6 +1546,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   if (bcg) return collect(t->state.as<BcgState>(), BcgState{});
   if (cgs) return collect(t->state.as<CgState>(), CgState{});
   if (sq) return collect(t->state.as<CgsState>(), CgsState{});
+  if (tf) return collect(t->state.as<TfqState>(), TfqState{});
   return collect(t->state.as<QmrState>(), QmrState{});
 }
 
@@ -1686,7 +1721,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
 
 static int check_opts(const dda_solve_opts* opts, const char* who) {
   if (!opts) return fail(DDA_EINVAL, "%s: opts is NULL", who);
-  if (opts->solver < DDA_BICGSTAB || opts->solver > DDA_CGS)
+  if (opts->solver < DDA_BICGSTAB || opts->solver > DDA_TFQMR)
     return fail(DDA_EINVAL, "%s: solver %d", who, opts->solver);
   if (opts->precision != DDA_SOLVE_FP64 && opts->precision != DDA_SOLVE_MIXED)
     return fail(DDA_EINVAL, "%s: precision %d", who, opts->precision);

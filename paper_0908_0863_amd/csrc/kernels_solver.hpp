@@ -656,6 +656,260 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_update(cx<R>* __restrict__ 
   }
 }
 // ============================================================================
+// TFQMR, transpose-free QMR (Freund 1993): two products per iteration, shadow
+// vector rt = r_0 with Hermitian inner products.  Half-steps m = 0, 1, ...
+// with u_m = ue (m even) or uo (m odd):
+//   m even: alpha = rho / rt^H v;  uo = ue - alpha v
+//   w -= alpha A u_m;  d = u_m + (theta^2 / alpha) eta d
+//   theta' = |w| / tau;  c = (1 + theta'^2)^{-1/2};  tau' = tau theta' c;
+//   eta' = c^2 alpha;  x += eta' d
+//   m odd:  rho' = rt^H w;  beta = rho' / rho;  ue = w + beta uo;
+//           v = A ue + beta (A uo + beta v)
+// rt^H v is carried by the recurrence sigma' = rt^H A ue + beta (rt^H A uo +
+// beta sigma), both inner products fused into the products.  Stopping on the
+// residual bound |r_m| <= sqrt(m + 1) tau_m.  A right-hand side that meets it
+// after its x update only marks the state; the next iteration's first kernel,
+// where no block does vector work, clears `active`, so no block of an
+// updating kernel can miss its update.
+// ============================================================================
+struct TfqState {
+  c64 rho, sigma, s_uo, alpha, beta, eta;
+  double tau, theta, bnorm2, tol2, best2, rnorm2;
+  int m, converged, breakdown, iters, best_it;
+  int ver;  // incremented by every kernel that writes the state
+};
+
+// Close a half-step from |w|^2: theta, c, tau, eta = c^2 alpha; true when the
+// residual bound meets the tolerance.
+__device__ inline bool tfq_close(TfqState& s, double w2) {
+  const double th = sqrt(w2) / s.tau;
+  const double c2 = 1.0 / (1.0 + th * th);
+  s.tau = s.tau * th * sqrt(c2);
+  s.theta = th;
+  s.eta = c2 * s.alpha;
+  s.m += 1;
+  s.rnorm2 = s.tau * s.tau * (double)(s.m + 1);
+  s.iters = (s.m + 1) / 2;
+  return s.rnorm2 <= s.tol2 || !(w2 > 0.0);
+}
+
+// x = 0, ue = w = rt = b, uo = v = d = A uo = 0; partials [|b|^2, 0]
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_tfq_init(const cx<R>* __restrict__ b, cx<R>* __restrict__ x,
+                                                          cx<R>* __restrict__ rt, cx<R>* __restrict__ w,
+                                                          cx<R>* __restrict__ ue, cx<R>* __restrict__ uo,
+                                                          cx<R>* __restrict__ v, cx<R>* __restrict__ d,
+                                                          cx<R>* __restrict__ auo, const int* __restrict__ active,
+                                                          SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  c64 acc[1] = {mk(0.0, 0.0)};
+  if (active[rhs]) {
+    const long o = (long)rhs * dm.n3;
+    const cx<R> z = mk((R)0, (R)0);
+    DDA_RANGE(dm, i) {
+      const cx<R> bv = b[o + i];
+      x[o + i] = z;
+      rt[o + i] = bv;
+      w[o + i] = bv;
+      ue[o + i] = bv;
+      uo[o + i] = z;
+      v[o + i] = z;
+      d[o + i] = z;
+      auo[o + i] = z;
+      acc[0].x += abs2(up(bv));
+    }
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = mk(0.0, 0.0);
+  }
+}
+
+__global__ void k_tfq_fin_init(const c64* __restrict__ part, int nblk, TfqState* __restrict__ st,
+                               int* __restrict__ active, const double* __restrict__ tolv) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 v[2];
+  reduce_partials<2>(part, nblk, rhs, v);
+  if (threadIdx.x == 0) {
+    TfqState s;
+    const double nb2 = v[0].x;
+    s.bnorm2 = nb2;
+    s.rnorm2 = nb2;
+    const double tol = tolv[rhs];
+    s.tol2 = tol * tol * nb2;
+    s.best2 = nb2;
+    s.best_it = 0;
+    s.rho = mk(nb2, 0.0);  // rt^H r_0
+    s.sigma = mk(0.0, 0.0);
+    s.s_uo = mk(0.0, 0.0);
+    s.alpha = mk(0.0, 0.0);
+    s.beta = mk(0.0, 0.0);
+    s.eta = mk(0.0, 0.0);
+    s.tau = sqrt(nb2);
+    s.theta = 0.0;
+    s.m = 0;
+    s.converged = nb2 == 0.0;
+    s.breakdown = 0;
+    s.iters = 0;
+    s.ver = 0;
+    st[rhs] = s;
+    if (s.converged) active[rhs] = 0;
+  }
+}
+
+// First kernel of an iteration (half-step m even opens).  pue: rt^H A ue
+// (nblk_mv blocks, stride 2).  sigma, v = A ue + beta (A uo + beta v),
+// alpha = rho / sigma, uo = ue - alpha v, w -= alpha A ue,
+// d = ue + (theta^2 / alpha) eta d;  partials [|w|^2, 0].
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_tfq_a(const cx<R>* __restrict__ ue, const cx<R>* __restrict__ aue,
+                                                       const cx<R>* __restrict__ auo, cx<R>* __restrict__ v,
+                                                       cx<R>* __restrict__ uo, cx<R>* __restrict__ w,
+                                                       cx<R>* __restrict__ d, const c64* __restrict__ pue,
+                                                       int nblk_mv, const TfqState* __restrict__ sin,
+                                                       TfqState* __restrict__ sout, int* __restrict__ active,
+                                                       SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 red[2];
+  reduce_all<2>(pue, nblk_mv, rhs, red);
+  TfqState s = sin[rhs];
+  int stop = s.converged || s.breakdown;
+  c64 dcoef = mk(0.0, 0.0);
+  if (!stop) {
+    s.sigma = red[0] + s.beta * (s.s_uo + s.beta * s.sigma);
+    if (tiny(s.sigma, s.bnorm2 * s.bnorm2 * 1e-32) || !isfinite(s.sigma.x) || !isfinite(s.sigma.y)) {
+      s.breakdown = 1;
+      stop = 1;
+    } else {
+      s.alpha = cdiv(s.rho, s.sigma);
+      dcoef = (s.theta * s.theta) * cdiv(s.eta, s.alpha);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+    if (stop) active[rhs] = 0;
+  }
+  if (stop) return;
+  const cx<R> be = cvt<R>(s.beta), al = cvt<R>(s.alpha), dc = cvt<R>(dcoef);
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> ai = aue[o + i];
+    const cx<R> vi = ai + be * (auo[o + i] + be * v[o + i]);
+    v[o + i] = vi;
+    const cx<R> ui = ue[o + i];
+    uo[o + i] = ui - al * vi;
+    const cx<R> wi = w[o + i] - al * ai;
+    w[o + i] = wi;
+    d[o + i] = ui + dc * d[o + i];
+    acc[0].x += abs2(up(wi));
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+// Half-step m closes (|w|^2 from pw; x += eta d); half-step m + 1 (odd)
+// opens: w -= alpha A uo, d = uo + (theta^2 / alpha) eta d; partials
+// [|w|^2, rt^H w].  rt^H A uo (puo) is kept for the sigma recurrence.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_tfq_b(cx<R>* __restrict__ x, const cx<R>* __restrict__ uo,
+                                                       const cx<R>* __restrict__ auo, const cx<R>* __restrict__ rt,
+                                                       cx<R>* __restrict__ w, cx<R>* __restrict__ d,
+                                                       const c64* __restrict__ pw, const c64* __restrict__ puo,
+                                                       int nblk_mv, const TfqState* __restrict__ sin,
+                                                       TfqState* __restrict__ sout, const int* __restrict__ active,
+                                                       SolverDims dm, c64* __restrict__ part) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 rw[2], ru[2];
+  reduce_all<2>(pw, dm.nblk, rhs, rw);
+  reduce_all<2>(puo, nblk_mv, rhs, ru);
+  TfqState s = sin[rhs];
+  if (s.converged || s.breakdown) return;
+  const bool conv = tfq_close(s, rw[0].x);
+  s.s_uo = ru[0];
+  if (conv) s.converged = 1;
+  const c64 dcoef = (s.theta * s.theta) * cdiv(s.eta, s.alpha);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+  }
+  const cx<R> et = cvt<R>(s.eta), al = cvt<R>(s.alpha), dc = cvt<R>(dcoef);
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    const cx<R> di = d[o + i];
+    x[o + i] = x[o + i] + et * di;
+    if (!conv) {
+      const cx<R> wi = w[o + i] - al * auo[o + i];
+      w[o + i] = wi;
+      d[o + i] = uo[o + i] + dc * di;
+      const c64 wd = up(wi);
+      acc[0].x += abs2(wd);
+      acc[1] = acc[1] + conjg(up(rt[o + i])) * wd;
+    }
+  }
+  if (conv) return;
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2] = acc[0];
+    part[((long)rhs * dm.nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+// Half-step m + 1 closes (x += eta d); then rho' = rt^H w, beta = rho'/rho,
+// ue = w + beta uo (the next product's input).
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_tfq_c(cx<R>* __restrict__ x, const cx<R>* __restrict__ d,
+                                                       const cx<R>* __restrict__ w, const cx<R>* __restrict__ uo,
+                                                       cx<R>* __restrict__ ue, const c64* __restrict__ pw,
+                                                       const TfqState* __restrict__ sin, TfqState* __restrict__ sout,
+                                                       const int* __restrict__ active, SolverDims dm) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  c64 rw[2];
+  reduce_all<2>(pw, dm.nblk, rhs, rw);
+  TfqState s = sin[rhs];
+  if (s.converged || s.breakdown) return;
+  const bool conv = tfq_close(s, rw[0].x);
+  bool upd = !conv;
+  if (conv) {
+    s.converged = 1;
+  } else {
+    const c64 rho_new = rw[1];
+    if (tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32) || !isfinite(rho_new.x)) {
+      s.breakdown = 1;
+      upd = false;
+    } else {
+      s.beta = cdiv(rho_new, s.rho);
+      s.rho = rho_new;
+    }
+    if (s.rnorm2 < 0.98 * s.best2) {
+      s.best2 = s.rnorm2;
+      s.best_it = s.iters;
+    } else if (s.iters - s.best_it > kStallWindow && s.rnorm2 < stall_level2<R>() * s.bnorm2) {
+      s.breakdown = 2;  // stagnated
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.ver += 1;
+    sout[rhs] = s;
+  }
+  const cx<R> et = cvt<R>(s.eta), be = cvt<R>(s.beta);
+  const long o = (long)rhs * dm.n3;
+  DDA_RANGE(dm, i) {
+    x[o + i] = x[o + i] + et * d[o + i];
+    if (upd) ue[o + i] = w[o + i] + be * uo[o + i];
+  }
+}
+// ============================================================================
 // QMR for complex-symmetric matrices (Freund 1992): Lanczos with the bilinear
 // form x^T y and Euclidean-normalised vectors v_n = vt_n / rho_n, the
 // tridiagonal matrix reduced by Givens rotations, iterate u_n updated through

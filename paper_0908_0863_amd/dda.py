@@ -23,12 +23,12 @@ LIB_PATH = os.path.join(HERE, "libdda.so")
 DDA_OK, DDA_EINVAL, DDA_ENOMEM, DDA_EDEVICE, DDA_ENOTCONV, DDA_ESTATE = 0, -1, -2, -3, -4, -5
 DDA_FP64, DDA_FP32 = 0, 1
 DDA_POL_CM, DDA_POL_RR, DDA_POL_LDR = 0, 1, 2
-DDA_BICGSTAB, DDA_QMR_SYM, DDA_BICG_SYM, DDA_CGS = 0, 1, 2, 3
+DDA_BICGSTAB, DDA_QMR_SYM, DDA_BICG_SYM, DDA_CGS, DDA_TFQMR = 0, 1, 2, 3, 4
 DDA_SOLVE_FP64, DDA_SOLVE_MIXED = 0, 1
 
 _PRESC = {"cm": DDA_POL_CM, "rr": DDA_POL_RR, "ldr": DDA_POL_LDR}
 _SOLVER = {"bicgstab": DDA_BICGSTAB, "qmr": DDA_QMR_SYM, "qmr_sym": DDA_QMR_SYM, "bicg_sym": DDA_BICG_SYM,
-           "cocg": DDA_BICG_SYM, "cgs": DDA_CGS}
+           "cocg": DDA_BICG_SYM, "cgs": DDA_CGS, "tfqmr": DDA_TFQMR}
 _SPREC = {"fp64": DDA_SOLVE_FP64, "mixed": DDA_SOLVE_MIXED}
 
 

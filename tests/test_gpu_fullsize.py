@@ -182,13 +182,13 @@ def test_autograd_gradcheck_sphere10(lib):
 @pytest.mark.timeout(600)
 def test_iteration_counts_sphere200_table3(lib):
     """The paper's benchmark solve (Table 3): iteration counts of BiCG_sym,
-    BiCGSTAB, CGS and QMR_sym within 50% of the printed ones (the paper leaves the
+    BiCGSTAB, CGS, QMR_sym and TFQMR within 50% of the printed ones (the paper leaves the
     stopping rule and the polarisability unstated, so only the scale is
     fixed)."""
     w = inputs.workload("sphere200")
     t, nd = _target(lib, w)
     assert nd == 4188896
-    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "qmr_sym": "qmr", "cgs": "cgs"}
+    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "qmr_sym": "qmr", "cgs": "cgs", "tfqmr": "tfqmr"}
     for solver, ni in read_golden("table3_iterations.txt"):
         P, info = t.solve(khat=w["khat"], ehat=w["ehat"], solver=name[solver], precision="fp64", tol=1e-10)
         it = info[0]["iterations"]

@@ -125,7 +125,7 @@ def test_symmetry_of_gpu_matvec(lib):
     assert abs(a - b) <= 1e-12 * abs(a)
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs"])
+@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
 def test_solve_fp64_sphere16_matches_lu(lib, solver):
     w = inputs.workload("sphere16")
     eps = w["m"] ** 2
@@ -144,7 +144,7 @@ def test_solve_fp64_sphere16_matches_lu(lib, solver):
         assert _rel(P[r], Po) < 1e-10
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs"])
+@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
 def test_solve_mixed_sphere16(lib, solver):
     w = inputs.workload("sphere16")
     eps = w["m"] ** 2
@@ -197,7 +197,7 @@ def test_gradient_matches_dense_adjoint_sphere10(lib):
     assert _rel(g[0], go) < 1e-9
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs"])
+@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_replay_matches_eager(lib, solver, precision):
     """The captured iteration (HIP graph, replayed several times with eager
