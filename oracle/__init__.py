@@ -149,12 +149,31 @@ def neg_green_many(k: float, rx, ry, rz) -> np.ndarray:
     return out
 
 
+def _diag3(ainv, nd) -> np.ndarray:
+    """alpha^{-1} as [3][N_d] (per component of each dipole); an [N_d] or
+    scalar argument is an isotropic polarisability, the same on all three."""
+    a = np.asarray(ainv, np.complex128)
+    if a.ndim == 2:
+        return np.ascontiguousarray(a.reshape(3, nd))
+    return np.ascontiguousarray(np.broadcast_to(a, (nd,))[None, :].repeat(3, axis=0))
+
+
+def alpha_inv_composition(eps_materials, flags, kd: float, prescription: str = "ldr", S: float = 0.0):
+    """alpha^{-1} [3][N_d] of a multi-material, anisotropic target: each dipole
+    carries a material index per direction x, y, z (Sec. 2), flags [3][N_d];
+    component c of dipole n takes the prescription at eps_materials[flags[c, n]]
+    (the polarisability tensor is diagonal in the lattice axes)."""
+    em = np.asarray(eps_materials, np.complex128)
+    return alpha_inv(em[np.asarray(flags)], kd, prescription, S)
+
+
 def dense_matvec(sites, k, ainv, x, rows=None, nthreads: int = 0) -> np.ndarray:
     """y = A x by direct O(N_d^2) double summation (Eq. 1).  With ``rows`` only
-    those dipoles' rows are formed (y is then [3][len(rows)])."""
+    those dipoles' rows are formed (y is then [3][len(rows)]).  ainv: [N_d]
+    (isotropic) or [3][N_d] (per component)."""
     sites = np.ascontiguousarray(sites, dtype=np.int32)
     nd = sites.shape[0]
-    ainv = np.ascontiguousarray(np.broadcast_to(np.asarray(ainv, np.complex128), (nd,)))
+    ainv = _diag3(ainv, nd)
     x = np.ascontiguousarray(x, dtype=np.complex128).reshape(3, nd)
     if rows is None:
         y = np.zeros((3, nd), dtype=np.complex128)
@@ -171,7 +190,7 @@ def dense_matrix(sites, k, ainv) -> np.ndarray:
     """The explicit 3N_d x 3N_d matrix of Eq. 1, index (c*N_d + n, c'*N_d + m)."""
     sites = np.ascontiguousarray(sites, dtype=np.int32)
     nd = sites.shape[0]
-    ainv = np.ascontiguousarray(np.broadcast_to(np.asarray(ainv, np.complex128), (nd,)))
+    ainv = _diag3(ainv, nd)
     A = np.zeros((3 * nd, 3 * nd), dtype=np.complex128)
     _lib().ora_dense_matrix(nd, _p(sites), float(k), _p(ainv), _p(A))
     return A
@@ -289,9 +308,8 @@ def c_ext(k, E, P) -> float:
 def c_abs(k, ainv, P) -> float:
     """C_abs = 4 pi k sum_n |P_n|^2 (-Im alpha_n^{-1} - (2/3) k^3), isotropic alpha."""
     nd = P.shape[-1]
-    ainv = np.broadcast_to(np.asarray(ainv, np.complex128), (nd,))
-    w = -np.imag(ainv) - (2.0 / 3.0) * k ** 3
-    return float(4.0 * math.pi * k * np.sum(w[None, :] * np.abs(P) ** 2))
+    w = -np.imag(_diag3(ainv, nd)) - (2.0 / 3.0) * k ** 3
+    return float(4.0 * math.pi * k * np.sum(w * np.abs(np.reshape(P, (3, nd))) ** 2))
 
 
 def quadrature_sizes(sites, k):

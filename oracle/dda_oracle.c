@@ -93,7 +93,8 @@ static void neg_green_3x3(double k, double rx, double ry, double rz, cplx t[3][3
 
 /*
  * y = A x on a subset of rows (dipoles `rows[0..nrows)`, or all dipoles when
- * rows == NULL).  sites: int32 [nd][3]; ainv: complex [nd] (alpha^{-1});
+ * rows == NULL).  sites: int32 [nd][3]; ainv: complex [3][nd] (alpha^{-1} of
+ * each component of each dipole: a diagonal polarisability tensor, Sec. 2);
  * x: complex [3][nd]; y: complex [3][nrows].  Direct double summation.
  */
 void ora_dense_matvec(int64_t nd, const int32_t *sites, double k, const double *ainv,
@@ -128,7 +129,7 @@ void ora_dense_matvec(int64_t nd, const int32_t *sites, double k, const double *
         }
         for (int a = 0; a < 3; ++a) {
             tot[a] += blk[a];
-            yc[a * nrows + q] = ai[n] * xc[a * nd + n] + tot[a];
+            yc[a * nrows + q] = ai[a * nd + n] * xc[a * nd + n] + tot[a];
         }
     }
 }
@@ -147,7 +148,7 @@ void ora_dense_matrix(int64_t nd, const int32_t *sites, double k, const double *
             cplx t[3][3];
             if (m == n) {
                 for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) t[a][b] = (a == b) ? ai[n] : 0;
+                    for (int b = 0; b < 3; ++b) t[a][b] = (a == b) ? ai[a * nd + n] : 0;
             } else {
                 neg_green_3x3(k, (double)(sites[3 * n] - sites[3 * m]),
                               (double)(sites[3 * n + 1] - sites[3 * m + 1]),

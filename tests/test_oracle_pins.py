@@ -359,3 +359,37 @@ def test_mueller_of_a_pure_amplitude_matrix():
     M = ora.mueller_from_amplitude(S)
     np.testing.assert_allclose(np.sum(M ** 2, axis=(1, 2)), 4 * M[:, 0, 0] ** 2, rtol=1e-12)
     np.testing.assert_allclose(ora.mueller_from_amplitude([[1, 1, 0, 0]])[0], np.eye(4), atol=1e-15)
+
+
+# --- anisotropic, multi-material composition (Sec. 2: a material per direction)
+
+def test_single_anisotropic_dipole_closed_form():
+    """alpha = diag(ax, ay, az): an x-polarised wave along z excites P = ax x,
+    a y-polarised one P = ay y; C_ext = 4 pi k Im(a_c), C_sca = (8 pi/3) k^4 |a_c|^2."""
+    k = 0.4
+    a = np.array([0.8 + 0.3j, 0.2 + 0.05j, 1.1 + 0.7j])
+    ainv = (1.0 / a).reshape(3, 1)
+    site = np.zeros((1, 3), np.int32)
+    for c, e in ((0, [1, 0, 0]), (1, [0, 1, 0])):
+        E = ora.einc(site, k, [0, 0, 1], e)
+        P = ora.solve_dense(site, k, ainv, E)
+        assert P[c, 0] == pytest.approx(a[c], rel=1e-14)
+        assert ora.c_ext(k, E, P) == pytest.approx(4 * math.pi * k * a[c].imag, rel=1e-13)
+        csca = ora.c_sca_quadrature(site, k, P)
+        assert csca == pytest.approx(8 * math.pi / 3 * k ** 4 * abs(a[c]) ** 2, rel=1e-12)
+
+
+def test_composition_reduces_to_isotropic_and_keeps_the_optical_theorem():
+    sites = _cluster(24, seed=4)
+    k, S = 0.6, 0.0
+    mats = [2.3 + 0.4j, 1.7 + 0.05j]
+    iso = ora.alpha_inv_composition(mats, np.zeros((3, 24), int), k, "ldr", S)
+    np.testing.assert_array_equal(iso, np.broadcast_to(ora.alpha_inv(mats[0], k, "ldr", S), (3, 24)))
+    flags = np.random.default_rng(3).integers(0, 2, (3, 24))
+    ainv = ora.alpha_inv_composition(mats, flags, k, "ldr", S)
+    A = ora.dense_matrix(sites, k, ainv)
+    assert np.array_equal(A, A.T)
+    E = ora.einc(sites, k, [0, 0, 1], [1, 0, 0])
+    P = ora.solve_dense(sites, k, ainv, E)
+    cext, cabs = ora.c_ext(k, E, P), ora.c_abs(k, ainv, P)
+    assert cext == pytest.approx(cabs + ora.c_sca_quadrature(sites, k, P), rel=1e-11)
