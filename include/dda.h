@@ -67,7 +67,11 @@ void dda_close(dda_lib *lib);
 /* A target on a K x J x P lattice (K, J, P >= 1) with wavenumber kd > 0 in
  * units of the lattice spacing.  Chooses the padded FFT sizes
  * K'' >= 2K-1, J'' >= 2J-1, P'' >= 2P-1 (Sec. 3: any size >= 2n-1 embeds the
- * Toeplitz matrix in a circulant; the smallest 2^a 3^b 5^c length is used). */
+ * Toeplitz matrix in a circulant; the smallest 2^a 3^b 5^c length is used,
+ * or a length with register-resident kernels when it is at most 30% longer).
+ * The target uses its library until dda_target_destroy, which frees the
+ * target's device memory and may run after dda_close of the library; every
+ * other call on a target needs its library open. */
 int dda_target_create(dda_lib *lib, int K, int J, int P, double kd, dda_target **out);
 void dda_target_destroy(dda_target *t);
 
@@ -88,6 +92,16 @@ int dda_set_permittivity(dda_target *t, const double *eps, int prescription);
 
 /* Per-dipole polarisability alpha[2*N_d] (re, im), used as given. */
 int dda_set_polarizability(dda_target *t, const double *alpha);
+
+/* Multi-material, anisotropic composition (Sec. 2: every dipole carries a
+ * material index for each of the directions x, y, z).  eps[2*nmat] (re, im)
+ * the materials' permittivities (nmat <= 256); flags[3*N_d] the material
+ * index of component c of dipole n at c*N_d + n.  The polarisability tensor is
+ * diagonal in the lattice axes, component c taking the prescription (as for
+ * dda_set_permittivity) at its own material.  DDA_EINVAL for a flag >= nmat
+ * or a material without finite alpha^{-1}.  dda_grad_cabs_eps needs an
+ * isotropic dda_set_permittivity instead (DDA_ESTATE after this call). */
+int dda_set_composition(dda_target *t, int nmat, const double *eps, const uint8_t *flags, int prescription);
 
 /* Interaction spectrum (Sec. 3): the six tensor components' first columns
  * t = -G on [0,K)x[0,J)x[0,P), implicit Toeplitz-to-circulant conversion with

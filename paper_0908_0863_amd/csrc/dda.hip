@@ -208,6 +208,7 @@ struct PrecBufs {
 
 struct dda_target {
   dda_lib* lib = nullptr;
+  int device = 0;  // the library's device, kept so that destruction needs no library
   int K = 0, J = 0, P = 0;
   double kd = 0;
   int Kpp = 0, Jpp = 0, Ppp = 0, Kh = 0, Jh = 0, Ph = 0;
@@ -398,6 +399,7 @@ void dda_close(dda_lib* lib) {
   for (hipEvent_t e : lib->ev_pool) (void)hipEventDestroy(e);
   for (hipStream_t w : lib->workers) (void)hipStreamDestroy(w);
   delete lib;
+  (void)hipGetLastError();  // leave no error state behind for later launches
 }
 
 int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target** out) {
@@ -409,6 +411,7 @@ int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target**
   HIPCHK(hipSetDevice(lib->device));
   dda_target* t = new dda_target();
   t->lib = lib;
+  t->device = lib->device;
   t->K = K;
   t->J = J;
   t->P = P;
@@ -451,8 +454,9 @@ int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target**
 
 void dda_target_destroy(dda_target* t) {
   if (!t) return;
-  (void)hipSetDevice(t->lib->device);
+  (void)hipSetDevice(t->device);
   delete t;
+  (void)hipGetLastError();  // leave no error state behind for later launches
 }
 
 int dda_target_set_option(dda_target* t, int option, int value) {
@@ -530,8 +534,22 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   return DDA_OK;
 }
 
-static int upload_diag(dda_target* t, const std::vector<c64>& a0, const std::vector<c64>* a1) {
-  const size_t nd = (size_t)t->nd;
+// Diagonal alpha^{-1} = a0 + S a1 as [3][N_d] (one value per component and
+// dipole); per-dipole (isotropic) inputs of N_d entries are repeated.
+static int upload_diag(dda_target* t, std::vector<c64> a0, const std::vector<c64>* a1_in) {
+  const size_t nd = (size_t)t->nd * 3;
+  std::vector<c64> a1v;
+  const std::vector<c64>* a1 = a1_in;
+  if (a0.size() * 3 == nd) {
+    std::vector<c64> r(nd);
+    for (int c = 0; c < 3; ++c) std::copy(a0.begin(), a0.end(), r.begin() + (size_t)c * t->nd);
+    a0.swap(r);
+    if (a1_in) {
+      a1v.resize(nd);
+      for (int c = 0; c < 3; ++c) std::copy(a1_in->begin(), a1_in->end(), a1v.begin() + (size_t)c * t->nd);
+      a1 = &a1v;
+    }
+  }
   CHK(t->p64.a0.ensure(nd * sizeof(c64)));
   CHK(t->p32.a0.ensure(nd * sizeof(c32)));
   std::vector<c32> f(nd);
@@ -549,39 +567,41 @@ static int upload_diag(dda_target* t, const std::vector<c64>& a0, const std::vec
   return DDA_OK;
 }
 
+// alpha^{-1}(eps) = v + S s1 and its eps-derivative dv + S ds1 for the
+// published prescriptions (CM; Draine 1988 radiative reaction; Draine &
+// Goodman 1993 lattice dispersion relation), d = 1.  False at a pole.
+static bool alpha_inv_of(c64 e, int prescription, double kd, c64& v, c64& s1, c64& dv, c64& ds1) {
+  const double b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004;
+  const double kd2 = kd * kd, kd3 = kd2 * kd;
+  const c64 em1 = e - mk(1.0, 0.0);
+  if (!(abs2(em1) > 0.0)) return false;
+  v = (4.0 * M_PI / 3.0) * cdiv(e + mk(2.0, 0.0), em1);
+  dv = (-4.0 * M_PI) * cdiv(mk(1.0, 0.0), em1 * em1);
+  s1 = mk(0.0, 0.0);
+  ds1 = mk(0.0, 0.0);
+  if (prescription >= DDA_POL_RR) v = v + mk(0.0, -(2.0 / 3.0) * kd3);
+  if (prescription == DDA_POL_LDR) {
+    v = v + kd2 * (mk(b1, 0.0) + b2 * e);
+    dv = dv + mk(b2 * kd2, 0.0);
+    s1 = (b3 * kd2) * e;
+    ds1 = mk(b3 * kd2, 0.0);
+  }
+  return std::isfinite(v.x) && std::isfinite(v.y) && abs2(v) > 0.0;
+}
+
 int dda_set_permittivity(dda_target* t, const double* eps, int prescription) {
   if (!t || !eps) return fail(DDA_EINVAL, "dda_set_permittivity: NULL argument");
   if (t->nd <= 0) return fail(DDA_ESTATE, "dda_set_permittivity: occupancy not set");
   if (prescription < DDA_POL_CM || prescription > DDA_POL_LDR)
     return fail(DDA_EINVAL, "dda_set_permittivity: prescription %d", prescription);
   HIPCHK(hipSetDevice(t->lib->device));
-  // Published prescriptions (CM; Draine 1988 radiative reaction; Draine &
-  // Goodman 1993 lattice dispersion relation), d = 1.
-  const double b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004;
-  const double kd = t->kd, kd2 = kd * kd, kd3 = kd2 * kd;
   const size_t nd = (size_t)t->nd;
   std::vector<c64> a0(nd), a1(nd), d0(nd), d1(nd);
   for (size_t n = 0; n < nd; ++n) {
     const c64 e = mk(eps[2 * n], eps[2 * n + 1]);
-    const c64 em1 = e - mk(1.0, 0.0);
-    if (!(abs2(em1) > 0.0)) return fail(DDA_EINVAL, "dda_set_permittivity: eps = 1 at dipole %zu", n);
-    c64 cm = (4.0 * M_PI / 3.0) * cdiv(e + mk(2.0, 0.0), em1);
-    c64 v = cm;
-    c64 dv = (-4.0 * M_PI) * cdiv(mk(1.0, 0.0), em1 * em1);
-    c64 s1 = mk(0.0, 0.0), ds1 = mk(0.0, 0.0);
-    if (prescription >= DDA_POL_RR) v = v + mk(0.0, -(2.0 / 3.0) * kd3);
-    if (prescription == DDA_POL_LDR) {
-      v = v + kd2 * (mk(b1, 0.0) + b2 * e);
-      dv = dv + mk(b2 * kd2, 0.0);
-      s1 = (b3 * kd2) * e;
-      ds1 = mk(b3 * kd2, 0.0);
-    }
-    if (!std::isfinite(v.x) || !std::isfinite(v.y) || !(abs2(v) > 0.0))
+    if (!(abs2(e - mk(1.0, 0.0)) > 0.0)) return fail(DDA_EINVAL, "dda_set_permittivity: eps = 1 at dipole %zu", n);
+    if (!alpha_inv_of(e, prescription, t->kd, a0[n], a1[n], d0[n], d1[n]))
       return fail(DDA_EINVAL, "dda_set_permittivity: alpha^-1 not finite at dipole %zu", n);
-    a0[n] = v;
-    a1[n] = s1;
-    d0[n] = dv;
-    d1[n] = ds1;
   }
   const bool ldr = prescription == DDA_POL_LDR;
   CHK(upload_diag(t, a0, ldr ? &a1 : nullptr));
@@ -613,6 +633,34 @@ int dda_set_polarizability(dda_target* t, const double* alpha) {
   t->prescription = -1;
   t->have_alpha = true;
   t->have_eps = false;
+  return DDA_OK;
+}
+
+int dda_set_composition(dda_target* t, int nmat, const double* eps, const uint8_t* flags, int prescription) {
+  if (!t || !eps || !flags || nmat < 1 || nmat > 256) return fail(DDA_EINVAL, "dda_set_composition: bad arguments");
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_set_composition: occupancy not set");
+  if (prescription < DDA_POL_CM || prescription > DDA_POL_LDR)
+    return fail(DDA_EINVAL, "dda_set_composition: prescription %d", prescription);
+  HIPCHK(hipSetDevice(t->lib->device));
+  std::vector<c64> mv(nmat), ms(nmat);
+  for (int q = 0; q < nmat; ++q) {
+    c64 dv, ds;
+    if (!alpha_inv_of(mk(eps[2 * q], eps[2 * q + 1]), prescription, t->kd, mv[q], ms[q], dv, ds))
+      return fail(DDA_EINVAL, "dda_set_composition: material %d has no finite alpha^-1 (eps = 1 or a pole)", q);
+  }
+  const size_t nd = (size_t)t->nd;
+  std::vector<c64> a0(3 * nd), a1(3 * nd);
+  for (size_t e = 0; e < 3 * nd; ++e) {
+    const int q = flags[e];
+    if (q >= nmat) return fail(DDA_EINVAL, "dda_set_composition: flag %d at entry %zu (nmat %d)", q, e, nmat);
+    a0[e] = mv[q];
+    a1[e] = ms[q];
+  }
+  const bool ldr = prescription == DDA_POL_LDR;
+  CHK(upload_diag(t, a0, ldr ? &a1 : nullptr));
+  t->prescription = prescription;
+  t->have_alpha = true;
+  t->have_eps = false;  // the permittivity gradient is defined per isotropic dipole
   return DDA_OK;
 }
 

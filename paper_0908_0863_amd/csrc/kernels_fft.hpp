@@ -165,9 +165,11 @@ __global__ void __launch_bounds__(256) k_lines_strided(const cx<R>* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal alpha_n^{-1} of right-hand side r: a0[n] + S[r] a1[n] (the LDR term
-// b3 S eps (kd)^2 depends on the incident direction and polarisation).
-// Point-Jacobi in symmetric form uses s_n = (alpha_n^{-1})^{-1/2}.
+// Diagonal alpha^{-1} of right-hand side r at entry c N_d + n (component c of
+// dipole n; a diagonal polarisability tensor per dipole, so anisotropic and
+// multi-material targets, Sec. 2): a0 + S[r] a1 (the LDR term b3 S eps (kd)^2
+// depends on the incident direction and polarisation).  Point-Jacobi in
+// symmetric form uses s = (alpha^{-1})^{-1/2}.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ cx<R> diag_of(const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1, R S, long n) {
@@ -207,6 +209,7 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
   const int i0 = blockIdx.x * TX, k = blockIdx.y;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
+  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
   for (int idx = tid; idx < d.n * TX; idx += nthr) {
     const int e = idx / TX, l = idx - e * TX, i = i0 + l;
     cx<R> v = mk((R)0, (R)0);
@@ -214,7 +217,7 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
       const int m = map[((long)k * a.J + e) * a.K + i];
       if (m >= 0) {
         v = xv[m];
-        if (a.jacobi) v = jacobi_scale(diag_of(a0, a1, Sr, m)) * v;
+        if (a.jacobi) v = jacobi_scale(diag_of(a0, a1, Sr, cd + m)) * v;
       }
     }
     A[e * TX + l] = v;
@@ -281,6 +284,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
+  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   for (int idx = tid; idx < a.J * TX; idx += nthr) {
@@ -289,7 +293,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
     const int m = map[((long)k * a.J + e) * a.K + i];
     if (m < 0) continue;
     const cx<R> conv = sc * res[e * TX + l];
-    const cx<R> dg = diag_of(a0, a1, Sr, m);
+    const cx<R> dg = diag_of(a0, a1, Sr, cd + m);
     const cx<R> xm = xv[m];
     const cx<R> ym = a.jacobi ? xm + jacobi_scale(dg) * conv : dg * xm + conv;
     yv[m] = ym;

@@ -1235,11 +1235,10 @@ __global__ void k_scale_rhs(const c64* __restrict__ in, cx<R>* __restrict__ out,
   if (!active[rhs]) return;
   const long n3 = 3 * nd;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x) {
-    const long n = i % nd;
     c64 v = sc[rhs] * in[(long)rhs * n3 + i];
     if (jacobi) {
-      c64 a = a0[n];
-      if (a1) a = a + S[rhs] * a1[n];
+      c64 a = a0[i];
+      if (a1) a = a + S[rhs] * a1[i];
       v = cdiv(mk(1.0, 0.0), csqrt(a)) * v;
     }
     out[(long)rhs * n3 + i] = cvt<R>(v);
@@ -1256,11 +1255,10 @@ __global__ void k_accumulate(c64* __restrict__ P, const cx<R>* __restrict__ d, c
   if (!active[rhs]) return;
   const long n3 = 3 * nd;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n3; i += (long)gridDim.x * blockDim.x) {
-    const long n = i % nd;
     c64 v = sc[rhs] * up(d[(long)rhs * n3 + i]);
     if (jacobi) {
-      c64 a = a0[n];
-      if (a1) a = a + S[rhs] * a1[n];
+      c64 a = a0[i];
+      if (a1) a = a + S[rhs] * a1[i];
       v = cdiv(mk(1.0, 0.0), csqrt(a)) * v;
     }
     P[(long)rhs * n3 + i] = P[(long)rhs * n3 + i] + v;
@@ -1289,7 +1287,7 @@ __global__ void __launch_bounds__(kRedThreads) k_residual(const c64* __restrict_
 
 // Sums for the cross sections (Draine 1988, |E0| = 1):
 //   [0] sum Im(E^* . P)              -> C_ext = 4 pi k [0]
-//   [1] sum |P|^2 (-Im a_n - 2k^3/3)  -> C_abs = 4 pi k [1]
+//   [1] sum_c,n |P_cn|^2 (-Im a_cn - 2k^3/3)  -> C_abs = 4 pi k [1]
 __global__ void __launch_bounds__(kRedThreads) k_cross_sums(const c64* __restrict__ E, const c64* __restrict__ P,
                                                     const c64* __restrict__ a0, const c64* __restrict__ a1,
                                                     const double* __restrict__ S, long nd, double k,
@@ -1299,11 +1297,10 @@ __global__ void __launch_bounds__(kRedThreads) k_cross_sums(const c64* __restric
   const long o = (long)rhs * dm.n3;
   const double rad = (2.0 / 3.0) * k * k * k;
   DDA_RANGE(dm, i) {
-    const long n = i % nd;
     const c64 pv = P[o + i];
     acc[0].x += (conjg(E[o + i]) * pv).y;
-    c64 a = a0[n];
-    if (a1) a = a + S[rhs] * a1[n];
+    c64 a = a0[i];
+    if (a1) a = a + S[rhs] * a1[i];
     acc[1].x += abs2(pv) * (-a.y - rad);
   }
   block_sum<2>(acc);
@@ -1313,7 +1310,7 @@ __global__ void __launch_bounds__(kRedThreads) k_cross_sums(const c64* __restric
   }
 }
 
-// Adjoint right-hand side W conj(P), w_n = 4 pi k (-Im alpha_n^{-1} - 2k^3/3)
+// Adjoint right-hand side W conj(P), w_cn = 4 pi k (-Im alpha_cn^{-1} - 2k^3/3)
 __global__ void k_adjoint_rhs(const c64* __restrict__ P, c64* __restrict__ out, const c64* __restrict__ a0,
                               const c64* __restrict__ a1, const double* __restrict__ S, long nd, double k,
                               int nrhs) {
@@ -1321,9 +1318,9 @@ __global__ void k_adjoint_rhs(const c64* __restrict__ P, c64* __restrict__ out, 
   const double rad = (2.0 / 3.0) * k * k * k, fk = 4.0 * M_PI * k;
   for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < n3 * nrhs; g += (long)gridDim.x * blockDim.x) {
     const int rhs = (int)(g / n3);
-    const long n = (g % n3) % nd;
-    c64 a = a0[n];
-    if (a1) a = a + S[rhs] * a1[n];
+    const long e = g % n3;
+    c64 a = a0[e];
+    if (a1) a = a + S[rhs] * a1[e];
     out[g] = (fk * (-a.y - rad)) * conjg(P[g]);
   }
 }

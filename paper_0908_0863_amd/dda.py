@@ -61,7 +61,7 @@ class dda_batch_item(ctypes.Structure):
 
 # Every symbol the header declares (tests check that the library exports them).
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
-           "dda_set_permittivity", "dda_set_polarizability", "dda_build_spectrum", "dda_matvec", "dda_solve",
+           "dda_set_permittivity", "dda_set_polarizability", "dda_set_composition", "dda_build_spectrum", "dda_matvec", "dda_solve",
            "dda_batch_solve",
            "dda_incident_field", "dda_cross_sections", "dda_far_field", "dda_csca_quadrature", "dda_mueller",
            "dda_grad_cabs_eps", "dda_target_set_option",
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_set_occupancy": (i, [vp, vp, P(i64)]),
         "dda_set_permittivity": (i, [vp, vp, i]),
         "dda_set_polarizability": (i, [vp, vp]),
+        "dda_set_composition": (i, [vp, i, vp, vp, i]),
         "dda_build_spectrum": (i, [vp, vp]),
         "dda_matvec": (i, [vp, i, i, vp, i, vp, vp, vp]),
         "dda_solve": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp, vp, vp, vp]),
@@ -271,6 +272,13 @@ class Target:
     def set_polarizability(self, alpha):
         a = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, np.complex128), (self.nd,)))
         _check(load().dda_set_polarizability(self.h, _np_ptr(a)))
+
+    def set_composition(self, eps_materials, flags, prescription: str = "ldr"):
+        """Materials eps_materials [nmat] and the material index of every
+        component of every dipole, flags [3, N_d] (x, y, z)."""
+        e = np.ascontiguousarray(np.asarray(eps_materials, np.complex128).reshape(-1))
+        f = np.ascontiguousarray(np.asarray(flags, np.uint8).reshape(3, self.nd))
+        _check(load().dda_set_composition(self.h, e.size, _np_ptr(e), _np_ptr(f), _PRESC[prescription]))
 
     def build_spectrum(self):
         _check(load().dda_build_spectrum(self.h, _stream()))

@@ -245,3 +245,59 @@ def test_matvec_fused_and_five_pass_schedules(lib, shape, sched, jacobi):
         yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
         assert _rel(y[r], yo) < 1e-12, (shape, r)
         assert _rel(y32[r], yo) < 2e-6, (shape, r)
+
+
+# --- anisotropic, multi-material composition (Sec. 2) -------------------------
+
+def _composed(lib, shape, seed, kd, mats):
+    from paper_0908_0863_amd import dda
+    K, J, P = shape
+    occ = _rand_occ((P, J, K), seed)
+    t = dda.Target(lib, K, J, P, kd)
+    nd = t.set_occupancy(occ)
+    flags = np.random.default_rng(seed + 100).integers(0, len(mats), (3, nd))
+    t.set_composition(mats, flags, "ldr")
+    t.build_spectrum()
+    return t, nd, occ, flags
+
+
+@pytest.mark.parametrize("shape", [(7, 5, 9), (16, 5, 12), (32, 30, 5)])
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_matvec_composition_matches_dense(lib, shape, jacobi):
+    mats = [2.4 + 0.3j, 1.6 + 0.02j, 3.1 + 1.0j]
+    kd = 0.45
+    t, nd, occ, flags = _composed(lib, shape, 21, kd, mats)
+    sites = ora.sites_of(occ)
+    S = [0.0, 0.35]
+    x = inputs.complex_gaussian(22, (2, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv_composition(mats, flags, kd, "ldr", S[r])
+        s = 1.0 / np.sqrt(ainv) if jacobi else np.ones((3, nd))
+        yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
+        assert _rel(y[r], yo) < 1e-12, (shape, r)
+        assert _rel(y32[r], yo) < 2e-6, (shape, r)
+
+
+@pytest.mark.parametrize("solver", ["qmr", "bicgstab"])
+def test_solve_composition_matches_lu(lib, solver):
+    from paper_0908_0863_amd import dda
+    mats = [2.4 + 0.3j, 1.6 + 0.02j]
+    kd = 0.5
+    t, nd, occ, flags = _composed(lib, (12, 11, 10), 23, kd, mats)
+    sites = ora.sites_of(occ)
+    kh, eh = [0.0, 0.6, 0.8], [1.0, 0.0, 0.0]
+    S = ora.ldr_S(kh, eh)
+    E = t.incident_field([kh], [eh])
+    P, info = t.solve(einc=E, S=[S], solver=solver, precision="fp64", tol=1e-12)
+    ainv = ora.alpha_inv_composition(mats, flags, kd, "ldr", S)
+    Eo = ora.einc(sites, kd, kh, eh)
+    Po = ora.solve_dense(sites, kd, ainv, Eo)
+    assert _rel(P[0].cpu().numpy(), Po) < 1e-10
+    ce, ca, _ = t.cross_sections(E, P, S=[S])
+    assert ce[0] == pytest.approx(ora.c_ext(kd, Eo, Po), rel=1e-10)
+    assert ca[0] == pytest.approx(ora.c_abs(kd, ainv, Po), rel=1e-10)
+    with pytest.raises(dda.DDAError) as e:
+        t.grad_cabs_eps(P, S=[S])
+    assert e.value.code == dda.DDA_ESTATE
