@@ -217,6 +217,7 @@ struct dda_target {
   DevBuf map;    // int [P][J][K], -1 where empty
   DevBuf sites;  // int [nd] linear index
   bool have_alpha = false, have_eps = false, has_a1 = false;
+  bool aniso = false;  // the three components' diagonals differ (dda_set_composition)
   int prescription = -1;
   DevBuf d0, d1;  // d alpha^{-1} / d eps = d0 + S d1 (FP64)
   PrecBufs<double> p64;
@@ -613,6 +614,7 @@ int dda_set_permittivity(dda_target* t, const double* eps, int prescription) {
   }
   t->prescription = prescription;
   t->have_alpha = t->have_eps = true;
+  t->aniso = false;
   return DDA_OK;
 }
 
@@ -633,6 +635,7 @@ int dda_set_polarizability(dda_target* t, const double* alpha) {
   t->prescription = -1;
   t->have_alpha = true;
   t->have_eps = false;
+  t->aniso = false;
   return DDA_OK;
 }
 
@@ -661,6 +664,7 @@ int dda_set_composition(dda_target* t, int nmat, const double* eps, const uint8_
   t->prescription = prescription;
   t->have_alpha = true;
   t->have_eps = false;  // the permittivity gradient is defined per isotropic dipole
+  t->aniso = true;
   return DDA_OK;
 }
 
@@ -972,6 +976,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.Kpp = Kpp;
   va.Ppp = Ppp;
   va.nd = t->nd;
+  va.dstride = t->aniso ? t->nd : 0;
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);

@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
   const int i = blockIdx.x * TX + l, k = blockIdx.y;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
+  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   cx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
+  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   if (i < a.K) {
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<
   if (active && !active[rhs]) return;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
+  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   // phase A: columns i in chunks of CA, M-point DFT along y
   for (int c0 = 0; c0 < a.K; c0 += CA) {
     const int l = threadIdx.x % CA, t = threadIdx.x / CA;
@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, co
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
+  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   for (int c0 = 0; c0 < Q; c0 += CY) {
     const int l = threadIdx.x % CY, t = threadIdx.x / CY;

@@ -186,6 +186,7 @@ __device__ __forceinline__ cx<R> jacobi_scale(cx<R> a) {
 struct VecArgs {
   int K, J, P, Jpp, Kpp, Ppp;
   long nd;
+  long dstride;  // distance between the components' diagonals: N_d, or 0 when isotropic (shared entries)
   int TX;
   int jacobi;  // 0: y = A x;  1: y = D^{-1/2} A D^{-1/2} x with D = diag(alpha^{-1})
   double scale;  // 1/(K''J''P'') for the inverse pass
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
   const int i0 = blockIdx.x * TX, k = blockIdx.y;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
+  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   for (int idx = tid; idx < d.n * TX; idx += nthr) {
     const int e = idx / TX, l = idx - e * TX, i = i0 + l;
     cx<R> v = mk((R)0, (R)0);
@@ -284,7 +285,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.nd;  // this component's diagonal entries
+  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   for (int idx = tid; idx < a.J * TX; idx += nthr) {
