@@ -225,6 +225,8 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * -1 (default) the autotuned choice; 0 five separate passes (y, x, z with
  * product, x inverse, y inverse) with the z lines read as strided tiles;
  * 1 five passes with the x passes transposing so that z lines are contiguous;
+ * 3 five passes with the z pass spread over three thread groups, one per
+ * vector component (fewer registers per thread, spectra exchanged in LDS);
  * D in {2, 4, 8} the fused xy-plane passes with the frequency range split
  * into D residue classes.  DDA_EINVAL if that schedule does not exist for the
  * lattice. */

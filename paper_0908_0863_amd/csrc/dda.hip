@@ -466,7 +466,9 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_SCHEDULE: {
       if (value == 1 && !(fast_size(t->Kpp) && fast_size(t->Ppp)))
         return fail(DDA_EINVAL, "dda_target_set_option: no z-contiguous schedule for this lattice");
-      if (value >= 2) {
+      if (value == 3 && !fast_size(t->Ppp))
+        return fail(DDA_EINVAL, "dda_target_set_option: no component-split z pass for this lattice");
+      if (value >= 2 && value != 3) {
         const std::vector<int> c64c = xy_candidates<double>(t), c32c = xy_candidates<float>(t);
         if (std::find(c64c.begin(), c64c.end(), value) == c64c.end() ||
             std::find(c32c.begin(), c32c.end(), value) == c32c.end())
@@ -850,6 +852,18 @@ struct FastLaunch {
                        lout_stride, Lin, Lout, rows_per_rhs, act, tw);
   }
   template <int N>
+  static void zsplit(int nrhs, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za,
+                     const cx<R>* tw) {
+    constexpr int TX = fast_txz<R, N>();
+    ZMap zm;
+    zm.NX = (za.Kpp + TX - 1) / TX;
+    zm.ngx = (zm.NX + 1) / 2;
+    zm.ngy = za.Jpp / 2 + 1;
+    zm.ngroups = nrhs * zm.ngx * zm.ngy;
+    dim3 grid(32 * ((zm.ngroups + 7) / 8));
+    hipLaunchKernelGGL((k_fast_zsplit<R, N, TX>), grid, dim3(3 * FastPlan<N>::T * TX), 0, st, G2, Y, act, za, zm, tw);
+  }
+  template <int N>
   static void zmul(int nrhs, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za, const cx<R>* tw) {
     constexpr int TX = fast_txz<R, N>();
     ZMap zm;
@@ -936,6 +950,10 @@ static int launch_xy_inv(dda_target* t, int nrhs, hipStream_t st, const cx<R>* G
   return DDA_OK;
 }
 
+// Schedules: 0 five passes (strided z tiles), 1 five passes (z-contiguous),
+// 3 five passes (z pass on three component groups), D in {2, 4, 8} fused xy.
+static inline bool is_fused(int s) { return s == 2 || s == 4 || s == 8; }
+
 // blocks per right-hand side of the last matvec pass (fused-dot partials)
 template <typename R>
 static int schedule_of(const dda_target* t, int nrhs);
@@ -943,7 +961,7 @@ static int schedule_of(const dda_target* t, int nrhs);
 template <typename R>
 static int yinv_blocks(const dda_target* t, int nrhs) {
   const int sc = schedule_of<R>(t, nrhs);
-  if (sc >= 2) return 3 * t->P * sc;
+  if (is_fused(sc)) return 3 * t->P * sc;
   int tx = 0;
   switch (t->Jpp) {
 #define DDA_CASE(N) \
@@ -981,7 +999,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
   const int sched = schedule_of<R>(t, nrhs);
-  const int dfwd = sched >= 2 ? sched : 0, dinv = dfwd;
+  const int dfwd = is_fused(sched) ? sched : 0, dinv = dfwd;
   if (dfwd) {
     // fused: xy forward -> z with product -> xy inverse
     {
@@ -1131,7 +1149,17 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     za.Kh = t->Kh;
     za.Jh = t->Jh;
     za.Ph = t->Ph;
-    if (fast_size(Ppp)) {
+    if (fast_size(Ppp) && sched == 3) {
+      switch (Ppp) {
+#define DDA_CASE(N)                                                                                      \
+  case N:                                                                                                \
+    FastLaunch<R>::template zsplit<N>(nrhs, st, G2, b.Y.template as<cx<R>>(), active, za,                 \
+                                      b.tw[2].template as<cx<R>>());                                      \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+    } else if (fast_size(Ppp)) {
       switch (Ppp) {
 #define DDA_CASE(N)                                                                                      \
   case N:                                                                                                \
@@ -1232,6 +1260,7 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   }
   std::vector<int> cand = {0};
   if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
+  if (fast_size(t->Ppp)) cand.push_back(3);
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {

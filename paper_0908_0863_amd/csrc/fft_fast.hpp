@@ -408,6 +408,94 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __rest
   }
 }
 
+// z pass with the three components on separate thread groups: a block holds
+// TX columns (i'', j'') and 3 T TX threads; group c transforms component c
+// (E values per thread instead of 3 E), the groups then exchange their
+// spectra through LDS so that group c forms Q_c = sum_b Y_cb X_b (Eqs. Q0-Q2)
+// with the three spectrum components of its row, and transforms back.  Same
+// tiles and XCD mirror grouping as k_fast_zmul.  More spectrum loads (9 per
+// point against 6) and an LDS exchange buy three times the threads per
+// column: measured faster for FP64 at 3 * 2^k lengths (the 96^3 ellipsoid),
+// slower in FP32; the autotuner decides per lattice and precision.
+template <typename R, int N, int TX>
+__global__ void __launch_bounds__(3 * FastPlan<N>::T * TX) k_fast_zsplit(
+    cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y, const int* __restrict__ active, ZArgs a, ZMap zm,
+    const cx<R>* __restrict__ tw) {
+  constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
+  __shared__ cx<R> lds[3 * N * TX];
+  const int b = blockIdx.x;
+  const int group = (b >> 5) * 8 + (b & 7);
+  const int member = (b >> 3) & 3;
+  if (group >= zm.ngroups) return;
+  const int per_rhs = zm.ngx * zm.ngy;
+  const int rhs = group / per_rhs;
+  const int rem = group - rhs * per_rhs;
+  const int gx = rem / zm.ngy, gy = rem - (rem / zm.ngy) * zm.ngy;
+  const int mxm = member & 1, mym = member >> 1;
+  const int xt = mxm ? zm.NX - 1 - gx : gx;
+  if (mxm && xt == gx) return;
+  const int jj = mym ? a.Jpp - gy : gy;
+  if (mym && (gy == 0 || jj == gy)) return;
+  if (active && !active[rhs]) return;
+  const int c = threadIdx.x / (T * TX);
+  const int rr = threadIdx.x - c * (T * TX);
+  const int l = rr % TX, t = rr / TX;
+  const int i = xt * TX + l;
+  const long plane = (long)a.Jpp * a.Kpp;
+  const bool ok = i < a.Kpp;
+  cx<R>* pl = lds + c * N * TX;
+  cx<R> v[E];
+  {
+    const cx<R>* src = G2 + ((long)(rhs * 3 + c) * a.P) * plane + (long)jj * a.Kpp + i;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      v[m] = (ok && e < a.P) ? src[e * plane] : mk((R)0, (R)0);
+    }
+  }
+  fast_fft<R, false, N>(v, t, pl, TX, l, tw);
+  // spectra of all three components at this thread's positions
+#pragma unroll
+  for (int m = 0; m < E; ++m) pl[(t + T * m) * TX + l] = v[m];
+  __syncthreads();
+  if (ok) {
+    const int jm = min(jj, a.Jpp - jj);
+    const bool my = jj > a.Jpp - jj;
+    const int im = min(i, a.Kpp - i);
+    const bool mx = i > a.Kpp - i;
+    // row c of the symmetric tensor: components (c,0), (c,1), (c,2)
+    const int u0 = c == 0 ? 0 : (c == 1 ? 1 : 2);
+    const int u1 = c == 0 ? 1 : (c == 1 ? 3 : 4);
+    const int u2 = c == 0 ? 2 : (c == 1 ? 4 : 5);
+    const int sx0 = (mx ? c_sign[0][u0] : 1) * (my ? c_sign[1][u0] : 1);
+    const int sx1 = (mx ? c_sign[0][u1] : 1) * (my ? c_sign[1][u1] : 1);
+    const int sx2 = (mx ? c_sign[0][u2] : 1) * (my ? c_sign[1][u2] : 1);
+    const long cs = (long)a.Ph * a.Jh * a.Kh;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      const int km = min(e, N - e);
+      const bool mz = e > N - e;
+      const cx<R>* ys = Y + ((long)km * a.Jh + jm) * a.Kh + im;
+      cx<R> y0 = ys[u0 * cs], y1 = ys[u1 * cs], y2 = ys[u2 * cs];
+      if (sx0 * (mz ? c_sign[2][u0] : 1) < 0) y0 = mk(-y0.x, -y0.y);
+      if (sx1 * (mz ? c_sign[2][u1] : 1) < 0) y1 = mk(-y1.x, -y1.y);
+      if (sx2 * (mz ? c_sign[2][u2] : 1) < 0) y2 = mk(-y2.x, -y2.y);
+      const int q = e * TX + l;
+      v[m] = y0 * lds[q] + y1 * lds[N * TX + q] + y2 * lds[2 * N * TX + q];
+    }
+  }
+  __syncthreads();  // every group has read the spectra before its plane is reused
+  fast_fft<R, true, N>(v, t, pl, TX, l, tw);
+  if (!ok) return;
+  cx<R>* dst = G2 + ((long)(rhs * 3 + c) * a.P) * plane + (long)jj * a.Kpp + i;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    if (e < a.P) dst[e * plane] = v[m];
+  }
+}
+
 // ===========================================================================
 // Fused xy-plane passes (lattices whose padded x and y lengths are equal, NN).
 //

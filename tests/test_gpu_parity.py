@@ -219,7 +219,7 @@ FUSED_SHAPES = [(16, 16, 16), (32, 30, 5), (45, 40, 3)]  # padded x = padded y: 
 
 
 @pytest.mark.parametrize("shape", FUSED_SHAPES)
-@pytest.mark.parametrize("sched", [0, 1, 2, 4, 8, -1])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 8, -1])
 @pytest.mark.parametrize("jacobi", [False, True])
 def test_matvec_fused_and_five_pass_schedules(lib, shape, sched, jacobi):
     from paper_0908_0863_amd import dda
