@@ -149,7 +149,7 @@ def bench_batch_rhs(args):
     n = args.nrhs if args.nrhs > 0 else len(w["khat"])
     khat = np.array(w["khat"][:n])
     ehat = np.array(w["ehat"][:n], np.complex128)
-    kw = dict(solver="qmr", tol=args.tol, inner_tol=args.inner_tol, check_every=16, use_graph=True)
+    kw = dict(solver="qmr_sym", tol=args.tol, inner_tol=args.inner_tol, check_every=16, use_graph=True)
     t.build_spectrum()
     for _ in range(max(1, args.warmup)):
         t.solve(khat=khat, ehat=ehat, precision="mixed", **kw)
@@ -203,7 +203,7 @@ def bench_batch_targets(args):
         items.append(dict(target=t, khat=[zh, zh], ehat=[xh, yh]))
     torch.cuda.synchronize()
     t_spec = time.perf_counter() - tb0
-    kw = dict(solver="qmr", precision="mixed", tol=args.tol, inner_tol=args.inner_tol, check_every=16,
+    kw = dict(solver="qmr_sym", precision="mixed", tol=args.tol, inner_tol=args.inner_tol, check_every=16,
               use_graph=True)
     lib.batch_solve(items, nworkers=args.workers, **kw)  # warm-up: tuning, workspaces, graphs
     torch.cuda.synchronize()
@@ -248,13 +248,18 @@ def bench_paper200(args):
     t.build_spectrum()
     torch.cuda.synchronize()
     t_spec = time.perf_counter() - t0
-    paper = {"bicg_sym": (21, 741.5, 212.7), "bicgstab": (12, 846.6, 234.7), "cgs": (13, 911.3, 257.4),
-             "qmr_sym": (21, 759.6, 216.7), "tfqmr": (13, 1850.3, 524.7)}
-    name = {"bicg_sym": "bicg_sym", "bicgstab": "bicgstab", "cgs": "cgs", "qmr_sym": "qmr", "tfqmr": "tfqmr"}
+    # Table 3: scheme (SV) -> iterations, serial and OpenMP-4 seconds on NEMO
+    paper = {("bicg", 0): (21, 1439.7, 404.3), ("bicg_sym", 0): (21, 741.5, 212.7),
+             ("bicgstab", 0): (12, 846.6, 234.7), ("cgs", 0): (13, 911.3, 257.4),
+             ("mlbicgstab", 1): (12, 836.0, 238.9), ("mlbicgstab", 2): (8, 811.7, 246.2),
+             ("mlbicgstab", 3): (6, 842.9, 266.2), ("qmr", 0): (22, 3704.6, 1055.1),
+             ("qmr_sym", 0): (21, 759.6, 216.7), ("rbicgstab", 1): (14, 996.3, 284.5),
+             ("rbicgstab", 2): (7, 990.5, 285.2), ("rbicgstab", 3): (4, 851.1, 242.2),
+             ("tfqmr", 0): (13, 1850.3, 524.7)}
     out = {}
-    for solver, (ni, ser, omp) in paper.items():
-        kw = dict(khat=w["khat"], ehat=w["ehat"], solver=name[solver], precision="fp64", tol=1e-10, check_every=4,
-                  use_graph=True)
+    for (solver, sv), (ni, ser, omp) in paper.items():
+        kw = dict(khat=w["khat"], ehat=w["ehat"], solver=solver, solver_param=sv, precision="fp64", tol=1e-10,
+                  check_every=4, use_graph=True)
         t.solve(**kw)  # tuning, workspaces, graph
         torch.cuda.synchronize()
         steps = max(1, min(args.steps, 5))
@@ -263,8 +268,9 @@ def bench_paper200(args):
             P, info = t.solve(**kw)
         torch.cuda.synchronize()
         el = (time.perf_counter() - t1) / steps
-        out[solver] = dict(iterations=info[0]["iterations"], seconds=round(el, 4), paper_iterations=ni,
-                           paper_serial_s=ser, paper_openmp4_s=omp, speedup_vs_openmp4=round(omp / el, 1))
+        key = solver + (f"({sv})" if sv else "")
+        out[key] = dict(iterations=info[0]["iterations"], seconds=round(el, 4), paper_iterations=ni,
+                        paper_serial_s=ser, paper_openmp4_s=omp, speedup_vs_openmp4=round(omp / el, 1))
     total = sum(v["seconds"] for v in out.values())
     _line("Table 3 benchmark solves/sec (200^3 sphere, FP64, tol 1e-10)", len(out) / total, "solves/s", args,
           total, len(out), "f64", {"workload": f"sphere200: 200^3 lattice, {nd} dipoles, m=1.63631+0.372i, "
@@ -291,7 +297,7 @@ def main():
                     help="single: one right-hand side of --workload (the headline line); batch-rhs: all "
                          "orientations of --workload in one multi-RHS solve; batch-targets: 40 seeded "
                          "aggregates through the multi-target batch solve; paper200: the paper's Table 3 "
-                         "benchmark solve (200^3 sphere, FP64, tol 1e-10) with BiCG_sym, BiCGSTAB, CGS, QMR_sym, TFQMR")
+                         "benchmark solve (200^3 sphere, FP64, tol 1e-10) with the schemes of its Table 3")
     ap.add_argument("--nrhs", type=int, default=0, help="batch-rhs: right-hand sides (default: all)")
     ap.add_argument("--workers", type=int, default=0, help="batch-targets: host workers (default 4)")
     args = ap.parse_args()
@@ -352,7 +358,7 @@ def main():
 
     def step(precision):
         t.build_spectrum()
-        P_, inf = t.solve(einc=E, S=S, solver="qmr", precision=precision, tol=args.tol,
+        P_, inf = t.solve(einc=E, S=S, solver="qmr_sym", precision=precision, tol=args.tol,
                           inner_tol=args.inner_tol, check_every=16, use_graph=not profiling[0])
         ce, ca, cs = t.cross_sections(E, P_, S=S)
         return P_, inf, (ce[0], ca[0], cs[0])
@@ -360,7 +366,7 @@ def main():
     profiling = [False]
     # reference cross sections: FP64 solve to 1e-12
     t.build_spectrum()
-    Pref, infref = t.solve(einc=E, S=S, solver="qmr", precision="fp64", tol=1e-12)
+    Pref, infref = t.solve(einc=E, S=S, solver="qmr_sym", precision="fp64", tol=1e-12)
     cref = [c[0] for c in t.cross_sections(E, Pref, S=S)]
     del Pref
 

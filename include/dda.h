@@ -52,8 +52,25 @@ enum { DDA_POL_CM = 0, DDA_POL_RR = 1, DDA_POL_LDR = 2 };  /* polarisability    
 /* Krylov solvers (schemes of Sec. 4): BiCGSTAB (van der Vorst 1992), CGS
  * (Sonneveld 1989) and TFQMR (Freund 1993), two products per iteration;
  * QMR_sym and BiCG_sym (Freund 1992a; complex-symmetric, one product per
- * iteration, bilinear form x^T y). */
-enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1, DDA_BICG_SYM = 2, DDA_CGS = 3, DDA_TFQMR = 4 };
+ * iteration, bilinear form x^T y); BiCG (Fletcher 1975) and QMR with coupled
+ * two-term recurrences (Freund & Nachtigal), whose shadow products A^H y are
+ * computed as conj(A conj(y)) since A is complex symmetric, two products per
+ * iteration; RBiCGSTAB = BiCGSTAB(l) (Sleijpen & Fokkema 1993), one iteration
+ * = l BiCG steps and a degree-l minimal-residual polynomial, 2l products;
+ * ML(n)BiCGSTAB (Yeung & Chan 1999) in the IDR(s) form with s = n
+ * (Sonneveld & van Gijzen 2008), one iteration = n + 1 products.  The l and
+ * n of the last two come from dda_solve_opts.solver_param. */
+enum {
+  DDA_BICGSTAB = 0,
+  DDA_QMR_SYM = 1,
+  DDA_BICG_SYM = 2,
+  DDA_CGS = 3,
+  DDA_TFQMR = 4,
+  DDA_BICG = 5,
+  DDA_QMR = 6,
+  DDA_RBICGSTAB = 7,
+  DDA_MLBICGSTAB = 8
+};
 enum { DDA_SOLVE_FP64 = 0, DDA_SOLVE_MIXED = 1 };          /* solve precision    */
 
 typedef struct dda_lib dda_lib;
@@ -118,7 +135,7 @@ int dda_matvec(dda_target *t, int precision, int nrhs, const double *S, int jaco
                void *y_dev, void *hip_stream);
 
 typedef struct {
-  int solver;        /* DDA_BICGSTAB, DDA_QMR_SYM, DDA_BICG_SYM, DDA_CGS, DDA_TFQMR */
+  int solver;        /* one of the DDA_* solver values above                      */
   int precision;     /* DDA_SOLVE_FP64, or DDA_SOLVE_MIXED (FP32 inner, FP64 outer) */
   int max_iter;      /* total inner iterations per right-hand side (<= 0: 10000)  */
   int max_outer;     /* refinement steps (<= 0: 20)                               */
@@ -127,6 +144,8 @@ typedef struct {
   int jacobi;        /* Point-Jacobi preconditioning (symmetric form)             */
   int check_every;   /* iterations between convergence read-backs (<= 0: 8)        */
   int use_graph;     /* capture the inner iteration in a HIP graph                */
+  int solver_param;  /* l of DDA_RBICGSTAB, n of DDA_MLBICGSTAB: 1..4 (<= 0: 2);
+                        ignored by the other solvers                             */
 } dda_solve_opts;
 
 typedef struct {
@@ -142,7 +161,9 @@ typedef struct {
  * ehat exp(i kd khat . r) built from khat[3*nrhs] and ehat[6*nrhs] (re, im).
  * S (nullable) as for dda_matvec; when NULL and the prescription is LDR, S is
  * computed from khat/ehat.  p_dev: out [nrhs][3][N_d] complex128.
- * info: host [nrhs].  DDA_ENOTCONV if a right-hand side missed tol. */
+ * info: host [nrhs].  DDA_ENOTCONV if a right-hand side missed tol;
+ * DDA_EINVAL for an unknown solver, a solver_param above 4, tol outside
+ * (0, 1) or an unknown precision. */
 int dda_solve(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *khat, const double *ehat,
               const double *S, const void *einc_dev, void *p_dev, dda_solve_info *info, void *hip_stream);
 

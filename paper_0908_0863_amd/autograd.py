@@ -40,7 +40,7 @@ class CAbs(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, eps, target, khat, ehat, prescription="ldr", solve_kw=None):
-        kw = dict(solver="qmr", precision="fp64", tol=1e-10)
+        kw = dict(solver="qmr_sym", precision="fp64", tol=1e-10)
         kw.update(solve_kw or {})
         e = eps.detach().to("cpu", torch.complex128).numpy()
         target.set_permittivity(e, prescription)

@@ -25,6 +25,7 @@
 #include "common.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_solver.hpp"
+#include "kernels_krylov.hpp"
 #include "fft_fast.hpp"
 #include "kernels_farfield.hpp"
 
@@ -202,8 +203,8 @@ struct PrecBufs {
   DevBuf a0, a1;            // diagonal alpha^{-1} = a0 + S a1
   DevBuf G1, G2;            // matvec workspaces
   int cap = 0;              // right-hand sides the workspaces hold
-  DevBuf vec;               // solver vectors: 7 x [cap][3][nd]
-  int vec_cap = 0;
+  DevBuf vec;               // solver vectors: vec_slots x [vec_cap][3][nd]
+  int vec_cap = 0, vec_slots = 0;
 };
 
 struct dda_target {
@@ -761,7 +762,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
   CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState), sizeof(CgsState),
-                                             sizeof(TfqState)})));
+                                             sizeof(TfqState), sizeof(GenState)})));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
   CHK(t->ehat.ensure(cap * 6 * sizeof(double)));
   t->h_active.resize(cap);
@@ -1361,12 +1362,29 @@ static int nblocks_for(long n3) {
 }
 
 template <typename R>
-static int ensure_solver_ws(dda_target* t, int nrhs) {
+static int ensure_solver_ws(dda_target* t, int nrhs, int nslots) {
   PrecBufs<R>& b = bufs<R>(t);
-  if (nrhs <= b.vec_cap) return DDA_OK;
-  CHK(b.vec.ensure((size_t)10 * nrhs * 3 * t->nd * sizeof(cx<R>)));
-  b.vec_cap = nrhs;
+  if (nrhs <= b.vec_cap && nslots <= b.vec_slots) return DDA_OK;
+  const int cap = std::max(nrhs, b.vec_cap), ns = std::max(nslots, b.vec_slots);
+  CHK(b.vec.ensure((size_t)ns * cap * 3 * t->nd * sizeof(cx<R>)));
+  b.vec_cap = cap;
+  b.vec_slots = ns;
   return DDA_OK;
+}
+
+// Solver vectors a scheme needs (slot 0 = right-hand side, 1 = solution).
+static int solver_slots(int solver, int param) {
+  switch (solver) {
+    case DDA_BICG: return 8;
+    case DDA_QMR: return 11;
+    case DDA_RBICGSTAB: return 5 + 2 * param;
+    case DDA_MLBICGSTAB: return 4 + 3 * param;
+    default: return 10;
+  }
+}
+
+static int solver_param(const dda_solve_opts& o) {
+  return o.solver_param > 0 ? o.solver_param : 2;
 }
 
 // Read the device `active` flags; returns the number still active.
@@ -1378,6 +1396,237 @@ static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
   return DDA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Host programs of the generic solvers (BiCG, QMR, BiCGSTAB(l), IDR(s) for
+// ML(n)BiCGSTAB): each iteration is a fixed sequence of k_gen_dot,
+// k_gen_scalar, k_gen_lin and matrix-vector launches.
+// ---------------------------------------------------------------------------
+static_assert(GEN_BICG == DDA_BICG && GEN_QMR == DDA_QMR && GEN_BICGSTAB_L == DDA_RBICGSTAB &&
+                  GEN_IDR == DDA_MLBICGSTAB,
+              "generic solver ids follow the C ABI");
+
+struct LinB {
+  GenLin L{};
+  bool overflow = false;
+  LinB& out(int slot) {
+    if (L.nout >= kGenOut) {
+      overflow = true;
+      return *this;
+    }
+    L.out[L.nout] = (signed char)slot;
+    L.nt[L.nout] = 0;
+    ++L.nout;
+    return *this;
+  }
+  LinB& term(int src, int code = kGenOne) {
+    const int q = L.nout - 1;
+    if (q < 0 || L.nt[q] >= kGenTerms) {
+      overflow = true;
+      return *this;
+    }
+    L.src[q][L.nt[q]] = (signed char)src;
+    L.coef[q][L.nt[q]] = (short)code;
+    ++L.nt[q];
+    return *this;
+  }
+};
+
+struct DotB {
+  GenDots D{};
+  bool overflow = false;
+  DotB& add(int a, int b, int herm) {
+    if (D.n >= kGenDots) {
+      overflow = true;
+      return *this;
+    }
+    D.a[D.n] = (signed char)a;
+    D.b[D.n] = (signed char)b;
+    D.herm[D.n] = (signed char)herm;
+    ++D.n;
+    return *this;
+  }
+  DotB& h(int a, int b) { return add(a, b, 1); }    // a^H b
+  DotB& bil(int a, int b) { return add(a, b, 0); }  // a^T b
+};
+
+template <typename R>
+struct GenRun {
+  dda_target* t;
+  int nrhs, solver, param, mvpi, jacobi;
+  cx<R>* V;
+  long vsz;
+  SolverDims dm;
+  c64* part;
+  GenState* st;
+  int* act;
+  const double* tolv;
+  const double* dS;
+
+  int dot(hipStream_t s, const DotB& d) {
+    if (d.overflow) return fail(DDA_EINVAL, "solver program: too many inner products");
+    hipLaunchKernelGGL((k_gen_dot<R>), dim3(dm.nblk, nrhs), dim3(kRedThreads), 0, s, V, vsz, d.D, act, dm, part);
+    return DDA_OK;
+  }
+  int scal(hipStream_t s, int step, int sub = 0) {
+    GenStep g{solver, step, sub, param, mvpi};
+    hipLaunchKernelGGL((k_gen_scalar<R>), dim3(nrhs), dim3(kRedThreads), 0, s, part, dm.nblk, g, st, act, tolv);
+    return DDA_OK;
+  }
+  int lin(hipStream_t s, const LinB& b) {
+    if (b.overflow) return fail(DDA_EINVAL, "solver program: too many terms");
+    const unsigned gx = (unsigned)std::min<long>((dm.n3 + 255) / 256, 2048);
+    hipLaunchKernelGGL((k_gen_lin<R>), dim3(gx, nrhs), dim3(256), 0, s, V, vsz, b.L, st, act, dm.n3);
+    return DDA_OK;
+  }
+  int rnd(hipStream_t s, int slot, uint64_t seed) {
+    const unsigned gx = (unsigned)std::min<long>((dm.n3 + 255) / 256, 2048);
+    hipLaunchKernelGGL((k_gen_random<R>), dim3(gx, nrhs), dim3(256), 0, s, V, vsz, slot, seed, act, dm.n3);
+    return DDA_OK;
+  }
+  int mv(hipStream_t s, int src, int dst) {
+    return matvec_T<R>(t, nrhs, dS, jacobi, V + src * vsz, V + dst * vsz, act, s);
+  }
+
+  // ---- BiCG: 0 b, 1 u, 2 r, 3 rh, 4 p, 5 ph, 6 q, 7 qh (h: conjugated shadow)
+  int init(hipStream_t s) {
+    const int B = 0, X = 1;
+    if (solver == GEN_BICG) {
+      CHK(lin(s, LinB().out(2).term(B).out(3).term(B, kGenOne | kGenConj).out(X).out(4).out(5)));
+    } else if (solver == GEN_QMR) {
+      // 2 r, 3 vt, 4 wt (conj), 5 p, 6 qh, 7 pt = A p, 8 t = A qh, 9 d, 10 s
+      CHK(lin(s, LinB().out(2).term(B).out(3).term(B).out(4).term(B, kGenOne | kGenConj).out(X).out(5).out(6).out(9)
+                     .out(10)));
+    } else if (solver == GEN_BICGSTAB_L) {
+      // 2 rt, r_j = 3 + j, u_j = 4 + l + j
+      CHK(lin(s, LinB().out(2).term(B).out(3).term(B).out(X).out(4 + param)));
+    } else {
+      // 2 r, 3 t, P_j = 4 + j, G_j = 4 + n + j, U_j = 4 + 2n + j
+      CHK(lin(s, LinB().out(2).term(B).out(X).out(4).term(B)));
+      LinB z;
+      for (int j = 0; j < param; ++j) z.out(4 + param + j).out(4 + 2 * param + j);
+      CHK(lin(s, z));
+      for (int j = 1; j < param; ++j) CHK(rnd(s, 4 + j, 0x1d2a7b3cull));
+    }
+    CHK(dot(s, DotB().h(B, B)));
+    return scal(s, GS_INIT);
+  }
+
+  int body(hipStream_t s) {
+    const int X = 1;
+    if (solver == GEN_BICG) {
+      const int Rr = 2, RH = 3, P = 4, PH = 5, Q = 6, QH = 7;
+      CHK(dot(s, DotB().h(Rr, Rr).bil(RH, Rr)));
+      CHK(scal(s, GS_A));
+      CHK(lin(s, LinB().out(P).term(Rr).term(P, BG_BETA).out(PH).term(RH).term(PH, BG_BETA)));
+      CHK(mv(s, P, Q));
+      CHK(mv(s, PH, QH));
+      CHK(dot(s, DotB().bil(PH, Q)));
+      CHK(scal(s, GS_B));
+      return lin(s, LinB()
+                        .out(X).term(X).term(P, BG_ALPHA)
+                        .out(Rr).term(Rr).term(Q, BG_ALPHA | kGenNeg)
+                        .out(RH).term(RH).term(QH, BG_ALPHA | kGenNeg));
+    }
+    if (solver == GEN_QMR) {
+      const int Rr = 2, VT = 3, WT = 4, P = 5, QH = 6, PT = 7, T = 8, D = 9, S = 10;
+      CHK(dot(s, DotB().h(Rr, Rr).h(WT, WT).bil(WT, VT)));
+      CHK(scal(s, GS_A));
+      CHK(lin(s, LinB()
+                     .out(P).term(VT, QM_INVRHO).term(P, QM_CP | kGenNeg)
+                     .out(VT).term(VT, QM_INVRHO)
+                     .out(QH).term(WT, QM_INVXI).term(QH, QM_CQ | kGenNeg)
+                     .out(WT).term(WT, QM_INVXI)));
+      CHK(mv(s, P, PT));
+      CHK(mv(s, QH, T));
+      CHK(dot(s, DotB().bil(QH, PT)));
+      CHK(scal(s, GS_B));
+      CHK(lin(s, LinB().out(VT).term(PT).term(VT, QM_BETA | kGenNeg).out(WT).term(T).term(WT, QM_BETA | kGenNeg)));
+      CHK(dot(s, DotB().h(VT, VT)));
+      CHK(scal(s, GS_C));
+      return lin(s, LinB()
+                        .out(D).term(P, QM_ETA).term(D, QM_CD)
+                        .out(S).term(PT, QM_ETA).term(S, QM_CD)
+                        .out(X).term(X).term(D)
+                        .out(Rr).term(Rr).term(S, kGenOne | kGenNeg));
+    }
+    if (solver == GEN_BICGSTAB_L) {
+      const int l = param, RT = 2;
+      auto r = [&](int j) { return 3 + j; };
+      auto u = [&](int j) { return 4 + l + j; };
+      for (int j = 0; j < l; ++j) {
+        DotB d;
+        if (j == 0) d.h(r(0), r(0));
+        d.h(RT, r(j));
+        CHK(dot(s, d));
+        CHK(scal(s, GS_A, j));
+        LinB a;
+        for (int i = 0; i <= j; ++i) a.out(u(i)).term(r(i)).term(u(i), BL_BETA | kGenNeg);
+        CHK(lin(s, a));
+        CHK(mv(s, u(j), u(j + 1)));
+        CHK(dot(s, DotB().h(RT, u(j + 1))));
+        CHK(scal(s, GS_B, j));
+        LinB b;
+        for (int i = 0; i <= j; ++i) b.out(r(i)).term(r(i)).term(u(i + 1), BL_ALPHA | kGenNeg);
+        b.out(X).term(X).term(u(0), BL_ALPHA);
+        CHK(lin(s, b));
+        CHK(mv(s, r(j), r(j + 1)));
+      }
+      DotB g;
+      for (int i = 1; i <= l; ++i)
+        for (int k = i; k <= l; ++k) g.h(r(i), r(k));
+      for (int i = 1; i <= l; ++i) g.h(r(i), r(0));
+      CHK(dot(s, g));
+      CHK(scal(s, GS_C));
+      LinB m;
+      m.out(X).term(X);
+      for (int j = 1; j <= l; ++j) m.term(r(j - 1), BL_GAM + j - 1);
+      m.out(r(0)).term(r(0));
+      for (int j = 1; j <= l; ++j) m.term(r(j), (BL_GAM + j - 1) | kGenNeg);
+      m.out(u(0)).term(u(0));
+      for (int j = 1; j <= l; ++j) m.term(u(j), (BL_GAM + j - 1) | kGenNeg);
+      return lin(s, m);
+    }
+    // IDR(s), s = n
+    const int n = param, Rr = 2, T = 3;
+    auto P = [&](int j) { return 4 + j; };
+    auto G = [&](int j) { return 4 + n + j; };
+    auto U = [&](int j) { return 4 + 2 * n + j; };
+    {
+      DotB d;
+      for (int j = 0; j < n; ++j) d.h(P(j), Rr);
+      d.h(Rr, Rr);
+      CHK(dot(s, d));
+      CHK(scal(s, GS_A));
+    }
+    for (int k = 0; k < n; ++k) {
+      // U_k = sum_{i>=k} c_i U_i + omega (r - sum_{i>=k} c_i G_i);  G_k = A U_k
+      LinB a;
+      a.out(U(k));
+      for (int i = k; i < n; ++i) a.term(U(i), ID_C + i);
+      a.term(Rr, ID_OMEGA);
+      for (int i = k; i < n; ++i) a.term(G(i), (ID_OC + i) | kGenNeg);
+      CHK(lin(s, a));
+      CHK(mv(s, U(k), G(k)));
+      DotB d;
+      for (int j = 0; j < n; ++j) d.h(P(j), G(k));
+      CHK(dot(s, d));
+      CHK(scal(s, GS_B, k));
+      LinB b;
+      b.out(G(k)).term(G(k));
+      for (int i = 0; i < k; ++i) b.term(G(i), (ID_AL + i) | kGenNeg);
+      b.out(U(k)).term(U(k));
+      for (int i = 0; i < k; ++i) b.term(U(i), (ID_AL + i) | kGenNeg);
+      b.out(Rr).term(Rr).term(G(k), ID_BETA | kGenNeg);
+      b.out(X).term(X).term(U(k), ID_BETA);
+      CHK(lin(s, b));
+    }
+    CHK(mv(s, Rr, T));
+    CHK(dot(s, DotB().h(T, Rr).h(T, T)));
+    CHK(scal(s, GS_C));
+    return lin(s, LinB().out(X).term(X).term(Rr, ID_OMEGA).out(Rr).term(Rr).term(T, ID_OMEGA | kGenNeg));
+  }
+};
+
 // Solve (jacobi-scaled) A u = b for the right-hand sides flagged in
 // t->active; b and u are slots 0 and 1 of the solver vectors.  The
 // iteration is enqueued as a fixed kernel sequence; with use_graph a chunk of
@@ -1385,7 +1634,7 @@ static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
 // and replayed on the caller's stream, the host reading the `active` flags
 // only between chunks.
 template <typename R>
-static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, int max_iter, int jacobi,
+static int inner_solve(dda_target* t, int solver, int param, int nrhs, const double* tolv, int max_iter, int jacobi,
                        int check_every, int use_graph, hipStream_t st, InnerResult& res) {
   PrecBufs<R>& B = bufs<R>(t);
   const long n3 = 3 * t->nd;
@@ -1400,7 +1649,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   dm.nblk = nblocks_for(n3);
   // four regions of partial sums (each nrhs x nblk x 2)
   const size_t preg = (size_t)nrhs * dm.nblk * 2;
-  CHK(t->part.ensure(4 * preg * sizeof(c64)));
+  CHK(t->part.ensure(std::max(4 * preg, (size_t)nrhs * dm.nblk * kGenDots) * sizeof(c64)));
   c64* part = t->part.as<c64>();
   c64 *R0 = part, *R1 = part + preg, *R2 = part + 2 * preg, *R3 = part + 3 * preg;
   int* act = t->active.as<int>();
@@ -1413,7 +1662,13 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   const bool cgs = solver == DDA_BICG_SYM;
   const bool sq = solver == DDA_CGS;
   const bool tf = solver == DDA_TFQMR;
-  const int mv_per_iter = (bcg || sq || tf) ? 2 : 1;
+  const bool gen = solver >= DDA_BICG;
+  int mv_per_iter = (bcg || sq || tf) ? 2 : 1;
+  if (solver == DDA_BICG || solver == DDA_QMR) mv_per_iter = 2;
+  if (solver == DDA_RBICGSTAB) mv_per_iter = 2 * param;
+  if (solver == DDA_MLBICGSTAB) mv_per_iter = param + 1;
+  GenRun<R> gr{t, nrhs, solver, param, mv_per_iter, jacobi, V, (long)vsz, dm, part, t->state.as<GenState>(), act,
+               tolv, dS};
 
   // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
   CHK(autotune<R>(t, nrhs, dS, jacobi, slot(0), slot(4), st));
@@ -1422,7 +1677,9 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   CHK(t->part_mv.ensure((size_t)2 * nrhs * nblk_mv * 2 * sizeof(c64)));
   c64* M0 = t->part_mv.as<c64>();
   c64* M1 = M0 + (size_t)nrhs * nblk_mv * 2;
-  if (bcg) {
+  if (gen) {
+    CHK(gr.init(st));
+  } else if (bcg) {
     BcgState* S0 = t->state.as<BcgState>();
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
                        R3);
@@ -1461,7 +1718,9 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
 
   // ---- one iteration; `par` selects the roles of the ring and state buffers
   auto body = [&](hipStream_t s, int par) -> int {
-    if (bcg) {
+    if (gen) {
+      CHK(gr.body(s));
+    } else if (bcg) {
       BcgState* SA = t->state.as<BcgState>() + (par ? nrhs : 0);
       BcgState* SB = t->state.as<BcgState>() + (par ? 0 : nrhs);
       cx<R>*r = slot(2), *rhat = slot(3), *p = slot(4), *v = slot(5), *tt = slot(6);
@@ -1550,6 +1809,7 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
   if (use_graph && !t->lib->prof) {
     std::vector<uintptr_t> key = {sizeof(R),
                                   (uintptr_t)solver,
+                                  (uintptr_t)param,
                                   (uintptr_t)nrhs,
                                   (uintptr_t)jacobi,
                                   (uintptr_t)check,
@@ -1625,6 +1885,19 @@ static int inner_solve(dda_target* t, int solver, int nrhs, const double* tolv, 
     }
     return DDA_OK;
   };
+  if (gen) {
+    std::vector<GenState> hs(nrhs);
+    HIPCHK(hipMemcpyAsync(hs.data(), t->state.p, nrhs * sizeof(GenState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < nrhs; ++q) {
+      res.iters[q] = hs[q].iters < 0 ? 0 : hs[q].iters;
+      res.converged[q] = hs[q].converged;
+      res.breakdown[q] = hs[q].breakdown;
+      res.rnorm2[q] = hs[q].rnorm2;
+      res.bnorm2[q] = hs[q].bnorm2;
+    }
+    return DDA_OK;
+  }
   if (bcg) return collect(t->state.as<BcgState>(), BcgState{});
   if (cgs) return collect(t->state.as<CgState>(), CgState{});
   if (sq) return collect(t->state.as<CgsState>(), CgsState{});
@@ -1696,8 +1969,9 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   // recurrences can stagnate, e.g. QMR_sym on point sources) switches the
   // remaining steps to FP64 inner solves.
   bool lo = mixed;
-  if (lo) CHK(ensure_solver_ws<float>(t, nrhs));
-  else CHK(ensure_solver_ws<double>(t, nrhs));
+  const int nslots = solver_slots(o.solver, solver_param(o));
+  if (lo) CHK(ensure_solver_ws<float>(t, nrhs, nslots));
+  else CHK(ensure_solver_ws<double>(t, nrhs, nslots));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
   const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
   const double tol = o.tol > 0 ? o.tol : 1e-6;
@@ -1745,13 +2019,13 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       hipLaunchKernelGGL((k_scale_rhs<float>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p32.vec.as<c32>(), a0, a1,
                          t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
       LAUNCHCHK();
-      CHK(inner_solve<float>(t, o.solver, nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
+      CHK(inner_solve<float>(t, o.solver, solver_param(o), nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
                              ir));
     } else {
       hipLaunchKernelGGL((k_scale_rhs<double>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p64.vec.as<c64>(), a0, a1,
                          t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
       LAUNCHCHK();
-      CHK(inner_solve<double>(t, o.solver, nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
+      CHK(inner_solve<double>(t, o.solver, solver_param(o), nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
                               ir));
     }
     // P += |r| D^{-1/2} u
@@ -1780,7 +2054,7 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       for (int q = 0; q < nrhs; ++q)
         if (hact[q] && rn2[q] > tol * tol * en2[q] && rn2[q] > prev[q] / 16.0) {
           lo = false;
-          CHK(ensure_solver_ws<double>(t, nrhs));
+          CHK(ensure_solver_ws<double>(t, nrhs, nslots));
           break;
         }
   }
@@ -1803,8 +2077,10 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
 
 static int check_opts(const dda_solve_opts* opts, const char* who) {
   if (!opts) return fail(DDA_EINVAL, "%s: opts is NULL", who);
-  if (opts->solver < DDA_BICGSTAB || opts->solver > DDA_TFQMR)
+  if (opts->solver < DDA_BICGSTAB || opts->solver > DDA_MLBICGSTAB)
     return fail(DDA_EINVAL, "%s: solver %d", who, opts->solver);
+  if (opts->solver_param > kGenMaxParam)
+    return fail(DDA_EINVAL, "%s: solver_param %d (at most %d)", who, opts->solver_param, kGenMaxParam);
   if (opts->precision != DDA_SOLVE_FP64 && opts->precision != DDA_SOLVE_MIXED)
     return fail(DDA_EINVAL, "%s: precision %d", who, opts->precision);
   if (!(opts->tol > 0.0) || !(opts->tol < 1.0)) return fail(DDA_EINVAL, "%s: tol %g", who, opts->tol);

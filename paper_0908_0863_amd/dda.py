@@ -24,11 +24,14 @@ DDA_OK, DDA_EINVAL, DDA_ENOMEM, DDA_EDEVICE, DDA_ENOTCONV, DDA_ESTATE = 0, -1, -
 DDA_FP64, DDA_FP32 = 0, 1
 DDA_POL_CM, DDA_POL_RR, DDA_POL_LDR = 0, 1, 2
 DDA_BICGSTAB, DDA_QMR_SYM, DDA_BICG_SYM, DDA_CGS, DDA_TFQMR = 0, 1, 2, 3, 4
+DDA_BICG, DDA_QMR, DDA_RBICGSTAB, DDA_MLBICGSTAB = 5, 6, 7, 8
 DDA_SOLVE_FP64, DDA_SOLVE_MIXED = 0, 1
 
 _PRESC = {"cm": DDA_POL_CM, "rr": DDA_POL_RR, "ldr": DDA_POL_LDR}
-_SOLVER = {"bicgstab": DDA_BICGSTAB, "qmr": DDA_QMR_SYM, "qmr_sym": DDA_QMR_SYM, "bicg_sym": DDA_BICG_SYM,
-           "cocg": DDA_BICG_SYM, "cgs": DDA_CGS, "tfqmr": DDA_TFQMR}
+# Scheme names as the paper's Table 3 lists them (cocg = bicg_sym).
+_SOLVER = {"bicgstab": DDA_BICGSTAB, "qmr_sym": DDA_QMR_SYM, "bicg_sym": DDA_BICG_SYM, "cocg": DDA_BICG_SYM,
+           "cgs": DDA_CGS, "tfqmr": DDA_TFQMR, "bicg": DDA_BICG, "qmr": DDA_QMR, "rbicgstab": DDA_RBICGSTAB,
+           "mlbicgstab": DDA_MLBICGSTAB}
 _SPREC = {"fp64": DDA_SOLVE_FP64, "mixed": DDA_SOLVE_MIXED}
 
 
@@ -45,7 +48,8 @@ class NotConverged(DDAError):
 class dda_solve_opts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
-                ("jacobi", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("jacobi", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("solver_param", ctypes.c_int)]
 
 
 class dda_solve_info(ctypes.Structure):
@@ -319,10 +323,12 @@ class Target:
         return E
 
     @staticmethod
-    def make_opts(solver="qmr", precision="fp64", tol=1e-6, inner_tol=0.0, max_iter=0, max_outer=0,
-                  jacobi=True, check_every=0, use_graph=False) -> dda_solve_opts:
+    def make_opts(solver="qmr_sym", precision="fp64", tol=1e-6, inner_tol=0.0, max_iter=0, max_outer=0,
+                  jacobi=True, check_every=0, use_graph=False, solver_param=0) -> dda_solve_opts:
+        """solver_param: l of "rbicgstab", n of "mlbicgstab" (1..4; 0 = 2)."""
         return dda_solve_opts(_SOLVER[solver], _SPREC[precision], int(max_iter), int(max_outer), float(tol),
-                              float(inner_tol), int(bool(jacobi)), int(check_every), int(bool(use_graph)))
+                              float(inner_tol), int(bool(jacobi)), int(check_every), int(bool(use_graph)),
+                              int(solver_param))
 
     def solve(self, khat=None, ehat=None, S=None, einc: torch.Tensor | None = None, raise_on_fail=True, **kw):
         """Solve A P = E_inc.  Returns (P [nrhs,3,N_d] complex128, list of info dicts)."""

@@ -35,3 +35,34 @@ def test_binding_lists_every_declared_symbol():
     src = open(spec.origin).read()
     for n in _declared():
         assert f'"{n}"' in src, n
+
+
+def _header():
+    return open(os.path.join(ROOT, "include", "dda.h")).read()
+
+
+def test_binding_constants_match_header():
+    """Every DDA_* enumerator the binding defines has the header's value."""
+    from paper_0908_0863_amd import dda
+    vals = {k: int(v) for k, v in re.findall(r"\b(DDA_[A-Z0-9_]+)\s*=\s*(-?\d+)", _header())}
+    seen = 0
+    for k, v in vals.items():
+        if hasattr(dda, k):
+            assert getattr(dda, k) == v, k
+            seen += 1
+    assert seen >= 20
+    # every solver value is reachable by name
+    solvers = [v for k, v in vals.items() if k in ("DDA_BICGSTAB", "DDA_QMR_SYM", "DDA_BICG_SYM", "DDA_CGS",
+                                                    "DDA_TFQMR", "DDA_BICG", "DDA_QMR", "DDA_RBICGSTAB",
+                                                    "DDA_MLBICGSTAB")]
+    assert sorted(set(dda._SOLVER.values())) == sorted(solvers)
+
+
+@pytest.mark.parametrize("struct", ["dda_solve_opts", "dda_solve_info", "dda_batch_item"])
+def test_binding_struct_fields_follow_header(struct):
+    """The ctypes structures list the header's fields in the header's order."""
+    from paper_0908_0863_amd import dda
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct + ";", _header()).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(\w+)\s*;", body)
+    assert [f for f, _ in getattr(dda, struct)._fields_] == fields

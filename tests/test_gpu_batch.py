@@ -59,7 +59,7 @@ def _rel(a, b):
 @pytest.mark.parametrize("precision,use_graph", [("fp64", False), ("mixed", True)])
 def test_batch_matches_individual_solves(lib, precision, use_graph):
     items = _targets(lib)
-    kw = dict(solver="qmr", precision=precision, tol=1e-10, inner_tol=1e-4, use_graph=use_graph, check_every=8)
+    kw = dict(solver="qmr_sym", precision=precision, tol=1e-10, inner_tol=1e-4, use_graph=use_graph, check_every=8)
     single = [it["target"].solve(khat=it["khat"], ehat=it["ehat"], **kw) for it in items]
     batch = lib.batch_solve([dict(target=it["target"], khat=it["khat"], ehat=it["ehat"]) for it in items],
                             nworkers=3, **kw)

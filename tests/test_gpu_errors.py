@@ -71,19 +71,23 @@ def test_out_of_order_and_bad_material(dda, lib):
         t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]], tol=2.0)
     assert _code(e) == dda.DDA_EINVAL
     with pytest.raises(dda.DDAError) as e:
+        t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]], solver="rbicgstab", solver_param=5)   # l above 4
+    assert _code(e) == dda.DDA_EINVAL
+    with pytest.raises(dda.DDAError) as e:
         t.far_field(t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]])[0], [[1.0, 1.0, 0.0]])  # not a unit vector
     assert _code(e) == dda.DDA_EINVAL
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
-def test_iteration_limit_reports_not_converged(dda, lib, solver):
+@pytest.mark.parametrize("solver,param", [("bicgstab", 0), ("qmr_sym", 0), ("bicg_sym", 0), ("cgs", 0), ("tfqmr", 0),
+                                          ("bicg", 0), ("qmr", 0), ("rbicgstab", 2), ("mlbicgstab", 3)])
+def test_iteration_limit_reports_not_converged(dda, lib, solver, param):
     w = inputs.workload("sphere16")
     t = dda.Target(lib, 16, 16, 16, w["kd"])
     nd = t.set_occupancy(w["occ"])
     t.set_permittivity(np.full(nd, w["m"] ** 2), "ldr")
     t.build_spectrum()
-    kw = dict(khat=w["khat"][:1], ehat=w["ehat"][:1], solver=solver, precision="fp64", tol=1e-12, max_iter=3,
-              max_outer=1)
+    kw = dict(khat=w["khat"][:1], ehat=w["ehat"][:1], solver=solver, solver_param=param, precision="fp64", tol=1e-12,
+              max_iter=3, max_outer=1)
     with pytest.raises(dda.NotConverged):
         t.solve(**kw)
     P, info = t.solve(raise_on_fail=False, **kw)

@@ -36,7 +36,7 @@ def sphere16(lib):
     kh = [[0.0, 0.0, 1.0], [0.0, 0.0, 1.0]]
     eh = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]
     E = t.incident_field(kh, eh)
-    P, _ = t.solve(einc=E, S=[0.0, 0.0], solver="qmr", precision="fp64", tol=1e-12)
+    P, _ = t.solve(einc=E, S=[0.0, 0.0], solver="qmr_sym", precision="fp64", tol=1e-12)
     sites = ora.sites_of(w["occ"])
     ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0)
     Po = [ora.solve_dense(sites, kd, ainv, ora.einc(sites, kd, kh[r], eh[r])) for r in range(2)]
@@ -102,7 +102,7 @@ def test_optical_theorem_full_size_cube64(lib):
     t.set_permittivity(np.full(nd, w["m"] ** 2), "ldr")
     t.build_spectrum()
     E = t.incident_field(w["khat"], w["ehat"])
-    P, _ = t.solve(einc=E, S=[0.0], solver="qmr", precision="fp64", tol=1e-10)
+    P, _ = t.solve(einc=E, S=[0.0], solver="qmr_sym", precision="fp64", tol=1e-10)
     ce, ca, _ = t.cross_sections(E, P, S=[0.0])
     torch.cuda.synchronize()
     import time

@@ -125,36 +125,51 @@ def test_symmetry_of_gpu_matvec(lib):
     assert abs(a - b) <= 1e-12 * abs(a)
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
-def test_solve_fp64_sphere16_matches_lu(lib, solver):
+# every scheme; (name, solver_param) with the l of RBiCGSTAB and the n of ML(n)BiCGSTAB
+SOLVERS = [("bicgstab", 0), ("qmr_sym", 0), ("bicg_sym", 0), ("cgs", 0), ("tfqmr", 0), ("bicg", 0), ("qmr", 0),
+           ("rbicgstab", 1), ("rbicgstab", 2), ("rbicgstab", 4), ("mlbicgstab", 1), ("mlbicgstab", 2),
+           ("mlbicgstab", 3), ("mlbicgstab", 4)]
+SOLVER_IDS = [f"{a}{b or ''}" for a, b in SOLVERS]
+
+
+_LU_CACHE = {}
+
+
+def _sphere16_lu(kd, eps, khat, ehat, S):
+    """Dense LU solution of the 16^3 sphere (the oracle), computed once per
+    right-hand side and shared by every solver's test."""
+    key = (kd, eps, tuple(np.ravel(khat)), tuple(np.ravel(ehat)), S)
+    if key not in _LU_CACHE:
+        w = inputs.workload("sphere16")
+        sites = ora.sites_of(w["occ"])
+        ainv = ora.alpha_inv(np.full(sites.shape[0], eps), kd, "ldr", S)
+        _LU_CACHE[key] = ora.solve_dense(sites, kd, ainv, ora.einc(sites, kd, khat, ehat))
+    return _LU_CACHE[key]
+
+
+@pytest.mark.parametrize("solver,param", SOLVERS, ids=SOLVER_IDS)
+def test_solve_fp64_sphere16_matches_lu(lib, solver, param):
     w = inputs.workload("sphere16")
     eps = w["m"] ** 2
     t, nd = _target(lib, w["occ"], w["kd"], eps)
-    sites = ora.sites_of(w["occ"])
     khat = np.array(w["khat"])
     ehat = np.array(w["ehat"], dtype=np.complex128)
-    P, info = t.solve(khat=khat, ehat=ehat, solver=solver, precision="fp64", tol=1e-12)
+    P, info = t.solve(khat=khat, ehat=ehat, solver=solver, solver_param=param, precision="fp64", tol=1e-12)
     P = P.cpu().numpy()
     for r in range(2):
         assert info[r]["converged"] and info[r]["rel_residual"] <= 1e-12
-        S = ora.ldr_S(khat[r], ehat[r])
-        ainv = ora.alpha_inv(np.full(nd, eps), w["kd"], "ldr", S)
-        E = ora.einc(sites, w["kd"], khat[r], ehat[r])
-        Po = ora.solve_dense(sites, w["kd"], ainv, E)
+        Po = _sphere16_lu(w["kd"], eps, khat[r], ehat[r], ora.ldr_S(khat[r], ehat[r]))
         assert _rel(P[r], Po) < 1e-10
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
-def test_solve_mixed_sphere16(lib, solver):
+@pytest.mark.parametrize("solver,param", SOLVERS, ids=SOLVER_IDS)
+def test_solve_mixed_sphere16(lib, solver, param):
     w = inputs.workload("sphere16")
     eps = w["m"] ** 2
     t, nd = _target(lib, w["occ"], w["kd"], eps)
-    sites = ora.sites_of(w["occ"])
-    P, info = t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]], solver=solver, precision="mixed", tol=1e-10,
-                      inner_tol=1e-4)
-    ainv = ora.alpha_inv(np.full(nd, eps), w["kd"], "ldr", 0.0)
-    E = ora.einc(sites, w["kd"], [0, 0, 1], [1, 0, 0])
-    Po = ora.solve_dense(sites, w["kd"], ainv, E)
+    P, info = t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]], solver=solver, solver_param=param, precision="mixed",
+                      tol=1e-10, inner_tol=1e-4)
+    Po = _sphere16_lu(w["kd"], eps, [0, 0, 1], [1, 0, 0], 0.0)
     assert info[0]["converged"] and info[0]["outer_iterations"] >= 2
     assert _rel(P[0].cpu().numpy(), Po) < 1e-8
 
@@ -167,7 +182,7 @@ def test_cross_sections_sphere16(lib):
     sites = ora.sites_of(w["occ"])
     khat, ehat = np.array(w["khat"]), np.array(w["ehat"], np.complex128)
     E = t.incident_field(khat, ehat)
-    P, info = t.solve(einc=E, S=[0.0, 0.0], solver="qmr", precision="fp64", tol=1e-12)
+    P, info = t.solve(einc=E, S=[0.0, 0.0], solver="qmr_sym", precision="fp64", tol=1e-12)
     ce, ca, cs = t.cross_sections(E, P, S=[0.0, 0.0])
     Eo = ora.einc(sites, kd, khat[0], ehat[0])
     assert _rel(E[0].cpu().numpy(), Eo) < 1e-14
@@ -190,22 +205,22 @@ def test_gradient_matches_dense_adjoint_sphere10(lib):
     eps = w["m"] ** 2 + 0.05 * (rng.random(nd) + 1j * rng.random(nd))
     t, _ = _target(lib, occ, kd, eps)
     E = t.incident_field([[0, 0, 1]], [[1, 0, 0]])
-    P, info = t.solve(einc=E, S=[0.0], solver="qmr", precision="fp64", tol=1e-12)
-    g = t.grad_cabs_eps(P, S=[0.0], solver="qmr", precision="fp64", tol=1e-12).cpu().numpy()
+    P, info = t.solve(einc=E, S=[0.0], solver="qmr_sym", precision="fp64", tol=1e-12)
+    g = t.grad_cabs_eps(P, S=[0.0], solver="qmr_sym", precision="fp64", tol=1e-12).cpu().numpy()
     Eo = ora.einc(sites, kd, [0, 0, 1], [1, 0, 0])
     go, _ = ora.grad_cabs_adjoint_dense(sites, kd, eps, "ldr", 0.0, Eo)
     assert _rel(g[0], go) < 1e-9
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "qmr", "bicg_sym", "cgs", "tfqmr"])
+@pytest.mark.parametrize("solver,param", SOLVERS, ids=SOLVER_IDS)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replay_matches_eager(lib, solver, precision):
+def test_graph_replay_matches_eager(lib, solver, param, precision):
     """The captured iteration (HIP graph, replayed several times with eager
     work and host read-backs in between) gives bitwise the eager result."""
     w = inputs.workload("sphere16")
     t, nd = _target(lib, w["occ"], w["kd"], w["m"] ** 2)
-    kw = dict(khat=[[0, 0, 1], [0, 0, 1]], ehat=[[1, 0, 0], [0, 1, 0]], solver=solver, precision=precision,
-              tol=1e-9, inner_tol=1e-4, check_every=4)
+    kw = dict(khat=[[0, 0, 1], [0, 0, 1]], ehat=[[1, 0, 0], [0, 1, 0]], solver=solver, solver_param=param,
+              precision=precision, tol=1e-9, inner_tol=1e-4, check_every=4)
     Pe, ie = t.solve(use_graph=False, **kw)
     for _ in range(3):
         Pg, ig = t.solve(use_graph=True, **kw)
@@ -280,7 +295,7 @@ def test_matvec_composition_matches_dense(lib, shape, jacobi):
         assert _rel(y32[r], yo) < 2e-6, (shape, r)
 
 
-@pytest.mark.parametrize("solver", ["qmr", "bicgstab"])
+@pytest.mark.parametrize("solver", ["qmr_sym", "bicgstab"])
 def test_solve_composition_matches_lu(lib, solver):
     from paper_0908_0863_amd import dda
     mats = [2.4 + 0.3j, 1.6 + 0.02j]
