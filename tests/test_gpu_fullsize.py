@@ -182,9 +182,9 @@ def test_autograd_gradcheck_sphere10(lib):
 @pytest.mark.timeout(900)
 def test_iteration_counts_sphere200_table3(lib):
     """The paper's benchmark solve (Table 3): iteration counts of all ten
-    schemes (with the SV variants of RBiCGSTAB and ML(n)BiCGSTAB) within 50%
-    of the printed ones (the paper leaves the stopping rule and the
-    polarisability unstated, so only the scale is fixed)."""
+    schemes (with the SV variants of RBiCGSTAB and ML(n)BiCGSTAB) within two
+    iterations or 20% of the printed ones (the paper leaves its stopping rule
+    and the polarisability unstated, so an exact match is not expected)."""
     w = inputs.workload("sphere200")
     t, nd = _target(lib, w)
     assert nd == 4188896
@@ -196,4 +196,4 @@ def test_iteration_counts_sphere200_table3(lib):
         print(f"sphere200 {solver} {sv}: {it} iterations (paper {ni}), residual {info[0]['rel_residual']:.2e}",
               flush=True)
         assert info[0]["converged"]
-        assert 0.5 * int(ni) <= it <= 1.5 * int(ni), (solver, sv, it, ni)
+        assert abs(it - int(ni)) <= max(2, 0.2 * int(ni)), (solver, sv, it, ni)
