@@ -230,7 +230,8 @@ def test_graph_replay_matches_eager(lib, solver, param, precision):
         assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
 
 
-FUSED_SHAPES = [(16, 16, 16), (32, 30, 5), (45, 40, 3)]  # padded x = padded y: fused xy-plane passes apply
+# padded x = padded y: fused xy-plane passes apply; the last two have P'' = 64 and 128
+FUSED_SHAPES = [(16, 16, 16), (32, 30, 5), (45, 40, 3), (10, 10, 32), (12, 12, 64)]
 
 
 @pytest.mark.parametrize("shape", FUSED_SHAPES)
