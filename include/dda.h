@@ -251,7 +251,11 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * D in {2, 4, 8} the fused xy-plane passes with the frequency range split
  * into D residue classes.  DDA_EINVAL if that schedule does not exist for the
  * lattice. */
-enum { DDA_OPT_SCHEDULE = 1 };
+/* DDA_OPT_INJECT_BREAKDOWN (fault injection for tests of the recovery path):
+ * the next `value` BiCGSTAB inner solves start from a zero shadow vector, so
+ * their first step breaks down (rhat^H v = 0) and the refinement loop must
+ * restart from the true residual.  DDA_EINVAL for a negative value. */
+enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:

@@ -225,6 +225,7 @@ struct dda_target {
   PrecBufs<float> p32;
   bool spec_ready = false;
   int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
+  int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
   int sched_override = -1;   // autotuner: schedule under trial (-1: none)
   // per-solve scratch
   DevBuf S;       // double [cap]
@@ -478,6 +479,10 @@ int dda_target_set_option(dda_target* t, int option, int value) {
       t->forced_sched = value < 0 ? -1 : value;
       return DDA_OK;
     }
+    case DDA_OPT_INJECT_BREAKDOWN:
+      if (value < 0) return fail(DDA_EINVAL, "dda_target_set_option: inject count %d", value);
+      t->inject_breakdown = value;
+      return DDA_OK;
     default:
       return fail(DDA_EINVAL, "dda_target_set_option: option %d", option);
   }
@@ -1684,6 +1689,11 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
     hipLaunchKernelGGL((k_bcg_init<R>), vg, dim3(kRedThreads), 0, st, b, slot(2), slot(3), slot(4), slot(5), u, act, dm,
                        R3);
     hipLaunchKernelGGL(k_bcg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
+    if (t->inject_breakdown > 0) {
+      // fault injection: rhat = 0 makes rhat^H v vanish in the first step
+      --t->inject_breakdown;
+      HIPCHK(hipMemsetAsync(slot(3), 0, vsz * sizeof(cx<R>), st));
+    }
   } else if (tf) {
     // slot 2 = rt, 3 = w, 4 = ue, 5 = uo, 6 = v, 7 = d, 8 = A ue, 9 = A uo;
     // the first product A ue (with rt^H A ue) completes the initialisation
@@ -1981,9 +1991,9 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   std::vector<double> rn2, en2;
   // P = 0: the residual is E
   HIPCHK(hipMemcpyAsync(r64, E, (size_t)nrhs * n3 * sizeof(c64), hipMemcpyDeviceToDevice, st));
-  {
-    CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
-  }
+  CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
+  for (int q = 0; q < nrhs; ++q)
+    if (!std::isfinite(en2[q])) return fail(DDA_EINVAL, "dda_solve: right-hand side %d is not finite", q);
   std::vector<int> iters(nrhs, 0), outer(nrhs, 0), done(nrhs, 0);
   InnerResult ir;
   ir.iters.resize(nrhs);

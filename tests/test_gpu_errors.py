@@ -94,3 +94,47 @@ def test_iteration_limit_reports_not_converged(dda, lib, solver, param):
     assert info[0]["converged"] == 0 and info[0]["iterations"] <= 4
     assert 1e-12 < info[0]["rel_residual"] < 1.0        # a partial solution, not garbage
     assert torch.isfinite(torch.view_as_real(P)).all()
+
+
+def _sphere16(dda, lib):
+    w = inputs.workload("sphere16")
+    t = dda.Target(lib, 16, 16, 16, w["kd"])
+    nd = t.set_occupancy(w["occ"])
+    t.set_permittivity(np.full(nd, w["m"] ** 2), "ldr")
+    t.build_spectrum()
+    return t, w
+
+
+def test_non_finite_right_hand_side_rejected(dda, lib):
+    t, w = _sphere16(dda, lib)
+    E = t.incident_field(w["khat"][:1], w["ehat"][:1])
+    E[0, 1, 5] = complex(float("nan"), 0.0)
+    with pytest.raises(dda.DDAError) as e:
+        t.solve(einc=E, S=[0.0], solver="bicgstab", precision="fp64", tol=1e-8)
+    assert _code(e) == dda.DDA_EINVAL
+    with pytest.raises(dda.DDAError) as e:
+        t.set_option(dda.DDA_OPT_INJECT_BREAKDOWN, -1)
+    assert _code(e) == dda.DDA_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_injected_breakdown_restarts_from_true_residual(dda, lib, precision):
+    """Two BiCGSTAB inner solves that start from a zero shadow vector break
+    down in their first step (rhat^H v = 0); the refinement loop restarts each
+    time from the FP64 true residual and the solve still reaches the answer of
+    the undisturbed one."""
+    t, w = _sphere16(dda, lib)
+    kw = dict(khat=w["khat"][:1], ehat=w["ehat"][:1], solver="bicgstab", precision=precision, tol=1e-10,
+              inner_tol=1e-4)
+    P0, i0 = t.solve(**kw)
+    t.set_option(dda.DDA_OPT_INJECT_BREAKDOWN, 2)
+    P1, i1 = t.solve(**kw)
+    assert i0[0]["converged"] and i1[0]["converged"]
+    # two wasted refinement steps, then at least one that solves (in mixed
+    # precision the first breakdown also switches the inner solves to FP64)
+    assert i1[0]["outer_iterations"] >= 3
+    if precision == "fp64":
+        assert i0[0]["outer_iterations"] == 1
+    assert (torch.linalg.norm(P1 - P0) / torch.linalg.norm(P0)).item() < 1e-8
+    P2, i2 = t.solve(**kw)  # the injections are used up
+    assert i2[0]["outer_iterations"] == i0[0]["outer_iterations"]
