@@ -255,7 +255,11 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * the next `value` BiCGSTAB inner solves start from a zero shadow vector, so
  * their first step breaks down (rhat^H v = 0) and the refinement loop must
  * restart from the true residual.  DDA_EINVAL for a negative value. */
-enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2 };
+/* DDA_OPT_CANARY (debug, value 0 or 1): dda_matvec fills its FFT workspaces
+ * with NaN (hipMemsetAsync, so not for stream capture) before the passes, so
+ * that a pruned pass reading data no earlier pass wrote shows as a non-finite
+ * or wrong product. */
+enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:

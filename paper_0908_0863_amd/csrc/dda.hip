@@ -226,6 +226,7 @@ struct dda_target {
   bool spec_ready = false;
   int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
   int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
+  int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
   int sched_override = -1;   // autotuner: schedule under trial (-1: none)
   // per-solve scratch
   DevBuf S;       // double [cap]
@@ -482,6 +483,10 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_INJECT_BREAKDOWN:
       if (value < 0) return fail(DDA_EINVAL, "dda_target_set_option: inject count %d", value);
       t->inject_breakdown = value;
+      return DDA_OK;
+    case DDA_OPT_CANARY:
+      if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: canary %d", value);
+      t->canary = value;
       return DDA_OK;
     default:
       return fail(DDA_EINVAL, "dda_target_set_option: option %d", option);
@@ -1340,14 +1345,24 @@ extern "C" int dda_matvec(dda_target* t, int precision, int nrhs, const double* 
     for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
   HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
+  // canaries: every workspace element starts as NaN (all bits set), so a pass
+  // that reads what no earlier pass wrote poisons the product
+  auto fill_canaries = [&](auto& b) -> int {
+    if (!t->canary) return DDA_OK;
+    HIPCHK(hipMemsetAsync(b.G1.p, 0xFF, b.G1.bytes, st));
+    HIPCHK(hipMemsetAsync(b.G2.p, 0xFF, b.G2.bytes, st));
+    return DDA_OK;
+  };
   if (precision == DDA_FP64) {
     CHK(ensure_matvec_ws<double>(t, nrhs));
     CHK(autotune<double>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c64*)x_dev, (c64*)y_dev, st));
+    CHK(fill_canaries(t->p64));
     return matvec_T<double>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c64*)x_dev, (c64*)y_dev, nullptr, st);
   }
   if (precision == DDA_FP32) {
     CHK(ensure_matvec_ws<float>(t, nrhs));
     CHK(autotune<float>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, st));
+    CHK(fill_canaries(t->p32));
     return matvec_T<float>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, nullptr, st);
   }
   return fail(DDA_EINVAL, "dda_matvec: precision %d", precision);

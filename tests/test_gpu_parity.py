@@ -263,6 +263,32 @@ def test_matvec_fused_and_five_pass_schedules(lib, shape, sched, jacobi):
         assert _rel(y32[r], yo) < 2e-6, (shape, r)
 
 
+@pytest.mark.parametrize("shape", FUSED_SHAPES)
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 8])
+def test_pruned_passes_never_read_unwritten_workspace(lib, shape, sched):
+    """With NaN canaries in every FFT workspace element before the product,
+    every schedule still gives the oracle's product: no pass reads a padded
+    line or plane that the pruned passes before it left unwritten."""
+    from paper_0908_0863_amd import dda
+    K, J, P = shape
+    occ = inputs.sphere(16) if shape == (16, 16, 16) else _rand_occ((P, J, K), 12)
+    kd, eps = 0.42, 2.2 + 0.15j
+    t, nd = _target(lib, occ, kd, eps)
+    try:
+        t.set_option(dda.DDA_OPT_SCHEDULE, sched)
+    except dda.DDAError:
+        pytest.skip(f"no schedule {sched} for {shape}")
+    t.set_option(dda.DDA_OPT_CANARY, 1)
+    x = inputs.complex_gaussian(21, (1, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=[0.1]).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=[0.1]).cpu().numpy()
+    assert np.isfinite(y).all() and np.isfinite(y32).all()
+    ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.1)
+    yo = ora.dense_matvec(ora.sites_of(occ), kd, ainv, x[0])
+    assert _rel(y[0], yo) < 1e-12
+    assert _rel(y32[0], yo) < 2e-6
+
+
 # --- anisotropic, multi-material composition (Sec. 2) -------------------------
 
 def _composed(lib, shape, seed, kd, mats):
