@@ -71,6 +71,63 @@ def test_matvec_full_size_sampled_rows(lib, name):
         assert err < (1e-12 if dt == np.complex128 else FP32_FULL_TOL), (name, dt, err)
 
 
+def _ellipsoid96_S(w):
+    return np.array([ora.ldr_S(k, e) for k, e in zip(w["khat"], w["ehat"])])
+
+
+def test_batched_128_rhs_matvec_sampled_rows(lib):
+    """The 96^3 ellipsoid with all 128 right-hand sides (64 directions x 2
+    polarisations, each with its own LDR S) in one product, as the batched
+    solve runs it: sampled rows of three right-hand sides against the dense
+    oracle, FP64 and FP32."""
+    w = inputs.workload("ellipsoid96")
+    t, nd = _target(lib, w)
+    sites = ora.sites_of(w["occ"])
+    S = _ellipsoid96_S(w)
+    n = S.size
+    assert n == 128
+    x32 = torch.from_numpy(inputs.complex_gaussian(3, (n, 3, nd)).astype(np.complex64)).cuda()
+    rows = np.sort(np.random.default_rng(1).choice(nd, 1024, replace=False))
+    picks = [0, 77, 127]
+    yo = {}
+    for r in picks:
+        ainv = ora.alpha_inv(np.full(nd, w["m"] ** 2), w["kd"], "ldr", S[r])
+        s = 1.0 / np.sqrt(ainv)
+        xr = x32[r].cpu().numpy().astype(np.complex128)
+        yo[r] = s[rows] * ora.dense_matvec(sites, w["kd"], ainv, s * xr, rows=rows)
+    for x in (x32.to(torch.complex128), x32):
+        y = t.matvec(x, S=S, jacobi=True)
+        for r in picks:
+            err = _rel(y[r].cpu().numpy()[:, rows], yo[r])
+            print(f"ellipsoid96 x128 {x.dtype} rhs {r}: rel err {err:.3e}", flush=True)
+            assert err < (1e-12 if x.dtype == torch.complex128 else FP32_FULL_TOL), (r, x.dtype, err)
+        del y
+
+
+@pytest.mark.timeout(600)
+def test_batched_128_rhs_mixed_solve_sampled_residual(lib):
+    """The batched mixed-precision solve of the 96^3 ellipsoid (128 RHS, QMR_sym
+    to 1e-6, the configuration the batch benchmark times): every right-hand
+    side reports convergence, and the true residual E - A P recomputed by the
+    dense oracle on sampled rows of two of them stays at the tolerance's scale."""
+    w = inputs.workload("ellipsoid96")
+    t, nd = _target(lib, w)
+    sites = ora.sites_of(w["occ"])
+    S = _ellipsoid96_S(w)
+    P, info = t.solve(khat=w["khat"], ehat=w["ehat"], solver="qmr_sym", precision="mixed", tol=1e-6, inner_tol=1e-4,
+                      check_every=16, use_graph=True)
+    assert all(i["converged"] and i["rel_residual"] <= 1e-6 for i in info)
+    rows = np.sort(np.random.default_rng(2).choice(nd, 1024, replace=False))
+    for r in (0, 127):
+        ainv = ora.alpha_inv(np.full(nd, w["m"] ** 2), w["kd"], "ldr", S[r])
+        E = ora.einc(sites, w["kd"], w["khat"][r], w["ehat"][r])[:, rows]
+        AP = ora.dense_matvec(sites, w["kd"], ainv, P[r].cpu().numpy(), rows=rows)
+        rel = float(np.linalg.norm(E - AP) / np.linalg.norm(E))
+        print(f"ellipsoid96 x128 mixed rhs {r}: sampled-row residual {rel:.2e}, reported "
+              f"{info[r]['rel_residual']:.2e}", flush=True)
+        assert rel < 1e-5
+
+
 def test_validation_cube100_efficiencies(lib):
     w = inputs.workload("cube100")
     t, nd = _target(lib, w)
