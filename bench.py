@@ -33,7 +33,7 @@ def pass_bytes(K, J, P, Kpp, Jpp, Kh, Jh, Ph, nd, b, jacobi):
     grid_y = 3 * K * Jpp * P      # y-transformed array, complex values
     grid_xy = 3 * Kpp * Jpp * P   # x- and y-transformed array
     spec = 6 * Kh * Jh * Ph
-    idx = 4 * K * J * P           # int32 site map
+    idx = 8 * ((K + 31) // 32) * J * P  # bit-fielded occupancy: (bits, base) per 32 sites of a row
     diag = nd * b * (1 if jacobi else 1)
     return {
         "y_forward": 3 * nd * b + idx + grid_y * b + (diag if jacobi else 0),

@@ -215,7 +215,8 @@ struct dda_target {
   int Kpp = 0, Jpp = 0, Ppp = 0, Kh = 0, Jh = 0, Ph = 0;
   FftDesc fx{}, fy{}, fz{};
   int64_t nd = 0;
-  DevBuf map;    // int [P][J][K], -1 where empty
+  int occ_words = 0;  // W of the bit-fielded occupancy
+  DevBuf occ;    // uint2 [P][J][W] (bits, occupied sites before the word), W = ceil(K / 32)
   DevBuf sites;  // int [nd] linear index
   bool have_alpha = false, have_eps = false, has_a1 = false;
   bool aniso = false;  // the three components' diagonals differ (dda_set_composition)
@@ -260,6 +261,14 @@ template <>
 PrecBufs<double>& bufs<double>(dda_target* t) { return t->p64; }
 template <>
 PrecBufs<float>& bufs<float>(dda_target* t) { return t->p32; }
+
+// the occupancy as the expand / compress passes read it
+static OccBits occ_of(const dda_target* t) {
+  OccBits o;
+  o.words = (const uint2*)t->occ.p;
+  o.W = t->occ_words;
+  return o;
+}
 
 template <typename R>
 static std::vector<int> xy_candidates(const dda_target* t);
@@ -515,19 +524,28 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   if (!t || !occ) return fail(DDA_EINVAL, "dda_set_occupancy: NULL argument");
   HIPCHK(hipSetDevice(t->lib->device));
   const long N = (long)t->K * t->J * t->P;
-  std::vector<int> map(N), sites;
-  for (long s = 0; s < N; ++s) {
-    if (occ[s]) {
-      map[s] = (int)sites.size();
-      sites.push_back((int)s);
-    } else {
-      map[s] = -1;
+  const int W = (t->K + 31) / 32;
+  const long nrow = (long)t->J * t->P;
+  std::vector<uint32_t> words((size_t)nrow * W * 2, 0u);  // (bits, base) pairs
+  std::vector<int> sites;
+  for (long r = 0; r < nrow; ++r)
+    for (int w = 0; w < W; ++w) {
+      uint32_t* wd = &words[((size_t)r * W + w) * 2];
+      wd[1] = (uint32_t)sites.size();
+      for (int b = 0; b < 32 && 32 * w + b < t->K; ++b) {
+        const long s = r * t->K + 32 * w + b;
+        if (occ[s]) {
+          wd[0] |= 1u << b;
+          sites.push_back((int)s);
+        }
+      }
     }
-  }
   if (sites.empty()) return fail(DDA_EINVAL, "dda_set_occupancy: no occupied site");
-  CHK(t->map.ensure(N * sizeof(int)));
+  (void)N;
+  CHK(t->occ.ensure(words.size() * sizeof(uint32_t)));
   CHK(t->sites.ensure(sites.size() * sizeof(int)));
-  HIPCHK(hipMemcpy(t->map.p, map.data(), N * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t->occ.p, words.data(), words.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  t->occ_words = W;
   HIPCHK(hipMemcpy(t->sites.p, sites.data(), sites.size() * sizeof(int), hipMemcpyHostToDevice));
   t->nd = (int64_t)sites.size();
   t->have_alpha = t->have_eps = false;
@@ -838,7 +856,7 @@ struct FastLaunch {
     hipLaunchKernelGGL((k_zline<R, N, RL>), grid, dim3(FastPlan<N>::T * RL), 0, st, G2t, Yz, act, za, zm, tw);
   }
   template <int N>
-  static void yfwd(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, const int* map, const cx<R>* a0,
+  static void yfwd(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
                    const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw) {
     constexpr int TX = fast_tx<N>();
     dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
@@ -846,7 +864,7 @@ struct FastLaunch {
                        va, tw);
   }
   template <int N>
-  static void yinv(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, const int* map,
+  static void yinv(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
                    const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
                    DotArgs dot) {
     constexpr int TX = fast_tx<N>();
@@ -936,7 +954,7 @@ static int launch_xy_fwd(dda_target* t, int nrhs, hipStream_t st, const cx<R>* x
   }
   const int ngroups = nrhs * 3 * t->P;
   dim3 grid(8 * D * ((ngroups + 7) / 8));
-  hipLaunchKernelGGL((k_xy_fwd<R, NN, D>), grid, dim3(256), lds, st, x, G2, t->map.as<int>(), a0, a1, dS, act, va,
+  hipLaunchKernelGGL((k_xy_fwd<R, NN, D>), grid, dim3(256), lds, st, x, G2, occ_of(t), a0, a1, dS, act, va,
                      ngroups, bufs<R>(t).tw[1].template as<cx<R>>(), bufs<R>(t).tw[0].template as<cx<R>>());
   LAUNCHCHK();
   return DDA_OK;
@@ -955,7 +973,7 @@ static int launch_xy_inv(dda_target* t, int nrhs, hipStream_t st, const cx<R>* G
   }
   const int ngroups = nrhs * 3 * t->P;
   dim3 grid(8 * D * ((ngroups + 7) / 8));
-  hipLaunchKernelGGL((k_xy_inv<R, NN, D>), grid, dim3(256), lds, st, G2, x, y, t->map.as<int>(), a0, a1, dS, act,
+  hipLaunchKernelGGL((k_xy_inv<R, NN, D>), grid, dim3(256), lds, st, G2, x, y, occ_of(t), a0, a1, dS, act,
                      va, ngroups, bufs<R>(t).tw[1].template as<cx<R>>(), bufs<R>(t).tw[0].template as<cx<R>>(), dot);
   LAUNCHCHK();
   return DDA_OK;
@@ -1069,7 +1087,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
-    FastLaunch<R>::template yfwd<N>(dim3(1, P, nrhs * 3), st, x, G1, t->map.as<int>(), a0, a1, dS, active, va, \
+    FastLaunch<R>::template yfwd<N>(dim3(1, P, nrhs * 3), st, x, G1, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>());                                            \
     break;
         DDA_FAST_SIZES(DDA_CASE)
@@ -1078,7 +1096,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     } else {
       const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
       dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
-      hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, t->map.as<int>(), a0, a1, dS,
+      hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, occ_of(t), a0, a1, dS,
                          active, va, t->fy, b.tw[1].template as<cx<R>>());
     }
     LAUNCHCHK();
@@ -1214,7 +1232,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                             \
   case N:                                                                                                       \
-    FastLaunch<R>::template yinv<N>(dim3(1, P, nrhs * 3), st, G1, x, y, t->map.as<int>(), a0, a1, dS, active, va, \
+    FastLaunch<R>::template yinv<N>(dim3(1, P, nrhs * 3), st, G1, x, y, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), dot);                                           \
     break;
         DDA_FAST_SIZES(DDA_CASE)
@@ -1223,7 +1241,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     } else {
       const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
       dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
-      hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, t->map.as<int>(), a0, a1, dS,
+      hipLaunchKernelGGL((k_vec_yinv<R>), grid, dim3(kThreads), lds, st, G1, x, y, occ_of(t), a0, a1, dS,
                          active, va, t->fy, b.tw[1].template as<cx<R>>(), dot);
     }
     LAUNCHCHK();

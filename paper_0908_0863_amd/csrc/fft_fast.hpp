@@ -208,7 +208,7 @@ struct FastStages3 {
 // ---------------------------------------------------------------------------
 template <typename R, int N, int TX>
 __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
-    const cx<R>* __restrict__ x, cx<R>* __restrict__ G1, const int* __restrict__ map, const cx<R>* __restrict__ a0,
+    const cx<R>* __restrict__ x, cx<R>* __restrict__ G1, OccBits map, const cx<R>* __restrict__ a0,
     const cx<R>* __restrict__ a1, const double* __restrict__ S, const int* __restrict__ active, VecArgs a,
     const cx<R>* __restrict__ tw) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
     const int e = t + T * m;
     cx<R> val = mk((R)0, (R)0);
     if (e < a.J && i < a.K) {
-      const int n = map[((long)k * a.J + e) * a.K + i];
+      const int n = site_index(map, (long)k * a.J + e, i);
       if (n >= 0) {
         val = xv[n];
         if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, cd + n)) * val;
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
 // standard algorithm), with the solver's inner products fused (DotArgs).
 template <typename R, int N, int TX>
 __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
-    const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, const int* __restrict__ map,
+    const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, OccBits map,
     const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1, const double* __restrict__ S,
     const int* __restrict__ active, VecArgs a, const cx<R>* __restrict__ tw, DotArgs dt) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
     for (int m = 0; m < E; ++m) {
       const int e = t + T * m;
       if (e >= a.J) continue;
-      const int n = map[((long)k * a.J + e) * a.K + i];
+      const int n = site_index(map, (long)k * a.J + e, i);
       if (n < 0) continue;
       const cx<R> conv = sc * v[m];
       const cx<R> dg = diag_of(a0, a1, Sr, cd + n);
@@ -536,7 +536,7 @@ struct XYPlan {
 
 template <typename R, int NN, int D>
 __global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<R>* __restrict__ G2,
-                                                const int* __restrict__ map, const cx<R>* __restrict__ a0,
+                                                OccBits map, const cx<R>* __restrict__ a0,
                                                 const cx<R>* __restrict__ a1, const double* __restrict__ S,
                                                 const int* __restrict__ active, VecArgs a, int ngroups,
                                                 const cx<R>* __restrict__ twy, const cx<R>* __restrict__ twx) {
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<
       cx<R> acc = mk((R)0, (R)0);
       if (i < a.K) {
         for (int j = j1; j < a.J; j += M) {
-          const int n = map[((long)k * a.J + j) * a.K + i];
+          const int n = site_index(map, (long)k * a.J + j, i);
           if (n >= 0) {
             cx<R> val = xv[n];
             if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, cd + n)) * val;
@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<
 
 template <typename R, int NN, int D>
 __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, const cx<R>* __restrict__ x,
-                                                cx<R>* __restrict__ y, const int* __restrict__ map,
+                                                cx<R>* __restrict__ y, OccBits map,
                                                 const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
                                                 const double* __restrict__ S, const int* __restrict__ active,
                                                 VecArgs a, int ngroups, const cx<R>* __restrict__ twy,
@@ -677,7 +677,7 @@ __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, co
       for (int m = 0; m < EY; ++m) {
         const int j = t + TY * m;
         if (j >= a.J) continue;
-        const int n = map[((long)k * a.J + j) * a.K + i];
+        const int n = site_index(map, (long)k * a.J + j, i);
         if (n < 0) continue;
         const cx<R> conv = sc * v[m];
         const cx<R> dg = diag_of(a0, a1, Sr, cd + n);

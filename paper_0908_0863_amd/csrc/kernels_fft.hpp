@@ -183,6 +183,24 @@ __device__ __forceinline__ cx<R> jacobi_scale(cx<R> a) {
   return cdiv(mk((R)1, (R)0), q);
 }
 
+// Bit-fielded occupancy (Sec. 2: the occupancy is stored one bit per lattice
+// site).  Row r = k J + j of the lattice holds W = ceil(K / 32) words; word w
+// is the pair (bits, base): bit b of `bits` marks site (32 w + b, j, k), and
+// `base` counts the occupied sites before word w in linear order, so the
+// dipole index of an occupied site is base + popcount of the lower bits.  One
+// 8-byte load per lookup.
+struct OccBits {
+  const uint2* __restrict__ words;
+  int W;
+};
+
+// Dipole index of site (i, row) or -1 if the site is empty.
+__device__ __forceinline__ int site_index(const OccBits& o, long row, int i) {
+  const uint2 wd = o.words[(int)row * o.W + (i >> 5)];
+  const uint32_t b = 1u << (i & 31);
+  return (wd.x & b) ? (int)wd.y + __popc(wd.x & (b - 1u)) : -1;
+}
+
 struct VecArgs {
   int K, J, P, Jpp, Kpp, Ppp;
   long nd;
@@ -197,7 +215,7 @@ struct VecArgs {
 // hold data (Sec. 3).  grid = (ceil(K/TX), P, nrhs*3).
 template <typename R>
 __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, cx<R>* __restrict__ G1,
-                                                  const int* __restrict__ map, const cx<R>* __restrict__ a0,
+                                                  OccBits map, const cx<R>* __restrict__ a0,
                                                   const cx<R>* __restrict__ a1, const double* __restrict__ S,
                                                   const int* __restrict__ active, VecArgs a, FftDesc d,
                                                   const cx<R>* __restrict__ tw) {
@@ -215,7 +233,7 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
     const int e = idx / TX, l = idx - e * TX, i = i0 + l;
     cx<R> v = mk((R)0, (R)0);
     if (e < a.J && i < a.K) {
-      const int m = map[((long)k * a.J + e) * a.K + i];
+      const int m = site_index(map, (long)k * a.J + e, i);
       if (m >= 0) {
         v = xv[m];
         if (a.jacobi) v = jacobi_scale(diag_of(a0, a1, Sr, cd + m)) * v;
@@ -264,7 +282,7 @@ __device__ __forceinline__ void dot_flush(const DotArgs& dt, int rhs, int c, c64
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ x,
-                                                  cx<R>* __restrict__ y, const int* __restrict__ map,
+                                                  cx<R>* __restrict__ y, OccBits map,
                                                   const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
                                                   const double* __restrict__ S, const int* __restrict__ active,
                                                   VecArgs a, FftDesc d, const cx<R>* __restrict__ tw, DotArgs dt) {
@@ -291,7 +309,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
   for (int idx = tid; idx < a.J * TX; idx += nthr) {
     const int e = idx / TX, l = idx - e * TX, i = i0 + l;
     if (i >= a.K) continue;
-    const int m = map[((long)k * a.J + e) * a.K + i];
+    const int m = site_index(map, (long)k * a.J + e, i);
     if (m < 0) continue;
     const cx<R> conv = sc * res[e * TX + l];
     const cx<R> dg = diag_of(a0, a1, Sr, cd + m);
