@@ -9,7 +9,7 @@ passes and Krylov vectors, FP64 residuals, refinement and inner products),
 and the cross sections.  Inputs are resident in HBM before timing starts.
 
 Prints ONE JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
-this build runs on one GPU.
+the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
