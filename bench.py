@@ -286,7 +286,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cube64")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="FP32 inner-solve tolerance (default: 5e-5 for the single-RHS line, 1e-4 for the batch modes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--profile-matvec", type=int, default=0,
@@ -301,6 +302,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=0, help="batch-rhs: right-hand sides (default: all)")
     ap.add_argument("--workers", type=int, default=0, help="batch-targets: host workers (default 4)")
     args = ap.parse_args()
+    if args.inner_tol <= 0:
+        args.inner_tol = 5e-5 if args.mode == "single" else 1e-4
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)

@@ -259,7 +259,11 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * with NaN (hipMemsetAsync, so not for stream capture) before the passes, so
  * that a pruned pass reading data no earlier pass wrote shows as a non-finite
  * or wrong product. */
-enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3 };
+/* DDA_OPT_FUSE_QMR_STEP (value 1, the default, or 0): QMR_sym runs the vector
+ * part of each step inside the y-forward pass of the next product where the
+ * schedule's y pass allows it (schedules 0, 1, 3); 0 keeps the separate step
+ * kernel.  Same recurrences either way. */
+enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:

@@ -228,6 +228,7 @@ struct dda_target {
   int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
   int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
   int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
+  int fuse_qmr = 1;          // QMR_sym step fused into the y-forward pass where possible
   int sched_override = -1;   // autotuner: schedule under trial (-1: none)
   // per-solve scratch
   DevBuf S;       // double [cap]
@@ -238,6 +239,7 @@ struct dda_target {
   DevBuf part_mv; // partials of the inner products fused into the matvec
   DevBuf scal;    // double [cap] scale factors
   DevBuf tolv;    // double [cap] inner tolerances
+  DevBuf qcoef;   // QmrCoef [cap]: fused QMR_sym step coefficients
   DevBuf outer;   // FP64 outer vectors: E, r, y  (3 x [cap][3][nd])
   DevBuf khat, ehat;
   DevBuf far_dirs, far_part, far_F, far_w, far_tp;  // far-field scratch
@@ -492,6 +494,10 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_INJECT_BREAKDOWN:
       if (value < 0) return fail(DDA_EINVAL, "dda_target_set_option: inject count %d", value);
       t->inject_breakdown = value;
+      return DDA_OK;
+    case DDA_OPT_FUSE_QMR_STEP:
+      if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: fuse %d", value);
+      t->fuse_qmr = value;
       return DDA_OK;
     case DDA_OPT_CANARY:
       if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: canary %d", value);
@@ -789,6 +795,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
+  CHK(t->qcoef.ensure(cap * sizeof(QmrCoef)));
   CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState), sizeof(CgsState),
                                              sizeof(TfqState), sizeof(GenState)})));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
@@ -857,11 +864,22 @@ struct FastLaunch {
   }
   template <int N>
   static void yfwd(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
-                   const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw) {
+                   const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
+                   const QmrFuse<R>* qf) {
     constexpr int TX = fast_tx<N>();
     dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
-    hipLaunchKernelGGL((k_fast_yfwd<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0, a1, S, act,
-                       va, tw);
+    if (qf)
+      hipLaunchKernelGGL((k_fast_yfwd<R, N, TX, true>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0, a1,
+                         S, act, va, tw, *qf);
+    else
+      hipLaunchKernelGGL((k_fast_yfwd<R, N, TX, false>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0,
+                         a1, S, act, va, tw, QmrFuse<R>{});
+  }
+  // y-forward blocks per right-hand side (3 components x P planes x x tiles)
+  template <int N>
+  static int yfwd_blocks(const dda_target* t) {
+    constexpr int TX = fast_tx<N>();
+    return 3 * t->P * ((t->K + TX - 1) / TX);
   }
   template <int N>
   static void yinv(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
@@ -1005,9 +1023,11 @@ static int yinv_blocks(const dda_target* t, int nrhs) {
   return 3 * t->P * ((t->K + tx - 1) / tx);
 }
 
+// qf (fused QMR_sym step): the y-forward pass forms its input from the
+// step's vectors (qmr_fusable schedules only).
 template <typename R>
 static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
-                    const int* active, hipStream_t st, DotArgs dot = DotArgs()) {
+                    const int* active, hipStream_t st, DotArgs dot = DotArgs(), const QmrFuse<R>* qf = nullptr) {
   CHK(ensure_matvec_ws<R>(t, nrhs));
   PrecBufs<R>& b = bufs<R>(t);
   const int K = t->K, J = t->J, P = t->P, Jpp = t->Jpp, Kpp = t->Kpp, Ppp = t->Ppp;
@@ -1029,6 +1049,7 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
   va.TX = tile_width<R>(K, Jpp, 2);
   const int sched = schedule_of<R>(t, nrhs);
   const int dfwd = is_fused(sched) ? sched : 0, dinv = dfwd;
+  if (dfwd && qf) return fail(DDA_EINVAL, "matvec: fused QMR step needs the register-resident y pass");
   if (dfwd) {
     // fused: xy forward -> z with product -> xy inverse
     {
@@ -1088,12 +1109,13 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
     FastLaunch<R>::template yfwd<N>(dim3(1, P, nrhs * 3), st, x, G1, occ_of(t), a0, a1, dS, active, va, \
-                                    b.tw[1].template as<cx<R>>());                                            \
+                                    b.tw[1].template as<cx<R>>(), qf);                                        \
     break;
         DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
       }
     } else {
+      if (qf) return fail(DDA_EINVAL, "matvec: fused QMR step needs the register-resident y pass");
       const size_t lds = 2 * (size_t)Jpp * va.TX * sizeof(cx<R>);
       dim3 grid((K + va.TX - 1) / va.TX, P, nrhs * 3);
       hipLaunchKernelGGL((k_vec_yfwd<R>), grid, dim3(kThreads), lds, st, x, G1, occ_of(t), a0, a1, dS,
@@ -1434,6 +1456,22 @@ static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
   return DDA_OK;
 }
 
+// QMR_sym runs its step fused into the y-forward pass when the product's
+// y pass is the register-resident one (schedules 0, 1 and 3); returns the
+// y-forward blocks per right-hand side, or 0 if the step stays separate.
+template <typename R>
+static int qmr_fused_blocks(dda_target* t, int nrhs) {
+  if (is_fused(schedule_of<R>(t, nrhs)) || !fast_size(t->Jpp)) return 0;
+  switch (t->Jpp) {
+#define DDA_CASE(N) \
+  case N:           \
+    return FastLaunch<R>::template yfwd_blocks<N>(t);
+    DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Host programs of the generic solvers (BiCG, QMR, BiCGSTAB(l), IDR(s) for
 // ML(n)BiCGSTAB): each iteration is a fixed sequence of k_gen_dot,
@@ -1685,13 +1723,18 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
   SolverDims dm;
   dm.n3 = n3;
   dm.nblk = nblocks_for(n3);
-  // four regions of partial sums (each nrhs x nblk x 2)
-  const size_t preg = (size_t)nrhs * dm.nblk * 2;
+  int* act = t->active.as<int>();
+  const double* dS = t->S.as<double>();
+  // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
+  CHK(autotune<R>(t, nrhs, dS, jacobi, slot(0), slot(4), st));
+  // QMR_sym: step fused into the y-forward pass where the schedule allows
+  const int nblk_f = (solver == DDA_QMR_SYM && t->fuse_qmr) ? qmr_fused_blocks<R>(t, nrhs) : 0;
+  const bool qfuse = nblk_f > 0;
+  // four regions of partial sums (each nrhs x nblk x 2, nblk_f when fused)
+  const size_t preg = (size_t)nrhs * std::max(dm.nblk, nblk_f) * 2;
   CHK(t->part.ensure(std::max(4 * preg, (size_t)nrhs * dm.nblk * kGenDots) * sizeof(c64)));
   c64* part = t->part.as<c64>();
   c64 *R0 = part, *R1 = part + preg, *R2 = part + 2 * preg, *R3 = part + 3 * preg;
-  int* act = t->active.as<int>();
-  const double* dS = t->S.as<double>();
   dim3 vg(dm.nblk, nrhs), fg(nrhs);
   int check = check_every > 0 ? check_every : 8;
   if (check % 2) ++check;  // vector rings and state buffers have period 2
@@ -1708,8 +1751,6 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
   GenRun<R> gr{t, nrhs, solver, param, mv_per_iter, jacobi, V, (long)vsz, dm, part, t->state.as<GenState>(), act,
                tolv, dS};
 
-  // ---- schedule: tune on scratch slots (4 -> 5, both rewritten below)
-  CHK(autotune<R>(t, nrhs, dS, jacobi, slot(0), slot(4), st));
   // ---- initialisation (eager); state buffer 0 receives the initial state
   const int nblk_mv = yinv_blocks<R>(t, nrhs);
   CHK(t->part_mv.ensure((size_t)2 * nrhs * nblk_mv * 2 * sizeof(c64)));
@@ -1752,10 +1793,21 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
     hipLaunchKernelGGL(k_cg_fin_init, fg, dim3(kRedThreads), 0, st, R3, dm.nblk, S0, act, tolv);
   } else {
     QmrState* S0 = t->state.as<QmrState>();
-    // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring, slot 7 = QMR residual
-    hipLaunchKernelGGL((k_qmr_init<R>), vg, dim3(kRedThreads), 0, st, b, u, slot(2), slot(3), slot(5), slot(6), slot(7),
-                       act, dm, R1);
-    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(kRedThreads), 0, st, R1, dm.nblk, S0, act, tolv);
+    // slot 2 = vt_1 = b, slot 3 = vt_0 = 0, slots 5, 6 = p ring, slot 7 = QMR residual;
+    // fused: the partials take the y-forward pass's block count, and the
+    // first product A vt_1 is formed here (each iteration then runs step n
+    // and the product of vt_{n+1})
+    SolverDims dmi = dm;
+    if (qfuse) dmi.nblk = nblk_f;
+    hipLaunchKernelGGL((k_qmr_init<R>), dim3(dmi.nblk, nrhs), dim3(kRedThreads), 0, st, b, u, slot(2), slot(3),
+                       slot(5), slot(6), slot(7), act, dmi, R1);
+    hipLaunchKernelGGL(k_qmr_fin_init, fg, dim3(kRedThreads), 0, st, R1, dmi.nblk, S0, act, tolv);
+    if (qfuse) {
+      DotArgs d0;
+      d0.mode = DOT_BIL;
+      d0.part = M0;
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, slot(2), slot(4), act, st, d0));
+    }
   }
   LAUNCHCHK();
 
@@ -1825,6 +1877,24 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
       d.part = M0;
       CHK(matvec_T<R>(t, nrhs, dS, jacobi, p, q, act, s, d));
       hipLaunchKernelGGL((k_cg_update<R>), vg, dim3(kRedThreads), 0, s, u, r, p, q, M0, nblk_mv, SB, SA, act, dm, R3);
+    } else if (qfuse) {
+      QmrState* SA = t->state.as<QmrState>() + (par ? nrhs : 0);
+      QmrState* SB = t->state.as<QmrState>() + (par ? 0 : nrhs);
+      cx<R>* w = slot(4);
+      cx<R>* vn = par ? slot(3) : slot(2);
+      cx<R>* vp = par ? slot(2) : slot(3);
+      cx<R>* p1 = par ? slot(6) : slot(5);
+      cx<R>* p2 = par ? slot(5) : slot(6);
+      c64* pn_in = par ? R3 : R1;
+      c64* pn_out = par ? R1 : R3;
+      QmrCoef* qc = t->qcoef.as<QmrCoef>();
+      hipLaunchKernelGGL((k_qmr_coef<R>), fg, dim3(kRedThreads), 0, s, pn_in, nblk_f, M0, nblk_mv, SA, SB, act, qc);
+      QmrFuse<R> f{w, vn, vp, p1, p2, u, slot(7), qc, pn_out, nblk_f};
+      DotArgs d;
+      d.mode = DOT_BIL;
+      d.part = M0;
+      // vt_{n+1} lands in vp's slot and is the product's input
+      CHK(matvec_T<R>(t, nrhs, dS, jacobi, vp, w, act, s, d, &f));
     } else {
       QmrState* SA = t->state.as<QmrState>() + (par ? nrhs : 0);
       QmrState* SB = t->state.as<QmrState>() + (par ? 0 : nrhs);
@@ -1853,6 +1923,8 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
     std::vector<uintptr_t> key = {sizeof(R),
                                   (uintptr_t)solver,
                                   (uintptr_t)param,
+                                  (uintptr_t)nblk_f,
+                                  (uintptr_t)t->qcoef.p,
                                   (uintptr_t)nrhs,
                                   (uintptr_t)jacobi,
                                   (uintptr_t)check,

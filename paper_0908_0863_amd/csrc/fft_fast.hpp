@@ -17,6 +17,7 @@
 #pragma once
 #include "fft_core.hpp"
 #include "kernels_fft.hpp"
+#include "kernels_solver.hpp"
 
 namespace dda {
 
@@ -206,11 +207,13 @@ struct FastStages3 {
 // y forward with expansion (Sec. 3 and 4): grid (ceil(K/TX), P, nrhs*3),
 // block T*TX threads; lane = t*TX + l (l fastest: coalesced rows).
 // ---------------------------------------------------------------------------
-template <typename R, int N, int TX>
+// QF: the vector part of a QMR_sym step runs here (QmrFuse), the input
+// values being the vt_{n+1} it forms instead of loads of x.
+template <typename R, int N, int TX, bool QF>
 __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
     const cx<R>* __restrict__ x, cx<R>* __restrict__ G1, OccBits map, const cx<R>* __restrict__ a0,
     const cx<R>* __restrict__ a1, const double* __restrict__ S, const int* __restrict__ active, VecArgs a,
-    const cx<R>* __restrict__ tw) {
+    const cx<R>* __restrict__ tw, QmrFuse<R> qf) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
   __shared__ cx<R> lds[N * TX];
   const int rc = blockIdx.z, rhs = rc / 3;
@@ -220,25 +223,39 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
   const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   cx<R> v[E];
+  {
+    const QmrCoefR<R> q(QF ? qf.coef[rhs] : QmrCoef{});
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int e = t + T * m;
-    cx<R> val = mk((R)0, (R)0);
-    if (e < a.J && i < a.K) {
-      const int n = site_index(map, (long)k * a.J + e, i);
-      if (n >= 0) {
-        val = xv[n];
-        if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, cd + n)) * val;
+    for (int m = 0; m < E; ++m) {
+      const int e = t + T * m;
+      cx<R> val = mk((R)0, (R)0);
+      if (e < a.J && i < a.K) {
+        const int n = site_index(map, (long)k * a.J + e, i);
+        if (n >= 0) {
+          if constexpr (QF) val = qmr_elem<R>(q, qf, (long)rc * a.nd + n, acc);
+          else val = xv[n];
+          if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, cd + n)) * val;
+        }
       }
+      v[m] = val;
     }
-    v[m] = val;
   }
   fast_fft<R, false, N>(v, t, lds, TX, l, tw);
   if (i < a.K) {
     cx<R>* dst = G1 + ((long)rc * a.P + k) * N * a.K + i;
 #pragma unroll
     for (int m = 0; m < E; ++m) dst[(long)(t + T * m) * a.K] = v[m];
+  }
+  if constexpr (QF) {
+    block_sum2_any(acc[0], acc[1]);
+    if (threadIdx.x == 0) {
+      const long bid = ((long)(rc % 3) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      c64* po = qf.pnorm_out + ((long)rhs * qf.nblk_out + bid) * 2;
+      po[0] = acc[0];
+      po[1] = acc[1];
+    }
   }
 }
 

@@ -1203,6 +1203,85 @@ __global__ void __launch_bounds__(kRedThreads) k_qmr_step(const cx<R>* __restric
   }
 }
 
+// Fused form of the same step: the scalar part runs once per right-hand side
+// (k_qmr_coef) and the vector part inside the y-forward pass of the next
+// product, which consumes vt_{n+1} as it is formed, so the iteration has no
+// separate streaming kernel and vt_{n+1} is not read back.  Same recurrences
+// and stopping as k_qmr_step; the partials of |vt_{n+1}|^2, |r|^2 and
+// vt_{n+1}^T vt_{n+1} come from the y-forward blocks (nblk_out per RHS).
+template <typename R>
+struct QmrFuse {
+  const cx<R>* w;
+  const cx<R>* vn;
+  cx<R>* vp;
+  const cx<R>* p1;
+  cx<R>* p2;
+  cx<R>* u;
+  cx<R>* r;
+  const QmrCoef* coef;  // [nrhs], written by k_qmr_coef
+  c64* pnorm_out;       // [nrhs][nblk_out][2]
+  int nblk_out;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads) k_qmr_coef(const c64* __restrict__ pnorm_in, int nblk_in,
+                                                      const c64* __restrict__ pdot, int nblk_mv,
+                                                      const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
+                                                      int* __restrict__ active, QmrCoef* __restrict__ coef) {
+  const int rhs = blockIdx.x;
+  if (!active[rhs]) return;
+  c64 rn[2], rd[2];
+  reduce_partials<2>(pnorm_in, nblk_in, rhs, rn);
+  reduce_partials<2>(pdot, nblk_mv, rhs, rd);
+  if (threadIdx.x == 0) {
+    QmrState s = sin[rhs];
+    QmrCoef q;
+    qmr_scalars(rn, rd, s, q);
+    if (s.breakdown == 2 && !(s.rnorm2 < stall_level2<R>() * s.bnorm2)) {
+      s.breakdown = 0;
+      q.stop = s.converged;
+    }
+    s.ver += 1;
+    sout[rhs] = s;
+    coef[rhs] = q;
+    if (q.stop) active[rhs] = 0;
+  }
+}
+
+// The step's coefficients in the vector precision.
+template <typename R>
+struct QmrCoefR {
+  bool upd;
+  R sgp, sg, rs;
+  cx<R> fpp, ep, rinv, coef, rc, alpha, bs;
+  __device__ explicit QmrCoefR(const QmrCoef& q)
+      : upd(q.upd != 0), sgp((R)q.sgp), sg((R)q.sg), rs((R)q.rs), fpp(cvt<R>(q.fpp)), ep(cvt<R>(q.ep)),
+        rinv(cvt<R>(q.rinv)), coef(cvt<R>(q.coef)), rc(cvt<R>(q.rc)), alpha(cvt<R>(q.alpha)), bs(cvt<R>(q.bs)) {}
+};
+
+// Vector part of the step for element i of one right-hand side (the body of
+// k_qmr_step's loop); returns vt_{n+1}[i].
+template <typename R>
+__device__ __forceinline__ cx<R> qmr_elem(const QmrCoefR<R>& q, const QmrFuse<R>& f, long i, c64 (&acc)[2]) {
+  const cx<R> vpi = f.vp[i];
+  const cx<R> vni = f.vn[i];
+  cx<R> ri = f.r[i];
+  if (q.upd) {
+    const cx<R> pn = q.rinv * (q.sgp * vpi - q.fpp * f.p1[i] - q.ep * f.p2[i]);
+    f.p2[i] = pn;
+    f.u[i] = f.u[i] + q.coef * pn;
+    ri = q.rs * ri + q.rc * vni;
+    f.r[i] = ri;
+  }
+  const cx<R> t = q.sg * (f.w[i] - q.alpha * vni) - q.bs * vpi;
+  f.vp[i] = t;
+  const c64 td = up(t);
+  acc[0].x += abs2(td);
+  acc[0].y += abs2(up(ri));
+  acc[1] = acc[1] + td * td;
+  return t;
+}
+
 // ============================================================================
 // Outer (FP64) refinement, incident field, cross sections, gradient
 // ============================================================================

@@ -74,7 +74,7 @@ EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "
            "dda_last_error"]
 
 PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse", "xy_forward", "xy_inverse"]
-DDA_OPT_SCHEDULE, DDA_OPT_INJECT_BREAKDOWN, DDA_OPT_CANARY = 1, 2, 3
+DDA_OPT_SCHEDULE, DDA_OPT_INJECT_BREAKDOWN, DDA_OPT_CANARY, DDA_OPT_FUSE_QMR_STEP = 1, 2, 3, 4
 
 _lib = None
 
