@@ -1230,11 +1230,24 @@ __global__ void __launch_bounds__(kRedThreads) k_qmr_coef(const c64* __restrict_
                                                       int* __restrict__ active, QmrCoef* __restrict__ coef) {
   const int rhs = blockIdx.x;
   if (!active[rhs]) return;
-  c64 rn[2], rd[2];
-  reduce_partials<2>(pnorm_in, nblk_in, rhs, rn);
-  reduce_partials<2>(pdot, nblk_mv, rhs, rd);
+  QmrState s;
+  if (threadIdx.x == 0) s = sin[rhs];  // issued before the reductions
+  // both partial sets in one block reduction (each sum in the fixed order of
+  // reduce_partials)
+  c64 v[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+  for (int b = threadIdx.x; b < nblk_in; b += blockDim.x) {
+    const c64* p = pnorm_in + ((long)rhs * nblk_in + b) * 2;
+    v[0] = v[0] + p[0];
+    v[1] = v[1] + p[1];
+  }
+  for (int b = threadIdx.x; b < nblk_mv; b += blockDim.x) {
+    const c64* p = pdot + ((long)rhs * nblk_mv + b) * 2;
+    v[2] = v[2] + p[0];
+    v[3] = v[3] + p[1];
+  }
+  block_sum<4>(v);
   if (threadIdx.x == 0) {
-    QmrState s = sin[rhs];
+    const c64 rn[2] = {v[0], v[1]}, rd[2] = {v[2], v[3]};
     QmrCoef q;
     qmr_scalars(rn, rd, s, q);
     if (s.breakdown == 2 && !(s.rnorm2 < stall_level2<R>() * s.bnorm2)) {
