@@ -1340,9 +1340,13 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
         (void)hipEventElapsedTime(&ms, e0, e1);
         best_c[ci] = std::min(best_c[ci], ms);
       }
-    float best_ms = 1e30f;
-    for (size_t ci = 0; ci < cand.size(); ++ci)
-      if (best_c[ci] < best_ms) {
+    // a later candidate must win by more than 3% (near-ties keep the earlier,
+    // simpler schedule, so that repeated tunings agree; the five-pass
+    // schedules also let QMR_sym fuse its step into the y pass)
+    float best_ms = best_c[0];
+    best = cand[0];
+    for (size_t ci = 1; ci < cand.size(); ++ci)
+      if (best_c[ci] < 0.97f * best_ms) {
         best_ms = best_c[ci];
         best = cand[ci];
       }
