@@ -239,7 +239,6 @@ struct dda_target {
   DevBuf part_mv; // partials of the inner products fused into the matvec
   DevBuf scal;    // double [cap] scale factors
   DevBuf tolv;    // double [cap] inner tolerances
-  DevBuf qcoef;   // QmrCoef [cap]: fused QMR_sym step coefficients
   DevBuf outer;   // FP64 outer vectors: E, r, y  (3 x [cap][3][nd])
   DevBuf khat, ehat;
   DevBuf far_dirs, far_part, far_F, far_w, far_tp;  // far-field scratch
@@ -795,7 +794,6 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   CHK(t->active_outer.ensure(cap * sizeof(int)));
   CHK(t->scal.ensure(cap * sizeof(double)));
   CHK(t->tolv.ensure(cap * sizeof(double)));
-  CHK(t->qcoef.ensure(cap * sizeof(QmrCoef)));
   CHK(t->state.ensure(2 * cap * std::max({sizeof(BcgState), sizeof(QmrState), sizeof(CgState), sizeof(CgsState),
                                              sizeof(TfqState), sizeof(GenState)})));
   CHK(t->khat.ensure(cap * 3 * sizeof(double)));
@@ -1891,9 +1889,7 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
       cx<R>* p2 = par ? slot(5) : slot(6);
       c64* pn_in = par ? R3 : R1;
       c64* pn_out = par ? R1 : R3;
-      QmrCoef* qc = t->qcoef.as<QmrCoef>();
-      hipLaunchKernelGGL((k_qmr_coef<R>), fg, dim3(kRedThreads), 0, s, pn_in, nblk_f, M0, nblk_mv, SA, SB, act, qc);
-      QmrFuse<R> f{w, vn, vp, p1, p2, u, slot(7), qc, pn_out, nblk_f};
+      QmrFuse<R> f{w, vn, vp, p1, p2, u, slot(7), pn_out, nblk_f, pn_in, nblk_f, M0, nblk_mv, SA, SB, act};
       DotArgs d;
       d.mode = DOT_BIL;
       d.part = M0;
@@ -1928,7 +1924,6 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
                                   (uintptr_t)solver,
                                   (uintptr_t)param,
                                   (uintptr_t)nblk_f,
-                                  (uintptr_t)t->qcoef.p,
                                   (uintptr_t)nrhs,
                                   (uintptr_t)jacobi,
                                   (uintptr_t)check,

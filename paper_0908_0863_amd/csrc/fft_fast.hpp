@@ -207,8 +207,10 @@ struct FastStages3 {
 // y forward with expansion (Sec. 3 and 4): grid (ceil(K/TX), P, nrhs*3),
 // block T*TX threads; lane = t*TX + l (l fastest: coalesced rows).
 // ---------------------------------------------------------------------------
-// QF: the vector part of a QMR_sym step runs here (QmrFuse), the input
-// values being the vt_{n+1} it forms instead of loads of x.
+// QF: a whole QMR_sym step runs here (QmrFuse): the block reduces the
+// previous partials and runs the scalar recurrence (as every block of
+// k_qmr_step does), then forms vt_{n+1} for the dipoles it expands, which
+// are its input values instead of loads of x.
 template <typename R, int N, int TX, bool QF>
 __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
     const cx<R>* __restrict__ x, cx<R>* __restrict__ G1, OccBits map, const cx<R>* __restrict__ a0,
@@ -225,8 +227,44 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
   const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   cx<R> v[E];
+  QmrCoef qd{};
+  if constexpr (QF) {
+    __shared__ QmrCoef cq;
+    QmrState s0;
+    if (threadIdx.x == 0) s0 = qf.sin[rhs];
+    c64 r4[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    for (int b = threadIdx.x; b < qf.nblk_in; b += blockDim.x) {
+      const c64* p = qf.pnorm_in + ((long)rhs * qf.nblk_in + b) * 2;
+      r4[0] = r4[0] + p[0];
+      r4[1] = r4[1] + p[1];
+    }
+    for (int b = threadIdx.x; b < qf.nblk_mv; b += blockDim.x) {
+      const c64* p = qf.pdot + ((long)rhs * qf.nblk_mv + b) * 2;
+      r4[2] = r4[2] + p[0];
+      r4[3] = r4[3] + p[1];
+    }
+    block_sum_n<4>(r4);
+    if (threadIdx.x == 0) {
+      const c64 rn[2] = {r4[0], r4[1]}, rd[2] = {r4[2], r4[3]};
+      QmrCoef q;
+      qmr_scalars(rn, rd, s0, q);
+      if (s0.breakdown == 2 && !(s0.rnorm2 < stall_level2<R>() * s0.bnorm2)) {
+        s0.breakdown = 0;
+        q.stop = s0.converged;
+      }
+      cq = q;
+      if (blockIdx.x == 0 && blockIdx.y == 0 && rc % 3 == 0) {
+        s0.ver += 1;
+        qf.sout[rhs] = s0;
+        if (q.stop) qf.active[rhs] = 0;
+      }
+    }
+    __syncthreads();
+    qd = cq;
+    if (qd.stop) return;
+  }
   {
-    const QmrCoefR<R> q(QF ? qf.coef[rhs] : QmrCoef{});
+    const QmrCoefR<R> q(qd);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int e = t + T * m;

@@ -1203,12 +1203,14 @@ __global__ void __launch_bounds__(kRedThreads) k_qmr_step(const cx<R>* __restric
   }
 }
 
-// Fused form of the same step: the scalar part runs once per right-hand side
-// (k_qmr_coef) and the vector part inside the y-forward pass of the next
-// product, which consumes vt_{n+1} as it is formed, so the iteration has no
-// separate streaming kernel and vt_{n+1} is not read back.  Same recurrences
-// and stopping as k_qmr_step; the partials of |vt_{n+1}|^2, |r|^2 and
-// vt_{n+1}^T vt_{n+1} come from the y-forward blocks (nblk_out per RHS).
+// Fused form of the same step: the whole step runs inside the y-forward pass
+// of the next product, which consumes vt_{n+1} as it is formed, so the
+// iteration has no separate step kernel and vt_{n+1} is not read back.  As in
+// k_qmr_step, every block reduces the partials in the same fixed order and
+// runs the scalar recurrence redundantly (block 0 of each right-hand side
+// writes the state); same recurrences and stopping.  The partials of
+// |vt_{n+1}|^2, |r|^2 and vt_{n+1}^T vt_{n+1} come from the y-forward blocks
+// (nblk_out per RHS).
 template <typename R>
 struct QmrFuse {
   const cx<R>* w;
@@ -1218,47 +1220,43 @@ struct QmrFuse {
   cx<R>* p2;
   cx<R>* u;
   cx<R>* r;
-  const QmrCoef* coef;  // [nrhs], written by k_qmr_coef
-  c64* pnorm_out;       // [nrhs][nblk_out][2]
+  c64* pnorm_out;  // [nrhs][nblk_out][2]
   int nblk_out;
+  const c64* pnorm_in;  // the previous step's partials [nrhs][nblk_in][2]
+  int nblk_in;
+  const c64* pdot;
+  int nblk_mv;
+  const QmrState* sin;
+  QmrState* sout;
+  int* active;
 };
 
-template <typename R>
-__global__ void __launch_bounds__(kRedThreads) k_qmr_coef(const c64* __restrict__ pnorm_in, int nblk_in,
-                                                      const c64* __restrict__ pdot, int nblk_mv,
-                                                      const QmrState* __restrict__ sin, QmrState* __restrict__ sout,
-                                                      int* __restrict__ active, QmrCoef* __restrict__ coef) {
-  const int rhs = blockIdx.x;
-  if (!active[rhs]) return;
-  QmrState s;
-  if (threadIdx.x == 0) s = sin[rhs];  // issued before the reductions
-  // both partial sets in one block reduction (each sum in the fixed order of
-  // reduce_partials)
-  c64 v[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
-  for (int b = threadIdx.x; b < nblk_in; b += blockDim.x) {
-    const c64* p = pnorm_in + ((long)rhs * nblk_in + b) * 2;
-    v[0] = v[0] + p[0];
-    v[1] = v[1] + p[1];
-  }
-  for (int b = threadIdx.x; b < nblk_mv; b += blockDim.x) {
-    const c64* p = pdot + ((long)rhs * nblk_mv + b) * 2;
-    v[2] = v[2] + p[0];
-    v[3] = v[3] + p[1];
-  }
-  block_sum<4>(v);
-  if (threadIdx.x == 0) {
-    const c64 rn[2] = {v[0], v[1]}, rd[2] = {v[2], v[3]};
-    QmrCoef q;
-    qmr_scalars(rn, rd, s, q);
-    if (s.breakdown == 2 && !(s.rnorm2 < stall_level2<R>() * s.bnorm2)) {
-      s.breakdown = 0;
-      q.stop = s.converged;
+// Sum of ND complex values over a block of any multiple-of-64 size; fixed
+// order, result valid in thread 0.
+template <int ND>
+__device__ __forceinline__ void block_sum_n(c64 (&v)[ND]) {
+  __shared__ c64 shn[ND][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < ND; ++q) {
+    double a = v[q].x, b = v[q].y;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
     }
-    s.ver += 1;
-    sout[rhs] = s;
-    coef[rhs] = q;
-    if (q.stop) active[rhs] = 0;
+    if (lane == 0) shn[q][wv] = mk(a, b);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+      c64 s = shn[q][0];
+      for (int w = 1; w < nw; ++w) s = s + shn[q][w];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
 }
 
 // The step's coefficients in the vector precision.
