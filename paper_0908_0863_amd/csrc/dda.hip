@@ -1459,11 +1459,17 @@ static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
 }
 
 // QMR_sym runs its step fused into the y-forward pass when the product's
-// y pass is the register-resident one (schedules 0, 1 and 3); returns the
-// y-forward blocks per right-hand side, or 0 if the step stays separate.
+// y pass is the register-resident one (schedules 0, 1 and 3) and the target
+// fills its lattice (>= 90% of the sites occupied): the fused pass reaches
+// the step's seven vectors through the occupancy, which is a coalesced
+// stream only where consecutive sites hold consecutive dipoles (measured:
+// faster at the filled 64^3 cube, slower at the 200^3 sphere, the 96^3
+// ellipsoid and the aggregates).  Returns the y-forward blocks per
+// right-hand side, or 0 if the step stays separate.
 template <typename R>
 static int qmr_fused_blocks(dda_target* t, int nrhs) {
   if (is_fused(schedule_of<R>(t, nrhs)) || !fast_size(t->Jpp)) return 0;
+  if ((double)t->nd < 0.9 * (double)t->K * t->J * t->P) return 0;
   switch (t->Jpp) {
 #define DDA_CASE(N) \
   case N:           \

@@ -174,29 +174,37 @@ def test_solve_mixed_sphere16(lib, solver, param):
     assert _rel(P[0].cpu().numpy(), Po) < 1e-8
 
 
+_BOX_LU = {}
+
+
 @pytest.mark.parametrize("fuse", [0, 1])
 @pytest.mark.parametrize("sched", [0, 1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_qmr_sym_fused_and_separate_step(lib, fuse, sched, precision):
-    """QMR_sym with its step fused into the y-forward pass (schedules whose y
-    pass is register-resident) and as a separate kernel (option off, or a
-    fused-xy schedule) reaches the dense LU solution, with graph replay."""
+    """QMR_sym with its step fused into the y-forward pass (a target that
+    fills its lattice, schedules whose y pass is register-resident) and as a
+    separate kernel (option off, or a fused-xy schedule) reaches the dense LU
+    solution, with graph replay."""
     from paper_0908_0863_amd import dda
-    w = inputs.workload("sphere16")
-    eps = w["m"] ** 2
-    t, nd = _target(lib, w["occ"], w["kd"], eps)
+    occ = np.ones((8, 10, 12), np.uint8)  # filled 12 x 10 x 8 box: the fused step applies
+    kd, eps = 0.35, (1.5 + 0.05j) ** 2
+    t, nd = _target(lib, occ, kd, eps)
     try:
         t.set_option(dda.DDA_OPT_SCHEDULE, sched)
     except dda.DDAError:
         pytest.skip(f"no schedule {sched}")
     t.set_option(dda.DDA_OPT_FUSE_QMR_STEP, fuse)
     tol = 1e-12 if precision == "fp64" else 1e-10
-    P, info = t.solve(khat=[[0, 0, 1], [0, 0, 1]], ehat=[[1, 0, 0], [0, 1, 0]], solver="qmr_sym", precision=precision,
-                      tol=tol, inner_tol=1e-4, use_graph=True, check_every=4)
-    for r, eh in enumerate([[1, 0, 0], [0, 1, 0]]):
+    ehs = [[1, 0, 0], [0, 1, 0]]
+    P, info = t.solve(khat=[[0, 0, 1], [0, 0, 1]], ehat=ehs, solver="qmr_sym", precision=precision, tol=tol,
+                      inner_tol=1e-4, use_graph=True, check_every=4)
+    sites = ora.sites_of(occ)
+    for r, eh in enumerate(ehs):
         assert info[r]["converged"] and info[r]["rel_residual"] <= tol
-        Po = _sphere16_lu(w["kd"], eps, [0, 0, 1], eh, 0.0)
-        assert _rel(P[r].cpu().numpy(), Po) < (1e-10 if precision == "fp64" else 1e-8)
+        if r not in _BOX_LU:
+            ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0)
+            _BOX_LU[r] = ora.solve_dense(sites, kd, ainv, ora.einc(sites, kd, [0, 0, 1], eh))
+        assert _rel(P[r].cpu().numpy(), _BOX_LU[r]) < (1e-10 if precision == "fp64" else 1e-8)
 
 
 def test_cross_sections_sphere16(lib):
