@@ -376,3 +376,38 @@ def test_solve_composition_matches_lu(lib, solver):
     with pytest.raises(dda.DDAError) as e:
         t.grad_cabs_eps(P, S=[S])
     assert e.value.code == dda.DDA_ESTATE
+
+
+def test_direct_polarizability_matvec_and_solve(lib):
+    """dda_set_polarizability: per-dipole alpha used as given (alpha^{-1} =
+    1/alpha on the diagonal, no S dependence) — product against the dense
+    oracle, solve against dense LU; alpha = 0 and the gradient (which needs a
+    permittivity) are rejected."""
+    from paper_0908_0863_amd import dda
+    occ = _rand_occ((6, 7, 9), 17)
+    kd = 0.4
+    t = dda.Target(lib, 9, 7, 6, kd)
+    nd = t.set_occupancy(occ)
+    rng = np.random.default_rng(23)
+    eps = 2.0 + rng.random(nd) + 1j * (0.05 + 0.3 * rng.random(nd))
+    alpha = 1.0 / ora.alpha_inv(eps, kd, "rr")
+    t.set_polarizability(alpha)
+    t.build_spectrum()
+    sites = ora.sites_of(occ)
+    ainv = 1.0 / alpha
+    x = inputs.complex_gaussian(29, (2, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=[0.0, 0.7]).cpu().numpy()
+    for r in range(2):
+        assert _rel(y[r], ora.dense_matvec(sites, kd, ainv, x[r])) < 1e-12
+    E = ora.einc(sites, kd, [0, 0, 1], [1, 0, 0])
+    P, info = t.solve(einc=torch.from_numpy(E[None]).cuda(), S=[0.0], solver="qmr_sym", precision="fp64", tol=1e-12)
+    assert info[0]["converged"]
+    assert _rel(P[0].cpu().numpy(), ora.solve_dense(sites, kd, ainv, E)) < 1e-10
+    with pytest.raises(dda.DDAError) as e:
+        t.grad_cabs_eps(P, S=[0.0])
+    assert e.value.code == dda.DDA_ESTATE
+    bad = alpha.copy()
+    bad[3] = 0.0
+    with pytest.raises(dda.DDAError) as e:
+        t.set_polarizability(bad)
+    assert e.value.code == dda.DDA_EINVAL
