@@ -411,3 +411,45 @@ def test_direct_polarizability_matvec_and_solve(lib):
     with pytest.raises(dda.DDAError) as e:
         t.set_polarizability(bad)
     assert e.value.code == dda.DDA_EINVAL
+
+
+def test_profiling_counts_and_tune_file(tmp_path):
+    """dda_profile_*: every pass of a product is timed once per launch in its
+    precision's slot, reset clears the record; dda_open's tune file records
+    the autotuner's choice and a second library reads it back."""
+    from paper_0908_0863_amd import dda
+    path = str(tmp_path / "tune.txt")
+    lib1 = dda.Library(0, tune_cache=path)
+    w = inputs.workload("sphere16")
+    t = dda.Target(lib1, 16, 16, 16, w["kd"])
+    nd = t.set_occupancy(w["occ"])
+    t.set_permittivity(w["m"] ** 2, "ldr")
+    t.build_spectrum()
+    x = torch.from_numpy(inputs.complex_gaussian(3, (1, 3, nd))).cuda()
+    y0 = t.matvec(x)  # tunes and records the choice
+    torch.cuda.synchronize()
+    lines = [l for l in open(path).read().splitlines() if l.strip()]
+    assert lines and all(" = " in l for l in lines)
+    t.set_option(dda.DDA_OPT_SCHEDULE, 0)  # the five separate passes
+    lib1.profile(True)
+    lib1.profile_reset()
+    for _ in range(3):
+        t.matvec(x)
+    rec = lib1.profile_read()
+    lib1.profile(False)
+    for p in ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse"]:
+        ms, n = rec[(p, "fp64")]
+        assert n == 3 and ms > 0.0, (p, ms, n)
+        assert rec[(p, "fp32")][1] == 0
+    assert rec[("xy_forward", "fp64")][1] == 0
+    lib1.profile_reset()
+    assert all(n == 0 for _, n in lib1.profile_read().values())
+    # a second library opened on the same file uses the recorded choice
+    lib2 = dda.Library(0, tune_cache=path)
+    t2 = dda.Target(lib2, 16, 16, 16, w["kd"])
+    t2.set_occupancy(w["occ"])
+    t2.set_permittivity(w["m"] ** 2, "ldr")
+    t2.build_spectrum()
+    y2 = t2.matvec(x)
+    assert _rel(y2.cpu().numpy(), y0.cpu().numpy()) < 1e-13
+    assert [l for l in open(path).read().splitlines() if l.strip()] == lines  # nothing re-tuned
