@@ -65,6 +65,17 @@ def test_spectrum_matches_circulant_dft(lib, shape):
     assert np.abs(Yg - Yo).max() <= 1e-13 * np.abs(Yo).max() + 1e-15
 
 
+@pytest.mark.parametrize("shape", [(7, 5, 9), (16, 5, 12), (40, 3, 20)])
+def test_fp32_spectrum_is_the_rounded_fp64_spectrum(lib, shape):
+    """The FP32 spectrum is the FP64 one rounded to nearest (bit for bit)."""
+    from paper_0908_0863_amd import dda
+    K, J, P = shape
+    t, nd = _target(lib, _rand_occ((P, J, K), 2), 0.37, 2.1 + 0.2j)
+    Y64 = t.spectrum(dda.DDA_FP64).cpu().numpy()
+    Y32 = t.spectrum(dda.DDA_FP32).cpu().numpy()
+    assert np.array_equal(Y32.view(np.float32), Y64.astype(np.complex64).view(np.float32))
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("jacobi", [False, True])
 def test_matvec_fp64_matches_dense(lib, shape, jacobi):
