@@ -407,6 +407,11 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __rest
   const int jj = mym ? a.Jpp - gy : gy;
   if (mym && (gy == 0 || jj == gy)) return;
   if (active && !active[rhs]) return;
+  // the twiddle table in LDS: the stages read it right after their barriers,
+  // where a global-memory round trip would sit on the dependent chain (the
+  // first stage has no twiddles, and its barrier publishes the copy)
+  __shared__ cx<R> twl[N];
+  for (int e = threadIdx.x; e < N; e += blockDim.x) twl[e] = tw[e];
   const int l = threadIdx.x % TX, t = threadIdx.x / TX;
   const int i = xt * TX + l;
   const long plane = (long)a.Jpp * a.Kpp;
@@ -421,7 +426,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __rest
       v[c][m] = (ok && e < a.P) ? src[e * plane] : mk((R)0, (R)0);
     }
   }
-  FastStages3<R, false, N, FastPlan<N>::S>::template run<0>(v, t, lds, TX, l, N * TX, tw);
+  FastStages3<R, false, N, FastPlan<N>::S>::template run<0>(v, t, lds, TX, l, N * TX, twl);
   if (ok) {
     const int jm = min(jj, a.Jpp - jj);
     const bool my = jj > a.Jpp - jj;
@@ -450,7 +455,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_zmul(cx<R>* __rest
       v[2][m] = yv[2] * x0 + yv[4] * x1 + yv[5] * x2;
     }
   }
-  FastStages3<R, true, N, FastPlan<N>::S>::template run<0>(v, t, lds, TX, l, N * TX, tw);
+  FastStages3<R, true, N, FastPlan<N>::S>::template run<0>(v, t, lds, TX, l, N * TX, twl);
   if (!ok) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
