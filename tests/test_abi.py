@@ -66,3 +66,20 @@ def test_binding_struct_fields_follow_header(struct):
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"(\w+)\s*;", body)
     assert [f for f, _ in getattr(dda, struct)._fields_] == fields
+
+
+def test_solve_options_marshalling():
+    """Solver names of the paper's Table 3 map to the header's values and the
+    options structure carries every field in order (no GPU needed)."""
+    from paper_0908_0863_amd import dda
+    o = dda.Target.make_opts(solver="rbicgstab", precision="mixed", tol=1e-7, inner_tol=2e-4, max_iter=50,
+                             max_outer=3, jacobi=False, check_every=6, use_graph=True, solver_param=3)
+    assert (o.solver, o.precision, o.max_iter, o.max_outer) == (dda.DDA_RBICGSTAB, dda.DDA_SOLVE_MIXED, 50, 3)
+    assert (o.tol, o.inner_tol, o.jacobi, o.check_every, o.use_graph, o.solver_param) == (1e-7, 2e-4, 0, 6, 1, 3)
+    names = {"bicg": dda.DDA_BICG, "bicg_sym": dda.DDA_BICG_SYM, "cocg": dda.DDA_BICG_SYM,
+             "bicgstab": dda.DDA_BICGSTAB, "cgs": dda.DDA_CGS, "mlbicgstab": dda.DDA_MLBICGSTAB,
+             "qmr": dda.DDA_QMR, "qmr_sym": dda.DDA_QMR_SYM, "rbicgstab": dda.DDA_RBICGSTAB, "tfqmr": dda.DDA_TFQMR}
+    for n, v in names.items():
+        assert dda.Target.make_opts(solver=n).solver == v
+    with pytest.raises(KeyError):
+        dda.Target.make_opts(solver="gmres")
