@@ -160,12 +160,21 @@ typedef struct {
  * E_inc is einc_dev ([nrhs][3][N_d] complex128) or, if NULL, plane waves
  * ehat exp(i kd khat . r) built from khat[3*nrhs] and ehat[6*nrhs] (re, im).
  * S (nullable) as for dda_matvec; when NULL and the prescription is LDR, S is
- * computed from khat/ehat.  p_dev: out [nrhs][3][N_d] complex128.
+ * computed from khat/ehat (S = sum_a Re[(khat_a ehat_a)^2]), and an LDR
+ * target given neither S nor khat/ehat is DDA_EINVAL.  The S values used are
+ * kept with the target (dda_solve_orientation_factors) for the calls that
+ * follow the solve.  p_dev: out [nrhs][3][N_d] complex128.
  * info: host [nrhs].  DDA_ENOTCONV if a right-hand side missed tol;
  * DDA_EINVAL for an unknown solver, a solver_param above 4, tol outside
  * (0, 1) or an unknown precision. */
 int dda_solve(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *khat, const double *ehat,
               const double *S, const void *einc_dev, void *p_dev, dda_solve_info *info, void *hip_stream);
+
+/* The LDR orientation factors S[nrhs] (host out) that the last dda_solve on
+ * the target used: the S it was given, or those it derived from khat/ehat (0
+ * for CM/RR targets).  DDA_ESTATE if no solve ran since the occupancy was set
+ * or it had another right-hand-side count. */
+int dda_solve_orientation_factors(const dda_target *t, int nrhs, double *S);
 
 /* One target's share of a batch: the arguments dda_solve takes for it. */
 typedef struct {
@@ -201,12 +210,15 @@ int dda_incident_field(dda_target *t, int nrhs, const double *khat, const double
 
 /* C_ext = 4 pi k sum Im(E^* . P), C_abs = 4 pi k sum |P|^2 (-Im alpha^{-1} - 2k^3/3)
  * (Draine 1988, |E0| = 1) and C_sca = C_ext - C_abs, per right-hand side
- * (host outputs, nrhs each; any may be NULL). */
+ * (host outputs, nrhs each; any may be NULL).  S (host [nrhs], nullable):
+ * the LDR orientation factors of alpha^{-1}; when NULL, an LDR target takes
+ * those of the last dda_solve if it had nrhs right-hand sides and is
+ * DDA_EINVAL otherwise (CM/RR targets have no S term). */
 int dda_cross_sections(dda_target *t, int nrhs, const double *S, const void *einc_dev, const void *p_dev,
                        double *cext, double *cabs, double *csca, void *hip_stream);
 
 /* Far-field amplitude of the solved dipoles (the step after the solve; the
- * paper reports Q_sca from it, Sec. 5): F(n) = kd^2 (I - n n) sum_m
+ * paper reports Q_sca from it, Sec. 6): F(n) = kd^2 (I - n n) sum_m
  * exp(-i kd n . r_m) P_m, so that the scattered field is exp(i kd r)/r F(n) as
  * r -> infinity (Gaussian units, |E0| = 1; Draine 1988).  dirs: host
  * [ndir][3] unit vectors (DDA_EINVAL otherwise).  p_dev [nrhs][3][N_d]
@@ -238,7 +250,7 @@ int dda_mueller(dda_target *t, const void *p_dev, int ndir, const double *theta_
 /* dC_abs/d eps_n for every dipole and right-hand side by one adjoint solve
  * with the same matrix (A is complex symmetric: A mu = W conj(P)).
  * grad_dev: out [nrhs][N_d] complex128 = dC/dRe eps + i dC/dIm eps.
- * Requires dda_set_permittivity. */
+ * S as for dda_cross_sections.  Requires dda_set_permittivity. */
 int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const double *S, const void *p_dev,
                       void *grad_dev, void *hip_stream);
 
@@ -248,6 +260,12 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * 1 five passes with the x passes transposing so that z lines are contiguous;
  * 3 five passes with the z pass spread over three thread groups, one per
  * vector component (fewer registers per thread, spectra exchanged in LDS);
+ * 5 five passes with a two-level z pass (each z line as an E-point DFT per
+ * thread and T-point DFTs after one LDS exchange, the product taken in that
+ * scrambled frequency order, several right-hand sides per block);
+ * 6 as 5 with the x-transformed array stored in z-column tiles (each tile's
+ * rows contiguous), written and read by x passes that take several z rows
+ * of one y row at a time;
  * D in {2, 4, 8} the fused xy-plane passes with the frequency range split
  * into D residue classes.  DDA_EINVAL if that schedule does not exist for the
  * lattice. */
@@ -263,7 +281,11 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * part of each step inside the y-forward pass of the next product where the
  * schedule's y pass allows it (schedules 0, 1, 3); 0 keeps the separate step
  * kernel.  Same recurrences either way. */
-enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4 };
+/* DDA_OPT_RHS_PER_BLOCK (0..8): right-hand sides each block of the two-level
+ * z pass (schedule 5) runs in turn, sharing its spectrum tile; 0 (default)
+ * picks it from the launch size. */
+enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4,
+       DDA_OPT_RHS_PER_BLOCK = 5 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:
@@ -276,14 +298,17 @@ int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
 int dda_get_spectrum(dda_target *t, int precision, void *out_dev, void *hip_stream);
 
 /* Kernel timing for measurement: while enabled, every launch of a
- * matrix-vector pass is bracketed by HIP events on its own stream (and the
- * solver does not capture graphs).  dda_profile_read fills ms[14] (summed
- * milliseconds) and count[14] (launches) for the passes y-forward, x-forward,
+ * matrix-vector pass, and every whole product, is bracketed by HIP events on
+ * its own stream (and the solver does not capture graphs).  dda_profile_read
+ * fills ms[2*DDA_PROF_SLOTS] (summed milliseconds) and
+ * count[2*DDA_PROF_SLOTS] (launches) for the slots y-forward, x-forward,
  * z (forward, product, inverse), x-inverse, y-inverse, fused xy-forward,
- * fused xy-inverse with FP64 vectors (0..6) and FP32 vectors (7..13); it
- * waits for the recorded events. */
+ * fused xy-inverse and the whole product (all its passes and the gaps
+ * between them), with FP64 vectors (slots 0..DDA_PROF_SLOTS-1) and FP32
+ * vectors (the next DDA_PROF_SLOTS); it waits for the recorded events. */
+enum { DDA_PROF_SLOTS = 8 };
 int dda_profile_enable(dda_lib *lib, int enable);
-int dda_profile_read(dda_lib *lib, double *ms /* 14 */, int64_t *count /* 14 */);
+int dda_profile_read(dda_lib *lib, double *ms, int64_t *count);
 int dda_profile_reset(dda_lib *lib);
 
 /* Message of the last failing call on this thread ("" if none). */

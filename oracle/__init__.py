@@ -297,7 +297,7 @@ def circulant_spectrum(K, J, P, Kpp, Jpp, Ppp, k, half: bool = True) -> np.ndarr
 
 
 # ----------------------------------------------------------------------------
-# Cross sections (Sec. 5 outputs Q_ext, Q_abs, Q_sca; formulas of Draine 1988)
+# Cross sections (Sec. 6 outputs Q_ext, Q_abs, Q_sca; formulas of Draine 1988)
 # ----------------------------------------------------------------------------
 
 def c_ext(k, E, P) -> float:
@@ -394,7 +394,7 @@ def mueller_from_amplitude(S) -> np.ndarray:
 
 
 def a_eff(nd: int) -> float:
-    """Radius of the sphere of equal volume (Sec. 5), in units of d."""
+    """Radius of the sphere of equal volume (Sec. 6), in units of d."""
     return (3.0 * nd / (4.0 * math.pi)) ** (1.0 / 3.0)
 
 

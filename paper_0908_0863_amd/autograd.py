@@ -12,18 +12,9 @@ leaves (so ``torch.autograd.gradcheck`` applies directly).
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from . import dda
-
-
-def _ldr_S(khat, ehat):
-    kh = np.asarray(khat, np.float64).reshape(-1, 3)
-    eh = np.asarray(ehat, np.complex128).reshape(-1, 3)
-    # S = sum_a (khat_a ehat_a)^2, real for real directions; the library takes
-    # the real part (a directional constant of the lattice dispersion relation)
-    return [float(np.real(np.sum((k * e) ** 2))) for k, e in zip(kh, eh)]
 
 
 class CAbs(torch.autograd.Function):
@@ -44,9 +35,11 @@ class CAbs(torch.autograd.Function):
         kw.update(solve_kw or {})
         e = eps.detach().to("cpu", torch.complex128).numpy()
         target.set_permittivity(e, prescription)
-        S = _ldr_S(khat, ehat) if prescription == "ldr" else None
         E = target.incident_field(khat, ehat)
-        P, _ = target.solve(einc=E, S=S, **kw)
+        # the library derives the LDR orientation factors from khat/ehat and
+        # reports the ones it used, so the backward pass can hand them back
+        P, _ = target.solve(khat=khat, ehat=ehat, **kw)
+        S = target.orientation_factors(P.shape[0])
         _, cabs, _ = target.cross_sections(E, P, S=S)
         ctx.target, ctx.prescription, ctx.kw, ctx.S = target, prescription, kw, S
         ctx.eps_host = e

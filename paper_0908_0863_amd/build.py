@@ -7,8 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdda.so")
-SOURCES = ["dda.hip"]
-HEADERS = ["common.hpp", "fft_core.hpp", "kernels_fft.hpp", "kernels_solver.hpp"]
+SOURCES = ["dda.hip"]  # includes every kernel header of csrc/
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -27,6 +27,7 @@
 #include "kernels_solver.hpp"
 #include "kernels_krylov.hpp"
 #include "fft_fast.hpp"
+#include "fft_reg.hpp"
 #include "kernels_farfield.hpp"
 
 using namespace dda;
@@ -109,6 +110,33 @@ static bool fast_size(int n) {
   }
 }
 
+// lengths with a two-level z pass (fft_reg.hpp)
+static bool z2_size(int n) {
+  switch (n) {
+#define DDA_CASE(N) \
+  case N:           \
+    return Z2Shape<float, N>::ok;
+    DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+    default:
+      return false;
+  }
+}
+
+// columns per tile of the two-level z pass (and of the blocked layout)
+template <typename R>
+static int z2_cols(int n) {
+  switch (n) {
+#define DDA_CASE(N) \
+  case N:           \
+    return Z2Shape<R, N>::C;
+    DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+    default:
+      return 1;
+  }
+}
+
 // Padded FFT length for a lattice extent: any n'' >= 2n - 1 embeds the
 // Toeplitz matrix in a circulant (Sec. 3).  Take the smallest 2^a 3^b 5^c
 // length, or the smallest length with a register-resident kernel when it is
@@ -148,7 +176,9 @@ static int pow2_floor(long v) {
 // ----------------------------------------------------------------------------
 // Optional per-pass kernel timing: HIP events recorded on the launch stream
 // around every matrix-vector pass.
-enum { PASS_YFWD = 0, PASS_XFWD, PASS_ZMUL, PASS_XINV, PASS_YINV, PASS_XYFWD, PASS_XYINV, PASS_PER_PREC };
+// PASS_MATVEC brackets the whole product (every pass and the gaps between).
+enum { PASS_YFWD = 0, PASS_XFWD, PASS_ZMUL, PASS_XINV, PASS_YINV, PASS_XYFWD, PASS_XYINV, PASS_MATVEC, PASS_PER_PREC };
+static_assert(PASS_PER_PREC == DDA_PROF_SLOTS, "profiling slots of the header");
 constexpr int PASS_COUNT = 2 * PASS_PER_PREC;  // second half: FP32 vectors
 
 struct dda_lib {
@@ -203,8 +233,9 @@ struct PrecBufs {
   DevBuf a0, a1;            // diagonal alpha^{-1} = a0 + S a1
   DevBuf G1, G2;            // matvec workspaces
   int cap = 0;              // right-hand sides the workspaces hold
-  DevBuf vec;               // solver vectors: vec_slots x [vec_cap][3][nd]
+  DevBuf vec;               // solver vectors: vec_slots x [vec_cap][3][vec_nd]
   int vec_cap = 0, vec_slots = 0;
+  int64_t vec_nd = 0;
 };
 
 struct dda_target {
@@ -229,6 +260,7 @@ struct dda_target {
   int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
   int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
   int fuse_qmr = 1;          // QMR_sym step fused into the y-forward pass where possible
+  int z_rb = 0;              // right-hand sides per block of the two-level z pass (0: by size)
   int sched_override = -1;   // autotuner: schedule under trial (-1: none)
   // per-solve scratch
   DevBuf S;       // double [cap]
@@ -244,6 +276,9 @@ struct dda_target {
   DevBuf far_dirs, far_part, far_F, far_w, far_tp;  // far-field scratch
   double extent = 0;  // diameter of the occupied sites' bounding box (units of d)
   int scap = 0;
+  // LDR orientation factor S per right-hand side of the last dda_solve (the
+  // values passed, or those derived from khat/ehat); empty before a solve
+  std::vector<double> solve_S;
   std::vector<int> h_active;
   int matvecs = 0;
   // captured inner iteration
@@ -481,7 +516,11 @@ int dda_target_set_option(dda_target* t, int option, int value) {
         return fail(DDA_EINVAL, "dda_target_set_option: no z-contiguous schedule for this lattice");
       if (value == 3 && !fast_size(t->Ppp))
         return fail(DDA_EINVAL, "dda_target_set_option: no component-split z pass for this lattice");
-      if (value >= 2 && value != 3) {
+      if (value == 5 && !z2_size(t->Ppp))
+        return fail(DDA_EINVAL, "dda_target_set_option: no two-level z pass for this lattice");
+      if (value == 6 && !(z2_size(t->Ppp) && fast_size(t->Kpp)))
+        return fail(DDA_EINVAL, "dda_target_set_option: no tile-blocked schedule for this lattice");
+      if (value >= 2 && value != 3 && value != 5 && value != 6) {
         const std::vector<int> c64c = xy_candidates<double>(t), c32c = xy_candidates<float>(t);
         if (std::find(c64c.begin(), c64c.end(), value) == c64c.end() ||
             std::find(c32c.begin(), c32c.end(), value) == c32c.end())
@@ -497,6 +536,10 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_FUSE_QMR_STEP:
       if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: fuse %d", value);
       t->fuse_qmr = value;
+      return DDA_OK;
+    case DDA_OPT_RHS_PER_BLOCK:
+      if (value < 0 || value > 8) return fail(DDA_EINVAL, "dda_target_set_option: right-hand sides per block %d", value);
+      t->z_rb = value;
       return DDA_OK;
     case DDA_OPT_CANARY:
       if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: canary %d", value);
@@ -554,6 +597,21 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   HIPCHK(hipMemcpy(t->sites.p, sites.data(), sites.size() * sizeof(int), hipMemcpyHostToDevice));
   t->nd = (int64_t)sites.size();
   t->have_alpha = t->have_eps = false;
+  // everything sized or captured for the previous N_d goes: solver vectors
+  // (ensure_solver_ws grows them by count, not bytes), the captured
+  // iteration (its launches bake in N_d, block counts and slot offsets) and
+  // the orientation factors of the last solve
+  t->p32.vec.release();
+  t->p64.vec.release();
+  t->p32.vec_cap = t->p32.vec_slots = 0;
+  t->p64.vec_cap = t->p64.vec_slots = 0;
+  t->p32.vec_nd = t->p64.vec_nd = 0;
+  if (t->graph_exec) {
+    (void)hipGraphExecDestroy(t->graph_exec);
+    t->graph_exec = nullptr;
+  }
+  t->graph_key.clear();
+  t->solve_S.clear();
   {
     int lo[3] = {t->K, t->J, t->P}, hi[3] = {-1, -1, -1};
     for (int sv : sites) {
@@ -808,7 +866,12 @@ static int ensure_matvec_ws(dda_target* t, int nrhs) {
   PrecBufs<R>& b = bufs<R>(t);
   if (nrhs <= b.cap) return DDA_OK;
   CHK(b.G1.ensure((size_t)nrhs * 3 * t->P * t->Jpp * t->K * sizeof(cx<R>)));
-  CHK(b.G2.ensure((size_t)nrhs * 3 * t->P * t->Jpp * t->Kpp * sizeof(cx<R>)));
+  size_t g2 = (size_t)t->P * t->Jpp * t->Kpp;
+  if (z2_size(t->Ppp)) {  // the tile-blocked layout pads K'' to whole tiles
+    const int C = z2_cols<R>(t->Ppp);
+    g2 = std::max(g2, (size_t)t->P * t->Jpp * ((t->Kpp + C - 1) / C) * C);
+  }
+  CHK(b.G2.ensure((size_t)nrhs * 3 * g2 * sizeof(cx<R>)));
   b.cap = nrhs;
   return DDA_OK;
 }
@@ -907,6 +970,37 @@ struct FastLaunch {
     zm.ngroups = nrhs * zm.ngx * zm.ngy;
     dim3 grid(32 * ((zm.ngroups + 7) / 8));
     hipLaunchKernelGGL((k_fast_zsplit<R, N, TX>), grid, dim3(3 * FastPlan<N>::T * TX), 0, st, G2, Y, act, za, zm, tw);
+  }
+  // two-level z pass: right-hand sides per block chosen so that a launch
+  // still has some 2048 groups of four mirror tiles
+  // x passes to and from the tile-blocked layout of the two-level z pass
+  template <int N, bool INV>
+  static void xb(const dda_target* t, int nrhs, int C, hipStream_t st, const cx<R>* in, cx<R>* out, const int* act,
+                 const cx<R>* tw) {
+    constexpr int RW = fast_rw<N>();
+    int lc = 0;
+    while ((1 << lc) < C) ++lc;
+    const int NT = (t->Kpp + C - 1) / C;
+    dim3 grid((t->P + RW - 1) / RW, t->Jpp, nrhs * 3);
+    hipLaunchKernelGGL((k_xb<R, INV, N, RW>), grid, dim3(FastPlan<N>::T * RW), 0, st, in, out, t->K, t->P, t->Jpp,
+                       NT, lc, act, tw);
+  }
+  template <int N, bool BLK>
+  static void z2(int nrhs, int rb, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za,
+                 const cx<R>* tw) {
+    if constexpr (Z2Shape<R, N>::ok) {
+      constexpr int T = Z2Shape<R, N>::T, C = Z2Shape<R, N>::C, W = Z2Shape<R, N>::W;
+      Z2Map zm;
+      zm.NX = (za.Kpp + C - 1) / C;
+      zm.ngx = (zm.NX + 1) / 2;
+      zm.ngy = za.Jpp / 2 + 1;
+      const int per = zm.ngx * zm.ngy;
+      zm.nrhs = nrhs;
+      zm.RB = rb > 0 ? std::min(rb, nrhs) : std::max(1, std::min(8, (int)(((long)nrhs * per) / 2048)));
+      zm.ngroups = ((nrhs + zm.RB - 1) / zm.RB) * per;
+      dim3 grid(32 * ((zm.ngroups + 7) / 8));
+      hipLaunchKernelGGL((k_z2<R, N, T, W, BLK>), grid, dim3(64 * W), 0, st, G2, Y, act, za, zm, tw);
+    }
   }
   template <int N>
   static void zmul(int nrhs, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za, const cx<R>* tw) {
@@ -1024,8 +1118,19 @@ static int yinv_blocks(const dda_target* t, int nrhs) {
 // qf (fused QMR_sym step): the y-forward pass forms its input from the
 // step's vectors (qmr_fusable schedules only).
 template <typename R>
+static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
+                         const int* active, hipStream_t st, DotArgs dot, const QmrFuse<R>* qf);
+
+template <typename R>
 static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
                     const int* active, hipStream_t st, DotArgs dot = DotArgs(), const QmrFuse<R>* qf = nullptr) {
+  PassTimer pt(t->lib, PASS_MATVEC + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+  return matvec_passes<R>(t, nrhs, dS, jacobi, x, y, active, st, dot, qf);
+}
+
+template <typename R>
+static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
+                         const int* active, hipStream_t st, DotArgs dot, const QmrFuse<R>* qf) {
   CHK(ensure_matvec_ws<R>(t, nrhs));
   PrecBufs<R>& b = bufs<R>(t);
   const int K = t->K, J = t->J, P = t->P, Jpp = t->Jpp, Kpp = t->Kpp, Ppp = t->Ppp;
@@ -1122,7 +1227,55 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     LAUNCHCHK();
   }
   const long rows = (long)nrhs * 3 * P * Jpp;
-  if (sched == 1) {
+  if (sched == 6) {
+    // tile-blocked layout: x forward into z tiles -> two-level z pass -> x inverse
+    const int C = z2_cols<R>(Ppp);
+    ZArgs za;
+    za.Kpp = Kpp;
+    za.Jpp = Jpp;
+    za.P = P;
+    za.Ppp = Ppp;
+    za.Kh = t->Kh;
+    za.Jh = t->Jh;
+    za.Ph = t->Ph;
+    {
+      PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      switch (Kpp) {
+#define DDA_CASE(N)                                                                                          \
+  case N:                                                                                                    \
+    FastLaunch<R>::template xb<N, false>(t, nrhs, C, st, G1, G2, active, b.tw[0].template as<cx<R>>());    \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+      LAUNCHCHK();
+    }
+    {
+      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      switch (Ppp) {
+#define DDA_CASE(N)                                                                                      \
+  case N:                                                                                                \
+    FastLaunch<R>::template z2<N, true>(nrhs, t->z_rb, st, G2, b.Y.template as<cx<R>>(), active, za,      \
+                                        b.tw[2].template as<cx<R>>());                                    \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+      LAUNCHCHK();
+    }
+    {
+      PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      switch (Kpp) {
+#define DDA_CASE(N)                                                                                         \
+  case N:                                                                                                   \
+    FastLaunch<R>::template xb<N, true>(t, nrhs, C, st, G2, G1, active, b.tw[0].template as<cx<R>>());     \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+      LAUNCHCHK();
+    }
+  } else if (sched == 1) {
     // z-contiguous layout: x forward (transposed out) -> z lines -> x inverse (transposed in)
     {
       PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
@@ -1198,7 +1351,17 @@ static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const
     za.Kh = t->Kh;
     za.Jh = t->Jh;
     za.Ph = t->Ph;
-    if (fast_size(Ppp) && sched == 3) {
+    if (sched == 5 && z2_size(Ppp)) {
+      switch (Ppp) {
+#define DDA_CASE(N)                                                                                      \
+  case N:                                                                                                \
+    FastLaunch<R>::template z2<N, false>(nrhs, t->z_rb, st, G2, b.Y.template as<cx<R>>(), active, za,     \
+                                  b.tw[2].template as<cx<R>>());                                          \
+    break;
+        DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+      }
+    } else if (fast_size(Ppp) && sched == 3) {
       switch (Ppp) {
 #define DDA_CASE(N)                                                                                      \
   case N:                                                                                                \
@@ -1310,6 +1473,8 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   std::vector<int> cand = {0};
   if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
   if (fast_size(t->Ppp)) cand.push_back(3);
+  if (z2_size(t->Ppp)) cand.push_back(5);
+  if (z2_size(t->Ppp) && fast_size(t->Kpp)) cand.push_back(6);
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {
@@ -1426,6 +1591,10 @@ static int nblocks_for(long n3) {
 template <typename R>
 static int ensure_solver_ws(dda_target* t, int nrhs, int nslots) {
   PrecBufs<R>& b = bufs<R>(t);
+  if (b.vec_nd != t->nd) {  // sized for another occupancy: start over
+    b.vec_cap = b.vec_slots = 0;
+    b.vec_nd = t->nd;
+  }
   if (nrhs <= b.vec_cap && nslots <= b.vec_slots) return DDA_OK;
   const int cap = std::max(nrhs, b.vec_cap), ns = std::max(nslots, b.vec_slots);
   CHK(b.vec.ensure((size_t)ns * cap * 3 * t->nd * sizeof(cx<R>)));
@@ -1944,7 +2113,12 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
                                   (uintptr_t)B.G2.p,
                                   (uintptr_t)B.Y.p,
                                   (uintptr_t)B.a0.p,
-                                  (uintptr_t)B.a1.p};
+                                  (uintptr_t)B.a1.p,
+                                  (uintptr_t)t->has_a1,
+                                  (uintptr_t)t->aniso,
+                                  (uintptr_t)t->nd,
+                                  (uintptr_t)t->occ.p,
+                                  (uintptr_t)t->fuse_qmr};
     if (!t->graph_exec || t->graph_key != key) {
       if (t->graph_exec) {
         (void)hipGraphExecDestroy(t->graph_exec);
@@ -2216,9 +2390,12 @@ static int solve_one(dda_target* t, const dda_solve_opts* opts, int nrhs, const 
   HIPCHK(hipSetDevice(t->lib->device));
   CHK(ensure_scratch(t, nrhs));
   CHK(ensure_outer(t, nrhs));
+  if (t->has_a1 && !S && (!khat || !ehat))
+    return fail(DDA_EINVAL, "dda_solve: an LDR target needs S or khat and ehat (S depends on the orientation)");
   std::vector<double> hs;
   orientation_S(t, nrhs, khat, ehat, S, hs);
   HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  t->solve_S = hs;
   const c64* E = (const c64*)einc_dev;
   if (!E) {
     c64* Eg = t->outer.as<c64>();
@@ -2336,6 +2513,33 @@ extern "C" int dda_incident_field(dda_target* t, int nrhs, const double* khat, c
   return DDA_OK;
 }
 
+// S of a call after the solve: the caller's values, else (LDR targets) those
+// of the last dda_solve on the target when it had the same right-hand-side
+// count; an LDR target with neither is an error, since alpha^{-1} then
+// depends on an orientation the library does not know.  Non-LDR targets
+// have no S term (0).
+static int resolve_S(const dda_target* t, int nrhs, const double* S, const char* who, std::vector<double>& hs) {
+  hs.assign(nrhs, 0.0);
+  if (S) {
+    for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
+    return DDA_OK;
+  }
+  if (!t->has_a1) return DDA_OK;
+  if ((int)t->solve_S.size() != nrhs)
+    return fail(DDA_EINVAL, "%s: LDR target without S, and no solve of %d right-hand sides to take it from", who, nrhs);
+  hs = t->solve_S;
+  return DDA_OK;
+}
+
+extern "C" int dda_solve_orientation_factors(const dda_target* t, int nrhs, double* S_out) {
+  if (!t || !S_out || nrhs < 1) return fail(DDA_EINVAL, "dda_solve_orientation_factors: bad arguments");
+  if ((int)t->solve_S.size() != nrhs)
+    return fail(DDA_ESTATE, "dda_solve_orientation_factors: the last solve had %d right-hand sides, not %d",
+                (int)t->solve_S.size(), nrhs);
+  for (int r = 0; r < nrhs; ++r) S_out[r] = t->solve_S[r];
+  return DDA_OK;
+}
+
 extern "C" int dda_cross_sections(dda_target* t, int nrhs, const double* S, const void* einc_dev, const void* p_dev,
                                   double* cext, double* cabs, double* csca, void* hip_stream) {
   CHK(check_ready(t, "dda_cross_sections"));
@@ -2343,9 +2547,8 @@ extern "C" int dda_cross_sections(dda_target* t, int nrhs, const double* S, cons
   HIPCHK(hipSetDevice(t->lib->device));
   hipStream_t st = (hipStream_t)hip_stream;
   CHK(ensure_scratch(t, nrhs));
-  std::vector<double> hs(nrhs, 0.0);
-  if (S)
-    for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
+  std::vector<double> hs;
+  CHK(resolve_S(t, nrhs, S, "dda_cross_sections", hs));
   HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
   SolverDims dm;
   dm.n3 = 3 * t->nd;
@@ -2534,9 +2737,8 @@ extern "C" int dda_grad_cabs_eps(dda_target* t, const dda_solve_opts* opts, int 
   hipStream_t st = (hipStream_t)hip_stream;
   CHK(ensure_scratch(t, nrhs));
   CHK(ensure_outer(t, nrhs));
-  std::vector<double> hs(nrhs, 0.0);
-  if (S)
-    for (int r = 0; r < nrhs; ++r) hs[r] = S[r];
+  std::vector<double> hs;
+  CHK(resolve_S(t, nrhs, S, "dda_grad_cabs_eps", hs));
   HIPCHK(hipMemcpyAsync(t->S.p, hs.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
   const long n3 = 3 * t->nd;
   // adjoint right-hand side W conj(P) into a separate buffer (the outer slot 0

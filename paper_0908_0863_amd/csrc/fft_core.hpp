@@ -28,14 +28,14 @@ namespace dda {
 #define DDA_SIN144 0.58778525229247312917
 
 template <typename R, bool INV>
-__device__ __forceinline__ void dft2(cx<R>& a, cx<R>& b) {
+__host__ __device__ __forceinline__ void dft2(cx<R>& a, cx<R>& b) {
   cx<R> t = a - b;
   a = a + b;
   b = t;
 }
 
 template <typename R, bool INV>
-__device__ __forceinline__ void dft4(cx<R>* v) {
+__host__ __device__ __forceinline__ void dft4(cx<R>* v) {
   cx<R> t0 = v[0] + v[2], t1 = v[0] - v[2];
   cx<R> t2 = v[1] + v[3], t3 = rot90<R, INV>(v[1] - v[3]);
   v[0] = t0 + t2;
@@ -45,7 +45,7 @@ __device__ __forceinline__ void dft4(cx<R>* v) {
 }
 
 template <typename R, bool INV>
-__device__ __forceinline__ void dft3(cx<R>* v) {
+__host__ __device__ __forceinline__ void dft3(cx<R>* v) {
   cx<R> s = v[1] + v[2];
   cx<R> d = v[1] - v[2];
   cx<R> m = v[0] - (R)0.5 * s;
@@ -56,7 +56,7 @@ __device__ __forceinline__ void dft3(cx<R>* v) {
 }
 
 template <typename R, bool INV>
-__device__ __forceinline__ void dft5(cx<R>* v) {
+__host__ __device__ __forceinline__ void dft5(cx<R>* v) {
   const R c1 = (R)DDA_COS72, c2 = (R)DDA_COS144, s1 = (R)DDA_SIN72, s2 = (R)DDA_SIN144;
   cx<R> b1 = v[1] + v[4], b2 = v[2] + v[3];
   cx<R> d1 = v[1] - v[4], d2 = v[2] - v[3];
@@ -72,7 +72,7 @@ __device__ __forceinline__ void dft5(cx<R>* v) {
 }
 
 template <typename R, bool INV>
-__device__ __forceinline__ void dft8(cx<R>* v) {
+__host__ __device__ __forceinline__ void dft8(cx<R>* v) {
   cx<R> e[4] = {v[0], v[2], v[4], v[6]};
   cx<R> o[4] = {v[1], v[3], v[5], v[7]};
   dft4<R, INV>(e);
@@ -92,7 +92,7 @@ __device__ __forceinline__ void dft8(cx<R>* v) {
 }
 
 template <int RR, typename R, bool INV>
-__device__ __forceinline__ void dft_small(cx<R>* v) {
+__host__ __device__ __forceinline__ void dft_small(cx<R>* v) {
   if constexpr (RR == 2) dft2<R, INV>(v[0], v[1]);
   else if constexpr (RR == 3) dft3<R, INV>(v);
   else if constexpr (RR == 4) dft4<R, INV>(v);

@@ -1,7 +1,7 @@
 // Far-field outputs of a solved polarisation: the scattering amplitude of the
 // dipole array in any direction, C_sca by angular quadrature, and the
 // amplitude and Mueller matrices (the quantities the paper's code reports
-// after the solve, Sec. 5: Q_sca; formulas of Draine 1988 and Bohren &
+// after the solve, Sec. 6: Q_sca; formulas of Draine 1988 and Bohren &
 // Huffman 1983, Sec. 3.2-3.3).
 //
 // F(n) = k^2 (I - n n) A(n),  A(n) = sum_m e^{-i k n . r_m} P_m,

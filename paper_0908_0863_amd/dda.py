@@ -65,16 +65,17 @@ class dda_batch_item(ctypes.Structure):
 
 # Every symbol the header declares (tests check that the library exports them).
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
-           "dda_set_permittivity", "dda_set_polarizability", "dda_set_composition", "dda_build_spectrum", "dda_matvec", "dda_solve",
-           "dda_batch_solve",
+           "dda_set_permittivity", "dda_set_polarizability", "dda_set_composition", "dda_build_spectrum", "dda_matvec",
+           "dda_solve", "dda_solve_orientation_factors", "dda_batch_solve",
            "dda_incident_field", "dda_cross_sections", "dda_far_field", "dda_csca_quadrature", "dda_mueller",
            "dda_grad_cabs_eps", "dda_target_set_option",
            "dda_target_info",
            "dda_get_spectrum", "dda_profile_enable", "dda_profile_read", "dda_profile_reset",
            "dda_last_error"]
 
-PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse", "xy_forward", "xy_inverse"]
-DDA_OPT_SCHEDULE, DDA_OPT_INJECT_BREAKDOWN, DDA_OPT_CANARY, DDA_OPT_FUSE_QMR_STEP = 1, 2, 3, 4
+PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse", "xy_forward", "xy_inverse", "matvec"]
+DDA_PROF_SLOTS = len(PASS_NAMES)
+DDA_OPT_SCHEDULE, DDA_OPT_INJECT_BREAKDOWN, DDA_OPT_CANARY, DDA_OPT_FUSE_QMR_STEP, DDA_OPT_RHS_PER_BLOCK = 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -101,6 +102,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_build_spectrum": (i, [vp, vp]),
         "dda_matvec": (i, [vp, i, i, vp, i, vp, vp, vp]),
         "dda_solve": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp, vp, vp, vp]),
+        "dda_solve_orientation_factors": (i, [vp, i, vp]),
         "dda_batch_solve": (i, [vp, P(dda_solve_opts), i, vp, i, vp]),
         "dda_incident_field": (i, [vp, i, vp, vp, vp, vp]),
         "dda_cross_sections": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
@@ -352,6 +354,12 @@ class Target:
         if rc != DDA_ENOTCONV or raise_on_fail:
             _check(rc)
         return P, infos
+
+    def orientation_factors(self, nrhs: int) -> list:
+        """The LDR orientation factors S the last solve on this target used."""
+        out = np.zeros(int(nrhs))
+        _check(load().dda_solve_orientation_factors(self.h, int(nrhs), _np_ptr(out)))
+        return [float(v) for v in out]
 
     def cross_sections(self, einc: torch.Tensor, P: torch.Tensor, S=None):
         nrhs = P.shape[0]

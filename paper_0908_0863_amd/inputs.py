@@ -20,7 +20,7 @@ def sphere(K: int) -> np.ndarray:
     |r - c|^2 <= (K/2)^2 with c = ((K-1)/2, (K-1)/2, (K-1)/2).  Evaluated in
     exact integers as sum (2x - (K-1))^2 <= K^2.  This rule reproduces every
     occupied-site count the paper prints (18^3 -> 3,112 in Sec. 4; 200^3 ...
-    600^3 in Sec. 5 and its system-size table)."""
+    600^3 in Sec. 6 and its system-size table)."""
     a = (2 * np.arange(K, dtype=np.int64) - (K - 1)) ** 2
     d = a[:, None, None] + a[None, :, None] + a[None, None, :]
     return (d <= K * K).astype(np.uint8)
@@ -177,14 +177,14 @@ def workload(name: str) -> dict:
         big = sphere_count(128)
         return dict(name=name, occ=occ, K=10, J=10, P=10, m=1.6 + 0.05j,
                     kd=kd_from_size_parameter(20.0, big), khat=[zhat], ehat=[xh])
-    if name == "sphere200":    # the paper's benchmark sphere (Sec. 5, Table 3): same optics as cube100
+    if name == "sphere200":    # the paper's benchmark sphere (Sec. 6, Table 3): same optics as cube100
         occ = sphere(200)
         nd = int(occ.sum())
         lam, a = 3.175, 0.5
         x = 2.0 * math.pi * a / lam
         return dict(name=name, occ=occ, K=200, J=200, P=200, m=1.63631 + 0.372j,
                     kd=kd_from_size_parameter(x, nd), khat=[zhat], ehat=[xh])
-    if name == "cube100":      # the paper's validation cube (Sec. 5): x = 0.989478
+    if name == "cube100":      # the paper's validation cube (Sec. 6): x = 0.989478
         occ = cube(100)
         lam, a = 3.175, 0.5
         x = 2.0 * math.pi * a / lam

@@ -3,7 +3,7 @@
 * Matrix-vector product at the full lattices (64^3 cube, 96^3 ellipsoid,
   128^3 sphere) in the configuration the solver runs it (Jacobi-scaled, tuned
   schedule), on seeded sampled rows that the dense oracle forms one by one.
-* The paper's validation cube (Sec. 5): 100^3 dipoles, efficiencies against
+* The paper's validation cube (Sec. 6): 100^3 dipoles, efficiencies against
   the published table.
 * The adjoint gradient at the 128^3 sphere against central finite differences
   of C_abs, each perturbed C_abs obtained from unperturbed solves by an exact
@@ -52,6 +52,11 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
+def _maxrel(a, b):
+    """Largest single-element error relative to the largest oracle element."""
+    return float(np.abs(np.ravel(a - b)).max() / np.abs(np.ravel(b)).max())
+
+
 @pytest.mark.parametrize("name", ["cube64", "ellipsoid96", "sphere128"])
 def test_matvec_full_size_sampled_rows(lib, name):
     w = inputs.workload(name)
@@ -66,9 +71,11 @@ def test_matvec_full_size_sampled_rows(lib, name):
     yo = s[rows] * ora.dense_matvec(sites, w["kd"], ainv, s * x[0], rows=rows)
     for dt in (np.complex128, np.complex64):
         y = t.matvec(torch.from_numpy(x.astype(dt)).cuda(), S=[S], jacobi=True).cpu().numpy()[0][:, rows]
-        err = _rel(y, yo)
-        print(f"{name} {np.dtype(dt).name}: rel err on {rows.size} rows = {err:.3e}", flush=True)
-        assert err < (1e-12 if dt == np.complex128 else FP32_FULL_TOL), (name, dt, err)
+        err, emax = _rel(y, yo), _maxrel(y, yo)
+        print(f"{name} {np.dtype(dt).name}: rel err on {rows.size} rows = {err:.3e}, max element {emax:.3e}",
+              flush=True)
+        tol = 1e-12 if dt == np.complex128 else FP32_FULL_TOL
+        assert err < tol and emax < tol, (name, dt, err, emax)
 
 
 def _ellipsoid96_S(w):
@@ -98,9 +105,11 @@ def test_batched_128_rhs_matvec_sampled_rows(lib):
     for x in (x32.to(torch.complex128), x32):
         y = t.matvec(x, S=S, jacobi=True)
         for r in picks:
-            err = _rel(y[r].cpu().numpy()[:, rows], yo[r])
-            print(f"ellipsoid96 x128 {x.dtype} rhs {r}: rel err {err:.3e}", flush=True)
-            assert err < (1e-12 if x.dtype == torch.complex128 else FP32_FULL_TOL), (r, x.dtype, err)
+            yr = y[r].cpu().numpy()[:, rows]
+            err, emax = _rel(yr, yo[r]), _maxrel(yr, yo[r])
+            print(f"ellipsoid96 x128 {x.dtype} rhs {r}: rel err {err:.3e}, max element {emax:.3e}", flush=True)
+            tol = 1e-12 if x.dtype == torch.complex128 else FP32_FULL_TOL
+            assert err < tol and emax < tol, (r, x.dtype, err, emax)
         del y
 
 

@@ -393,3 +393,58 @@ def test_composition_reduces_to_isotropic_and_keeps_the_optical_theorem():
     P = ora.solve_dense(sites, k, ainv, E)
     cext, cabs = ora.c_ext(k, E, P), ora.c_abs(k, ainv, P)
     assert cext == pytest.approx(cabs + ora.c_sca_quadrature(sites, k, P), rel=1e-11)
+
+
+# --- the LDR orientation factor S = sum_a (khat_a ehat_a)^2 (Sec. 1 names LDR) --
+# Pinned by geometry, not by re-typing the formula: an axis-aligned wave has no
+# product k_a e_a; on a body diagonal every k_a^2 is 1/3 and sum_a e_a^2 = 1;
+# for an orthonormal triad (e1, e2, khat) every axis obeys
+# e1_a^2 + e2_a^2 + k_a^2 = 1, so S(e1) + S(e2) = sum_a k_a^2 (1 - k_a^2).  A
+# dropped square, (khat . ehat)^2 (identically 0) or a swapped operand fails.
+
+def _transverse_pair(khat, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(3)
+    e1 = v - np.dot(v, khat) * khat
+    e1 /= np.linalg.norm(e1)
+    return e1, np.cross(khat, e1)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_ldr_S_vanishes_along_lattice_axes(axis):
+    khat = np.eye(3)[axis]
+    for seed in range(4):
+        e1, e2 = _transverse_pair(khat, seed)
+        assert ora.ldr_S(khat, e1) == 0.0
+        assert ora.ldr_S(-khat, e2) == 0.0
+
+
+def test_ldr_S_is_one_third_on_the_body_diagonal():
+    for signs in ([1, 1, 1], [1, -1, 1], [-1, -1, 1]):
+        khat = np.array(signs, float) / math.sqrt(3.0)
+        for seed in range(5):
+            e1, e2 = _transverse_pair(khat, seed)
+            assert ora.ldr_S(khat, e1) == pytest.approx(1.0 / 3.0, abs=1e-15)
+            assert ora.ldr_S(khat, e2) == pytest.approx(1.0 / 3.0, abs=1e-15)
+
+
+def test_ldr_S_transverse_sum_rule():
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        khat = rng.standard_normal(3)
+        khat /= np.linalg.norm(khat)
+        e1, e2 = _transverse_pair(khat, int(rng.integers(1 << 30)))
+        want = float(np.sum(khat ** 2 * (1.0 - khat ** 2)))
+        assert ora.ldr_S(khat, e1) + ora.ldr_S(khat, e2) == pytest.approx(want, abs=1e-15)
+        assert 0.0 <= ora.ldr_S(khat, e1) <= 0.5 + 1e-15  # k_a^2 e_a^2 <= (k_a^2 + e_a^2) / 4 as k_a^2 + e_a^2 <= 1
+
+
+def test_ldr_S_enters_alpha_inv_through_b3_only():
+    """Only the b3 S eps kd^2 term depends on S: the difference of two S values
+    is b3 (S1 - S2) eps kd^2, and S = 0 leaves the CM + b1 + b2 eps form."""
+    eps, kd = 2.3 + 0.4j, 0.3
+    a1 = ora.alpha_inv(eps, kd, "ldr", 1.0 / 3.0)
+    a0 = ora.alpha_inv(eps, kd, "ldr", 0.0)
+    assert a1 - a0 == pytest.approx(ora.LDR_B3 * eps * kd ** 2 / 3.0, rel=1e-12)
+    rr = ora.alpha_inv(eps, kd, "rr")
+    assert a0 - rr == pytest.approx((ora.LDR_B1 + ora.LDR_B2 * eps) * kd ** 2, rel=1e-12)
