@@ -134,6 +134,23 @@ int dda_build_spectrum(dda_target *t, void *hip_stream);
 int dda_matvec(dda_target *t, int precision, int nrhs, const double *S, int jacobi, const void *x_dev,
                void *y_dev, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of dda_matvec with every device buffer it needs beyond x_dev and y_dev (the
+ * nrhs orientation factors and the two FFT workspaces, K'' padded to whole
+ * z tiles) placed in a device scratch array that the library holds on each
+ * device until the process ends, at most 64 MiB (e.g. the 64^3 cube with one
+ * FP32 right-hand side needs 38 MB).  A call that needs more returns
+ * DDA_EINVAL and does nothing.  The call allocates nothing, does not autotune
+ * (it runs the schedule the library has tuned for this lattice and
+ * right-hand-side count, else the five plain passes; DDA_OPT_SCHEDULE
+ * applies), records no profiling events, and synchronises the stream before
+ * returning (S may be reused at once).  All calls on one device share its
+ * scratch: calls that overlap in time on one device, from any target or
+ * library, race.  Arguments, layout and results as for dda_matvec. */
+int dda_matvec_noalloc(dda_target *t, int precision, int nrhs, const double *S, int jacobi, const void *x_dev,
+                       void *y_dev, void *hip_stream);
+
 typedef struct {
   int solver;        /* one of the DDA_* solver values above                      */
   int precision;     /* DDA_SOLVE_FP64, or DDA_SOLVE_MIXED (FP32 inner, FP64 outer) */

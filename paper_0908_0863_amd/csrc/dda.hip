@@ -181,8 +181,16 @@ enum { PASS_YFWD = 0, PASS_XFWD, PASS_ZMUL, PASS_XINV, PASS_YINV, PASS_XYFWD, PA
 static_assert(PASS_PER_PREC == DDA_PROF_SLOTS, "profiling slots of the header");
 constexpr int PASS_COUNT = 2 * PASS_PER_PREC;  // second half: FP32 vectors
 
+// Device scratch of the allocation-free product (dda_matvec_noalloc): the
+// orientation factors and the FFT workspaces of one call.  One copy per
+// device, held until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns with that device current (dda_open).
+static constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct dda_lib {
   int device = 0;
+  unsigned char* scratch_dev = nullptr;  // this device's copy of `scratch`
   std::string tune_path;
   std::map<std::string, int> tuned;  // schedule per (lattice, padding, nrhs, precision)
   std::mutex tune_mu;                // guards `tuned` and the tune file (batch workers)
@@ -209,16 +217,17 @@ struct PassTimer {
   dda_lib* l;
   int pass;
   hipStream_t st;
+  bool on;
   hipEvent_t a = nullptr, b = nullptr;
-  PassTimer(dda_lib* l_, int p, hipStream_t s) : l(l_), pass(p), st(s) {
-    if (l->prof) {
+  PassTimer(dda_lib* l_, int p, hipStream_t s, bool enabled = true) : l(l_), pass(p), st(s), on(enabled && l_->prof) {
+    if (on) {
       a = take_event(l);
       b = take_event(l);
       if (a) (void)hipEventRecord(a, st);
     }
   }
   ~PassTimer() {
-    if (l->prof && a && b) {
+    if (on && a && b) {
       (void)hipEventRecord(b, st);
       l->pending.push_back({pass, {a, b}});
     }
@@ -261,6 +270,8 @@ struct dda_target {
   int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
   int fuse_qmr = 1;          // QMR_sym step fused into the y-forward pass where possible
   int z_rb = 0;              // right-hand sides per block of the two-level z pass (0: by size)
+  // dda_matvec_noalloc: FFT workspaces in the device scratch, no profiling
+  void* ws_over[2] = {nullptr, nullptr};
   int sched_override = -1;   // autotuner: schedule under trial (-1: none)
   // per-solve scratch
   DevBuf S;       // double [cap]
@@ -423,6 +434,13 @@ int dda_open(int hip_device, const char* tune_cache_path, dda_lib** out) {
   HIPCHK(hipSetDevice(hip_device));
   dda_lib* l = new dda_lib();
   l->device = hip_device;
+  {
+    const hipError_t e = hipGetSymbolAddress((void**)&l->scratch_dev, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !l->scratch_dev) {
+      delete l;
+      return fail(DDA_EDEVICE, "dda_open: scratch address on device %d: %s", hip_device, hipGetErrorString(e));
+    }
+  }
   if (tune_cache_path) {
     l->tune_path = tune_cache_path;
     std::ifstream f(tune_cache_path);
@@ -861,17 +879,28 @@ static int ensure_scratch(dda_target* t, int nrhs) {
   return DDA_OK;
 }
 
+// Bytes of the two FFT workspaces of a product (every schedule): the
+// y-transformed array [nrhs][3][P][J''][K] and the x-transformed one (K''
+// padded to whole tiles where the tile-blocked layout exists).
+template <typename R>
+static void matvec_ws_bytes(const dda_target* t, int nrhs, size_t& g1, size_t& g2) {
+  size_t e2 = (size_t)t->P * t->Jpp * t->Kpp;
+  if (z2_size(t->Ppp)) {
+    const int C = z2_cols<R>(t->Ppp);
+    e2 = std::max(e2, (size_t)t->P * t->Jpp * ((t->Kpp + C - 1) / C) * C);
+  }
+  g1 = (size_t)nrhs * 3 * t->P * t->Jpp * t->K * sizeof(cx<R>);
+  g2 = (size_t)nrhs * 3 * e2 * sizeof(cx<R>);
+}
+
 template <typename R>
 static int ensure_matvec_ws(dda_target* t, int nrhs) {
   PrecBufs<R>& b = bufs<R>(t);
   if (nrhs <= b.cap) return DDA_OK;
-  CHK(b.G1.ensure((size_t)nrhs * 3 * t->P * t->Jpp * t->K * sizeof(cx<R>)));
-  size_t g2 = (size_t)t->P * t->Jpp * t->Kpp;
-  if (z2_size(t->Ppp)) {  // the tile-blocked layout pads K'' to whole tiles
-    const int C = z2_cols<R>(t->Ppp);
-    g2 = std::max(g2, (size_t)t->P * t->Jpp * ((t->Kpp + C - 1) / C) * C);
-  }
-  CHK(b.G2.ensure((size_t)nrhs * 3 * g2 * sizeof(cx<R>)));
+  size_t g1, g2;
+  matvec_ws_bytes<R>(t, nrhs, g1, g2);
+  CHK(b.G1.ensure(g1));
+  CHK(b.G2.ensure(g2));
   b.cap = nrhs;
   return DDA_OK;
 }
@@ -1124,18 +1153,19 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
 template <typename R>
 static int matvec_T(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
                     const int* active, hipStream_t st, DotArgs dot = DotArgs(), const QmrFuse<R>* qf = nullptr) {
-  PassTimer pt(t->lib, PASS_MATVEC + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+  PassTimer pt(t->lib, PASS_MATVEC + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, !t->ws_over[0]);
   return matvec_passes<R>(t, nrhs, dS, jacobi, x, y, active, st, dot, qf);
 }
 
 template <typename R>
 static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, const cx<R>* x, cx<R>* y,
                          const int* active, hipStream_t st, DotArgs dot, const QmrFuse<R>* qf) {
-  CHK(ensure_matvec_ws<R>(t, nrhs));
+  const bool own_ws = !t->ws_over[0];
+  if (own_ws) CHK(ensure_matvec_ws<R>(t, nrhs));
   PrecBufs<R>& b = bufs<R>(t);
   const int K = t->K, J = t->J, P = t->P, Jpp = t->Jpp, Kpp = t->Kpp, Ppp = t->Ppp;
-  cx<R>* G1 = b.G1.template as<cx<R>>();
-  cx<R>* G2 = b.G2.template as<cx<R>>();
+  cx<R>* G1 = own_ws ? b.G1.template as<cx<R>>() : (cx<R>*)t->ws_over[0];
+  cx<R>* G2 = own_ws ? b.G2.template as<cx<R>>() : (cx<R>*)t->ws_over[1];
   const cx<R>* a0 = b.a0.template as<cx<R>>();
   const cx<R>* a1 = t->has_a1 ? b.a1.template as<cx<R>>() : nullptr;
   VecArgs va;
@@ -1156,7 +1186,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   if (dfwd) {
     // fused: xy forward -> z with product -> xy inverse
     {
-      PassTimer pt(t->lib, PASS_XYFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_XYFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       int rc = DDA_EINVAL;
 #define DDA_CASE(NN, D)                                                                          \
   if (Kpp == NN && dfwd == D) rc = launch_xy_fwd<R, NN, D>(t, nrhs, st, x, G2, a0, a1, dS, active, va);
@@ -1165,7 +1195,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       CHK(rc);
     }
     {
-      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       ZArgs za;
       za.Kpp = Kpp;
       za.Jpp = Jpp;
@@ -1194,7 +1224,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       LAUNCHCHK();
     }
     {
-      PassTimer pt(t->lib, PASS_XYINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_XYINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       int rc = DDA_EINVAL;
 #define DDA_CASE(NN, D)                                                                                   \
   if (Kpp == NN && dinv == D) rc = launch_xy_inv<R, NN, D>(t, nrhs, st, G2, x, y, a0, a1, dS, active, va, dot);
@@ -1206,7 +1236,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     return DDA_OK;
   }
   {
-    PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+    PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
     if (fast_size(Jpp)) {
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                         \
@@ -1239,7 +1269,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     za.Jh = t->Jh;
     za.Ph = t->Ph;
     {
-      PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       switch (Kpp) {
 #define DDA_CASE(N)                                                                                          \
   case N:                                                                                                    \
@@ -1251,7 +1281,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       LAUNCHCHK();
     }
     {
-      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       switch (Ppp) {
 #define DDA_CASE(N)                                                                                      \
   case N:                                                                                                \
@@ -1264,7 +1294,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       LAUNCHCHK();
     }
     {
-      PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       switch (Kpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
@@ -1278,7 +1308,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   } else if (sched == 1) {
     // z-contiguous layout: x forward (transposed out) -> z lines -> x inverse (transposed in)
     {
-      PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       switch (Kpp) {
 #define DDA_CASE(N)                                                                               \
   case N:                                                                                         \
@@ -1290,7 +1320,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       LAUNCHCHK();
     }
     {
-      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       ZArgs za;
       za.Kpp = Kpp;
       za.Jpp = Jpp;
@@ -1311,7 +1341,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       LAUNCHCHK();
     }
     {
-      PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+      PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
       switch (Kpp) {
 #define DDA_CASE(N)                                                                              \
   case N:                                                                                        \
@@ -1324,7 +1354,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     }
   } else {
   {
-  PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+  PassTimer pt(t->lib, PASS_XFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
   if (fast_size(Kpp)) {
     switch (Kpp) {
 #define DDA_CASE(N)                                                                                          \
@@ -1342,7 +1372,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   }
   }
   {
-    PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+    PassTimer pt(t->lib, PASS_ZMUL + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
     ZArgs za;
     za.Kpp = Kpp;
     za.Jpp = Jpp;
@@ -1391,7 +1421,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     LAUNCHCHK();
   }
   {
-  PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+  PassTimer pt(t->lib, PASS_XINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
   if (fast_size(Kpp)) {
     switch (Kpp) {
 #define DDA_CASE(N)                                                                                         \
@@ -1410,7 +1440,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   }
   }
   {
-    PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st);
+    PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
     if (fast_size(Jpp)) {
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                             \
@@ -1573,6 +1603,54 @@ extern "C" int dda_matvec(dda_target* t, int precision, int nrhs, const double* 
     return matvec_T<float>(t, nrhs, t->S.as<double>(), jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, nullptr, st);
   }
   return fail(DDA_EINVAL, "dda_matvec: precision %d", precision);
+}
+
+// The product of dda_matvec with every device buffer it needs beyond x and y
+// (the orientation factors and the FFT workspaces) in the device scratch:
+// no allocation, no autotuning (the schedule is the tuned one if the library
+// has it, else the five plain passes), no profiling events.
+template <typename R>
+static int matvec_noalloc_T(dda_target* t, int nrhs, const double* S, int jacobi, const cx<R>* x, cx<R>* y,
+                            hipStream_t st) {
+  const size_t sb = ((size_t)nrhs * sizeof(double) + 255) & ~(size_t)255;
+  size_t g1, g2;
+  matvec_ws_bytes<R>(t, nrhs, g1, g2);
+  g1 = (g1 + 255) & ~(size_t)255;
+  g2 = (g2 + 255) & ~(size_t)255;
+  if (sb + g1 + g2 > kScratchBytes)
+    return fail(DDA_EINVAL, "dda_matvec_noalloc: %d right-hand sides of this lattice need %zu bytes of scratch, "
+                "the maximum is %zu", nrhs, sb + g1 + g2, kScratchBytes);
+  unsigned char* base = t->lib->scratch_dev;
+  double* dS = (double*)base;
+  if (S) HIPCHK(hipMemcpyAsync(dS, S, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  else HIPCHK(hipMemsetAsync(dS, 0, nrhs * sizeof(double), st));
+  if (t->canary) {
+    HIPCHK(hipMemsetAsync(base + sb, 0xFF, g1, st));
+    HIPCHK(hipMemsetAsync(base + sb + g1, 0xFF, g2, st));
+  }
+  t->ws_over[0] = base + sb;
+  t->ws_over[1] = base + sb + g1;
+  const int rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+  t->ws_over[0] = t->ws_over[1] = nullptr;
+  CHK(rc);
+  HIPCHK(hipStreamSynchronize(st));  // the caller's S may be reused at return
+  return DDA_OK;
+}
+
+extern "C" int dda_matvec_noalloc(dda_target* t, int precision, int nrhs, const double* S, int jacobi,
+                                  const void* x_dev, void* y_dev, void* hip_stream) {
+  CHK(check_ready(t, "dda_matvec_noalloc"));
+  if (nrhs < 1) return fail(DDA_EINVAL, "dda_matvec_noalloc: nrhs = %d", nrhs);
+  if (!x_dev || !y_dev) return fail(DDA_EINVAL, "dda_matvec_noalloc: NULL vector");
+  if (x_dev == y_dev) return fail(DDA_EINVAL, "dda_matvec_noalloc: x and y must not alias");
+  if (!t->lib->scratch_dev) return fail(DDA_ESTATE, "dda_matvec_noalloc: no device scratch");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == DDA_FP64)
+    return matvec_noalloc_T<double>(t, nrhs, S, jacobi ? 1 : 0, (const c64*)x_dev, (c64*)y_dev, st);
+  if (precision == DDA_FP32)
+    return matvec_noalloc_T<float>(t, nrhs, S, jacobi ? 1 : 0, (const c32*)x_dev, (c32*)y_dev, st);
+  return fail(DDA_EINVAL, "dda_matvec_noalloc: precision %d", precision);
 }
 
 // ----------------------------------------------------------------------------

@@ -66,7 +66,7 @@ class dda_batch_item(ctypes.Structure):
 # Every symbol the header declares (tests check that the library exports them).
 EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "dda_set_occupancy",
            "dda_set_permittivity", "dda_set_polarizability", "dda_set_composition", "dda_build_spectrum", "dda_matvec",
-           "dda_solve", "dda_solve_orientation_factors", "dda_batch_solve",
+           "dda_matvec_noalloc", "dda_solve", "dda_solve_orientation_factors", "dda_batch_solve",
            "dda_incident_field", "dda_cross_sections", "dda_far_field", "dda_csca_quadrature", "dda_mueller",
            "dda_grad_cabs_eps", "dda_target_set_option",
            "dda_target_info",
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_set_composition": (i, [vp, i, vp, vp, i]),
         "dda_build_spectrum": (i, [vp, vp]),
         "dda_matvec": (i, [vp, i, i, vp, i, vp, vp, vp]),
+        "dda_matvec_noalloc": (i, [vp, i, i, vp, i, vp, vp, vp]),
         "dda_solve": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp, vp, vp, vp]),
         "dda_solve_orientation_factors": (i, [vp, i, vp]),
         "dda_batch_solve": (i, [vp, P(dda_solve_opts), i, vp, i, vp]),
@@ -315,6 +316,17 @@ class Target:
         Sa, Sp = _opt_np(S, np.float64, nrhs)
         _check(load().dda_matvec(self.h, prec, nrhs, Sp, int(bool(jacobi)), _dptr(x), _dptr(y), _stream()))
         return y
+
+    def matvec_noalloc(self, x: torch.Tensor, out: torch.Tensor, S=None, jacobi: bool = False):
+        """dda_matvec_noalloc: y = A x into the caller's ``out`` with the
+        library's device scratch for every other buffer (nothing allocated)."""
+        if x.dim() != 3 or x.shape[1] != 3 or x.shape[2] != self.nd or out.shape != x.shape or out.dtype != x.dtype:
+            raise ValueError("x and out must be [nrhs, 3, N_d] of one dtype")
+        prec = {torch.complex128: DDA_FP64, torch.complex64: DDA_FP32}[x.dtype]
+        Sa, Sp = _opt_np(S, np.float64, x.shape[0])
+        _check(load().dda_matvec_noalloc(self.h, prec, x.shape[0], Sp, int(bool(jacobi)), _dptr(x), _dptr(out),
+                                         _stream()))
+        return out
 
     def incident_field(self, khat, ehat) -> torch.Tensor:
         kh = np.ascontiguousarray(np.asarray(khat, np.float64).reshape(-1, 3))
