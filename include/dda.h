@@ -115,7 +115,10 @@ int dda_set_polarizability(dda_target *t, const double *alpha);
  * the materials' permittivities (nmat <= 256); flags[3*N_d] the material
  * index of component c of dipole n at c*N_d + n.  The polarisability tensor is
  * diagonal in the lattice axes, component c taking the prescription (as for
- * dda_set_permittivity) at its own material.  DDA_EINVAL for a flag >= nmat
+ * dda_set_permittivity) at its own material.  The library keeps the flags
+ * bit-fielded at the smallest power-of-two width that holds nmat - 1 (1, 2, 4
+ * or 8 bits) with an nmat-entry table of alpha^{-1} per precision, which is
+ * what the matrix-vector passes read.  DDA_EINVAL for a flag >= nmat
  * or a material without finite alpha^{-1}.  dda_grad_cabs_eps needs an
  * isotropic dda_set_permittivity instead (DDA_ESTATE after this call). */
 int dda_set_composition(dda_target *t, int nmat, const double *eps, const uint8_t *flags, int prescription);

@@ -240,6 +240,7 @@ struct PrecBufs {
   DevBuf Yz;                // the same, z fastest: [6][Jh][Kh][Ph]
   DevBuf tw[3];             // twiddles for K'', J'', P''
   DevBuf a0, a1;            // diagonal alpha^{-1} = a0 + S a1
+  DevBuf mt0, mt1;          // composition: the materials' alpha^{-1} = mt0 + S mt1
   DevBuf G1, G2;            // matvec workspaces
   int cap = 0;              // right-hand sides the workspaces hold
   DevBuf vec;               // solver vectors: vec_slots x [vec_cap][3][vec_nd]
@@ -260,6 +261,12 @@ struct dda_target {
   DevBuf sites;  // int [nd] linear index
   bool have_alpha = false, have_eps = false, has_a1 = false;
   bool aniso = false;  // the three components' diagonals differ (dda_set_composition)
+  // bit-fielded composition (dda_set_composition): material index of entry
+  // c N_d + n at 2^mlb bits each; the matrix-vector passes read these and the
+  // materials' table instead of per-dipole diagonals
+  bool comp_bits = false;
+  int mlb = 0;
+  DevBuf mbits;
   int prescription = -1;
   DevBuf d0, d1;  // d alpha^{-1} / d eps = d0 + S d1 (FP64)
   PrecBufs<double> p64;
@@ -615,6 +622,7 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   HIPCHK(hipMemcpy(t->sites.p, sites.data(), sites.size() * sizeof(int), hipMemcpyHostToDevice));
   t->nd = (int64_t)sites.size();
   t->have_alpha = t->have_eps = false;
+  t->comp_bits = false;
   // everything sized or captured for the previous N_d goes: solver vectors
   // (ensure_solver_ws grows them by count, not bytes), the captured
   // iteration (its launches bake in N_d, block counts and slot offsets) and
@@ -727,6 +735,7 @@ int dda_set_permittivity(dda_target* t, const double* eps, int prescription) {
   t->prescription = prescription;
   t->have_alpha = t->have_eps = true;
   t->aniso = false;
+  t->comp_bits = false;
   return DDA_OK;
 }
 
@@ -748,6 +757,7 @@ int dda_set_polarizability(dda_target* t, const double* alpha) {
   t->have_alpha = true;
   t->have_eps = false;
   t->aniso = false;
+  t->comp_bits = false;
   return DDA_OK;
 }
 
@@ -772,7 +782,38 @@ int dda_set_composition(dda_target* t, int nmat, const double* eps, const uint8_
     a1[e] = ms[q];
   }
   const bool ldr = prescription == DDA_POL_LDR;
+  // per-dipole FP64 diagonals for the solver's outer kernels (scaling,
+  // refinement, cross sections), once per refinement step
   CHK(upload_diag(t, a0, ldr ? &a1 : nullptr));
+  // the matrix-vector passes read the flags at the minimal power-of-two bit
+  // width (Sec. 2: 4 materials need 2 bits) and the nmat-entry table
+  int fb = 1;
+  while ((1 << fb) < nmat) ++fb;
+  int mlb = 0;
+  while ((1 << mlb) < fb) ++mlb;
+  const size_t nbits = 3 * nd << mlb;
+  std::vector<uint32_t> words((nbits + 31) / 32, 0u);
+  for (size_t e = 0; e < 3 * nd; ++e) {
+    const size_t bit = e << mlb;
+    words[bit >> 5] |= (uint32_t)flags[e] << (bit & 31);
+  }
+  CHK(t->mbits.ensure(words.size() * sizeof(uint32_t)));
+  HIPCHK(hipMemcpy(t->mbits.p, words.data(), words.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  std::vector<c32> mf0(nmat), mf1(nmat);
+  for (int q = 0; q < nmat; ++q) {
+    mf0[q] = mk((float)mv[q].x, (float)mv[q].y);
+    mf1[q] = mk((float)ms[q].x, (float)ms[q].y);
+  }
+  CHK(t->p64.mt0.ensure(nmat * sizeof(c64)));
+  CHK(t->p64.mt1.ensure(nmat * sizeof(c64)));
+  CHK(t->p32.mt0.ensure(nmat * sizeof(c32)));
+  CHK(t->p32.mt1.ensure(nmat * sizeof(c32)));
+  HIPCHK(hipMemcpy(t->p64.mt0.p, mv.data(), nmat * sizeof(c64), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t->p64.mt1.p, ms.data(), nmat * sizeof(c64), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t->p32.mt0.p, mf0.data(), nmat * sizeof(c32), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t->p32.mt1.p, mf1.data(), nmat * sizeof(c32), hipMemcpyHostToDevice));
+  t->mlb = mlb;
+  t->comp_bits = true;
   t->prescription = prescription;
   t->have_alpha = true;
   t->have_eps = false;  // the permittivity gradient is defined per isotropic dipole
@@ -1177,6 +1218,12 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   va.Ppp = Ppp;
   va.nd = t->nd;
   va.dstride = t->aniso ? t->nd : 0;
+  if (t->comp_bits) {
+    va.mbits = t->mbits.as<uint32_t>();
+    va.mlb = t->mlb;
+    va.mt0 = b.mt0.p;
+    va.mt1 = t->has_a1 ? b.mt1.p : nullptr;
+  }
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
@@ -2196,7 +2243,11 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
                                   (uintptr_t)t->aniso,
                                   (uintptr_t)t->nd,
                                   (uintptr_t)t->occ.p,
-                                  (uintptr_t)t->fuse_qmr};
+                                  (uintptr_t)t->fuse_qmr,
+                                  (uintptr_t)t->comp_bits,
+                                  (uintptr_t)t->mbits.p,
+                                  (uintptr_t)B.mt0.p,
+                                  (uintptr_t)B.mt1.p};
     if (!t->graph_exec || t->graph_key != key) {
       if (t->graph_exec) {
         (void)hipGraphExecDestroy(t->graph_exec);

@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
   const int i = blockIdx.x * TX + l, k = blockIdx.y;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  const int cc = rc % 3;  // this component's diagonal entries
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   cx<R> v[E];
   QmrCoef qd{};
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
         if (n >= 0) {
           if constexpr (QF) val = qmr_elem<R>(q, qf, (long)rc * a.nd + n, acc);
           else val = xv[n];
-          if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, cd + n)) * val;
+          if (a.jacobi) val = jacobi_scale(diag_at(a0, a1, a, cc, n, Sr)) * val;
         }
       }
       v[m] = val;
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  const int cc = rc % 3;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   if (i < a.K) {
@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
       const int n = site_index(map, (long)k * a.J + e, i);
       if (n < 0) continue;
       const cx<R> conv = sc * v[m];
-      const cx<R> dg = diag_of(a0, a1, Sr, cd + n);
+      const cx<R> dg = diag_at(a0, a1, a, cc, n, Sr);
       const cx<R> xn = xv[n];
       const cx<R> yn = a.jacobi ? xn + jacobi_scale(dg) * conv : dg * xn + conv;
       yv[n] = yn;
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<
   if (active && !active[rhs]) return;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  const int cc = rc % 3;  // this component's diagonal entries
   // phase A: columns i in chunks of CA, M-point DFT along y
   for (int c0 = 0; c0 < a.K; c0 += CA) {
     const int l = threadIdx.x % CA, t = threadIdx.x / CA;
@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(256) k_xy_fwd(const cx<R>* __restrict__ x, cx<
           const int n = site_index(map, (long)k * a.J + j, i);
           if (n >= 0) {
             cx<R> val = xv[n];
-            if (a.jacobi) val = jacobi_scale(diag_of(a0, a1, Sr, cd + n)) * val;
+            if (a.jacobi) val = jacobi_scale(diag_at(a0, a1, a, cc, n, Sr)) * val;
             acc = acc + val * twy[(py * j) % NN];
           }
         }
@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, co
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  const int cc = rc % 3;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   for (int c0 = 0; c0 < Q; c0 += CY) {
     const int l = threadIdx.x % CY, t = threadIdx.x / CY;
@@ -740,7 +740,7 @@ __global__ void __launch_bounds__(256) k_xy_inv(const cx<R>* __restrict__ G2, co
         const int n = site_index(map, (long)k * a.J + j, i);
         if (n < 0) continue;
         const cx<R> conv = sc * v[m];
-        const cx<R> dg = diag_of(a0, a1, Sr, cd + n);
+        const cx<R> dg = diag_at(a0, a1, a, cc, n, Sr);
         const cx<R> xn = xv[n];
         const cx<R> yn = a.jacobi ? xn + jacobi_scale(dg) * conv : dg * xn + conv;
         yv[n] = yn;

@@ -208,7 +208,29 @@ struct VecArgs {
   int TX;
   int jacobi;  // 0: y = A x;  1: y = D^{-1/2} A D^{-1/2} x with D = diag(alpha^{-1})
   double scale;  // 1/(K''J''P'') for the inverse pass
+  // Bit-fielded composition (Sec. 2: a material index per dipole and
+  // direction, stored at the minimal bit width): when mbits is set, entry
+  // e = c N_d + n holds its material in bits [e 2^mlb, (e + 1) 2^mlb) of the
+  // word array, and alpha^{-1} = mt0[q] + S mt1[q] comes from the materials'
+  // table (of the pass's precision) instead of per-dipole arrays.
+  const uint32_t* mbits = nullptr;
+  int mlb = 0;
+  const void* mt0 = nullptr;
+  const void* mt1 = nullptr;
 };
+
+// alpha^{-1} of component c of dipole n for orientation factor S
+template <typename R>
+__device__ __forceinline__ cx<R> diag_at(const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
+                                         const VecArgs& a, int c, long n, R S) {
+  if (a.mbits) {
+    const long bit = ((long)c * a.nd + n) << a.mlb;
+    const uint32_t w = a.mbits[bit >> 5];
+    const int q = (int)((w >> (bit & 31)) & ((1u << (1 << a.mlb)) - 1u));
+    return diag_of((const cx<R>*)a.mt0, (const cx<R>*)a.mt1, S, q);
+  }
+  return diag_of(a0, a1, S, (long)c * a.dstride + n);
+}
 
 // Expansion (Sec. 4) of the compressed vector into the zero-padded
 // [K x J'' x P] array fused with the forward DFT along y on the K*P lines that
@@ -228,7 +250,7 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
   const int i0 = blockIdx.x * TX, k = blockIdx.y;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  const int cc = rc % 3;  // this component's diagonal entries
   for (int idx = tid; idx < d.n * TX; idx += nthr) {
     const int e = idx / TX, l = idx - e * TX, i = i0 + l;
     cx<R> v = mk((R)0, (R)0);
@@ -236,7 +258,7 @@ __global__ void __launch_bounds__(256) k_vec_yfwd(const cx<R>* __restrict__ x, c
       const int m = site_index(map, (long)k * a.J + e, i);
       if (m >= 0) {
         v = xv[m];
-        if (a.jacobi) v = jacobi_scale(diag_of(a0, a1, Sr, cd + m)) * v;
+        if (a.jacobi) v = jacobi_scale(diag_at(a0, a1, a, cc, m, Sr)) * v;
       }
     }
     A[e * TX + l] = v;
@@ -303,7 +325,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const long cd = (long)(rc % 3) * a.dstride;  // this component's diagonal entries
+  const int cc = rc % 3;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   for (int idx = tid; idx < a.J * TX; idx += nthr) {
@@ -312,7 +334,7 @@ __global__ void __launch_bounds__(256) k_vec_yinv(const cx<R>* __restrict__ G1, 
     const int m = site_index(map, (long)k * a.J + e, i);
     if (m < 0) continue;
     const cx<R> conv = sc * res[e * TX + l];
-    const cx<R> dg = diag_of(a0, a1, Sr, cd + m);
+    const cx<R> dg = diag_at(a0, a1, a, cc, m, Sr);
     const cx<R> xm = xv[m];
     const cx<R> ym = a.jacobi ? xm + jacobi_scale(dg) * conv : dg * xm + conv;
     yv[m] = ym;

@@ -411,6 +411,34 @@ def test_matvec_composition_matches_dense(lib, shape, jacobi):
         _close(y32[r], yo, 2e-6, (shape, r))
 
 
+@pytest.mark.parametrize("nmat", [1, 2, 5, 17, 256])
+@pytest.mark.parametrize("sched", [0, 2, 6])
+def test_matvec_bitfield_composition_widths(lib, nmat, sched):
+    """Material flags stored at 1, 1, 4, 8 and 8 bits (nmat = 1, 2, 5, 17,
+    256) on a lattice whose 3 N_d fields end mid-word, in the five-pass, fused
+    xy-plane and tile-blocked schedules, against the dense oracle."""
+    from paper_0908_0863_amd import dda
+    mats = [1.3 + 0.05 * q + 0.01j * (q % 7) + 0.2j for q in range(nmat)]
+    kd = 0.4
+    t, nd, occ, flags = _composed(lib, (16, 16, 7), 31 + nmat, kd, mats)
+    assert (3 * nd) % 32 != 0
+    try:
+        t.set_option(dda.DDA_OPT_SCHEDULE, sched)
+    except dda.DDAError:
+        pytest.skip(f"no schedule {sched}")
+    sites = ora.sites_of(occ)
+    S = [0.2]
+    x = inputs.complex_gaussian(32, (1, 3, nd))
+    for jacobi in (False, True):
+        y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+        y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=jacobi).cpu().numpy()
+        ainv = ora.alpha_inv_composition(mats, flags, kd, "ldr", S[0])
+        s = 1.0 / np.sqrt(ainv) if jacobi else np.ones((3, nd))
+        yo = s * ora.dense_matvec(sites, kd, ainv, s * x[0])
+        _close(y[0], yo, 1e-12, (nmat, sched, jacobi))
+        _close(y32[0], yo, 2e-6, (nmat, sched, jacobi))
+
+
 @pytest.mark.parametrize("solver", ["qmr_sym", "bicgstab"])
 def test_solve_composition_matches_lu(lib, solver):
     from paper_0908_0863_amd import dda
