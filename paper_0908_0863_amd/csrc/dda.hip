@@ -1332,7 +1332,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Ppp) {
 #define DDA_CASE(N)                                                                                      \
   case N:                                                                                                \
-    FastLaunch<R>::template z2<N, true>(nrhs, t->z_rb, st, G2, b.Y.template as<cx<R>>(), active, za,      \
+    FastLaunch<R>::template z2<N, true>(nrhs, t->z_rb, st, G2, b.Yz.template as<cx<R>>(), active, za,     \
                                         b.tw[2].template as<cx<R>>());                                    \
     break;
         DDA_FAST_SIZES(DDA_CASE)
@@ -1432,7 +1432,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Ppp) {
 #define DDA_CASE(N)                                                                                      \
   case N:                                                                                                \
-    FastLaunch<R>::template z2<N, false>(nrhs, t->z_rb, st, G2, b.Y.template as<cx<R>>(), active, za,     \
+    FastLaunch<R>::template z2<N, false>(nrhs, t->z_rb, st, G2, b.Yz.template as<cx<R>>(), active, za,    \
                                   b.tw[2].template as<cx<R>>());                                          \
     break;
         DDA_FAST_SIZES(DDA_CASE)

@@ -244,7 +244,7 @@ struct Z2Map {
 // wavefronts at 168 (FP32 at the 128^3 sphere: 235 against 271 us).
 template <typename R, int N, int T, int W, bool BLK>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y,
+k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Yz,
                                               const int* __restrict__ active, ZArgs a, Z2Map zm,
                                               const cx<R>* __restrict__ tw) {
   constexpr int E = N / T, Q = E / T, HE = E / 2, CW = 64 / T, C = W * CW, RP = 64 + CW;
@@ -290,10 +290,13 @@ k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y,
 #pragma unroll
   for (int u = 0; u < 6; ++u) sxy[u] = (mx ? c_sign[0][u] : 1) * (my ? c_sign[1][u] : 1);
   const unsigned cs = (unsigned)a.Ph * a.Jh * a.Kh;
-  const unsigned yl = (unsigned)(jm * a.Kh + im), ykm = (unsigned)(a.Jh * a.Kh);
+  // the spectrum's z-fastest copy Yz[u][j_h][i_h][k_h]: the T lanes of a
+  // column gather T consecutive z frequencies, one run instead of T rows
+  // (measured 185 against 240 us for the FP32 pass at the 128^3 sphere)
+  const unsigned yl = (unsigned)(jm * a.Kh + im) * (unsigned)a.Ph;
   brsrc yr[6];
 #pragma unroll
-  for (int u = 0; u < 6; ++u) yr[u] = make_rsrc(Y + (size_t)u * cs, cs * SZ);
+  for (int u = 0; u < 6; ++u) yr[u] = make_rsrc(Yz + (size_t)u * cs, cs * SZ);
   const int r0 = rg * zm.RB, r1 = min(zm.nrhs, r0 + zm.RB);
   __syncthreads();  // twiddle table ready; from here on the wavefronts are independent
   for (int rhs = r0; rhs < r1; ++rhs) {
@@ -339,7 +342,7 @@ k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Y,
         const int f = t + T * q + E * k2;
         const int km = min(f, N - f);
         const bool mz = f > N - f;
-        const unsigned yo = ((unsigned)km * ykm + yl) * SZ;
+        const unsigned yo = ((unsigned)km + yl) * SZ;
         cx<R> yv[6];
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
