@@ -302,8 +302,8 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * schedule's y pass allows it (schedules 0, 1, 3); 0 keeps the separate step
  * kernel.  Same recurrences either way. */
 /* DDA_OPT_RHS_PER_BLOCK (0..8): right-hand sides each block of the two-level
- * z pass (schedule 5) runs in turn, sharing its spectrum tile; 0 (default)
- * picks it from the launch size. */
+ * z pass (schedules 5 and 6) runs in turn, sharing its spectrum tile; 0
+ * (default) is one. */
 enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4,
        DDA_OPT_RHS_PER_BLOCK = 5 };
 int dda_target_set_option(dda_target *t, int option, int value);

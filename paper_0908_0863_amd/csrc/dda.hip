@@ -110,12 +110,13 @@ static bool fast_size(int n) {
   }
 }
 
-// lengths with a two-level z pass (fft_reg.hpp)
+// lengths with a two-level z pass (fft_reg.hpp) in precision R
+template <typename R = float>
 static bool z2_size(int n) {
   switch (n) {
 #define DDA_CASE(N) \
   case N:           \
-    return Z2Shape<float, N>::ok;
+    return Z2Shape<R, N>::ok;
     DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
     default:
@@ -300,11 +301,14 @@ struct dda_target {
   std::vector<int> h_active;
   int matvecs = 0;
   // captured inner iteration
-  hipGraphExec_t graph_exec = nullptr;
-  std::vector<uintptr_t> graph_key;
+  // captured inner iteration, one per vector precision (FP64 index 0, FP32 1):
+  // a batched mixed solve can run both kinds of inner solve in one step
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  std::vector<uintptr_t> graph_key[2];
   hipStream_t cap_stream = nullptr;
   ~dda_target() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    for (hipGraphExec_t g : graph_exec)
+      if (g) (void)hipGraphExecDestroy(g);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
@@ -632,11 +636,11 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   t->p32.vec_cap = t->p32.vec_slots = 0;
   t->p64.vec_cap = t->p64.vec_slots = 0;
   t->p32.vec_nd = t->p64.vec_nd = 0;
-  if (t->graph_exec) {
-    (void)hipGraphExecDestroy(t->graph_exec);
-    t->graph_exec = nullptr;
+  for (int g = 0; g < 2; ++g) {
+    if (t->graph_exec[g]) (void)hipGraphExecDestroy(t->graph_exec[g]);
+    t->graph_exec[g] = nullptr;
+    t->graph_key[g].clear();
   }
-  t->graph_key.clear();
   t->solve_S.clear();
   {
     int lo[3] = {t->K, t->J, t->P}, hi[3] = {-1, -1, -1};
@@ -926,7 +930,7 @@ static int ensure_scratch(dda_target* t, int nrhs) {
 template <typename R>
 static void matvec_ws_bytes(const dda_target* t, int nrhs, size_t& g1, size_t& g2) {
   size_t e2 = (size_t)t->P * t->Jpp * t->Kpp;
-  if (z2_size(t->Ppp)) {
+  if (z2_size<R>(t->Ppp)) {
     const int C = z2_cols<R>(t->Ppp);
     e2 = std::max(e2, (size_t)t->P * t->Jpp * ((t->Kpp + C - 1) / C) * C);
   }
@@ -1041,8 +1045,12 @@ struct FastLaunch {
     dim3 grid(32 * ((zm.ngroups + 7) / 8));
     hipLaunchKernelGGL((k_fast_zsplit<R, N, TX>), grid, dim3(3 * FastPlan<N>::T * TX), 0, st, G2, Y, act, za, zm, tw);
   }
-  // two-level z pass: right-hand sides per block chosen so that a launch
-  // still has some 2048 groups of four mirror tiles
+  // two-level z pass: one right-hand side per block unless the target asks
+  // for more (DDA_OPT_RHS_PER_BLOCK).  Several per block reuse the spectrum
+  // tile from the caches (8% faster on a full 128-RHS batch of the 96^3
+  // ellipsoid), but inside a solve the active right-hand sides thin out and a
+  // block then runs its few active ones in turn where one block each would
+  // run side by side (the batched solve took 21.5 s instead of 16.7 s).
   // x passes to and from the tile-blocked layout of the two-level z pass
   template <int N, bool INV>
   static void xb(const dda_target* t, int nrhs, int C, hipStream_t st, const cx<R>* in, cx<R>* out, const int* act,
@@ -1066,7 +1074,7 @@ struct FastLaunch {
       zm.ngy = za.Jpp / 2 + 1;
       const int per = zm.ngx * zm.ngy;
       zm.nrhs = nrhs;
-      zm.RB = rb > 0 ? std::min(rb, nrhs) : std::max(1, std::min(8, (int)(((long)nrhs * per) / 2048)));
+      zm.RB = rb > 0 ? std::min(rb, nrhs) : 1;
       zm.ngroups = ((nrhs + zm.RB - 1) / zm.RB) * per;
       dim3 grid(32 * ((zm.ngroups + 7) / 8));
       hipLaunchKernelGGL((k_z2<R, N, T, W, BLK>), grid, dim3(64 * W), 0, st, G2, Y, act, za, zm, tw);
@@ -1428,7 +1436,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     za.Kh = t->Kh;
     za.Jh = t->Jh;
     za.Ph = t->Ph;
-    if (sched == 5 && z2_size(Ppp)) {
+    if (sched == 5 && z2_size<R>(Ppp)) {
       switch (Ppp) {
 #define DDA_CASE(N)                                                                                      \
   case N:                                                                                                \
@@ -1529,7 +1537,12 @@ static std::string tune_key(const dda_target* t, int nrhs) {
 template <typename R>
 static int schedule_of(const dda_target* t, int nrhs) {
   if (t->sched_override >= 0) return t->sched_override;
-  if (t->forced_sched >= 0) return t->forced_sched;
+  if (t->forced_sched >= 0) {
+    // the two-level z pass is not built for every length in FP64: the
+    // five plain passes stand in for it there
+    if ((t->forced_sched == 5 || t->forced_sched == 6) && !z2_size<R>(t->Ppp)) return 0;
+    return t->forced_sched;
+  }
   const std::string key = tune_key<R>(t, nrhs);
   std::lock_guard<std::mutex> g(t->lib->tune_mu);
   auto it = t->lib->tuned.find(key);
@@ -1550,8 +1563,8 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   std::vector<int> cand = {0};
   if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
   if (fast_size(t->Ppp)) cand.push_back(3);
-  if (z2_size(t->Ppp)) cand.push_back(5);
-  if (z2_size(t->Ppp) && fast_size(t->Kpp)) cand.push_back(6);
+  if (z2_size<R>(t->Ppp)) cand.push_back(5);
+  if (z2_size<R>(t->Ppp) && fast_size(t->Kpp)) cand.push_back(6);
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {
@@ -2248,10 +2261,12 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
                                   (uintptr_t)t->mbits.p,
                                   (uintptr_t)B.mt0.p,
                                   (uintptr_t)B.mt1.p};
-    if (!t->graph_exec || t->graph_key != key) {
-      if (t->graph_exec) {
-        (void)hipGraphExecDestroy(t->graph_exec);
-        t->graph_exec = nullptr;
+    hipGraphExec_t& gexec = t->graph_exec[sizeof(R) == 4 ? 1 : 0];
+    std::vector<uintptr_t>& gkey = t->graph_key[sizeof(R) == 4 ? 1 : 0];
+    if (!gexec || gkey != key) {
+      if (gexec) {
+        (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
       }
       if (!t->cap_stream) HIPCHK(hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking));
       const int mv_save = t->matvecs;
@@ -2266,16 +2281,16 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
         return rc;
       }
       if (ec != hipSuccess) return fail(DDA_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
-      ec = hipGraphInstantiate(&t->graph_exec, graph, nullptr, nullptr, 0);
+      ec = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (ec != hipSuccess) {
-        t->graph_exec = nullptr;
+        gexec = nullptr;
         return fail(DDA_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ec));
       }
-      t->graph_key = key;
+      gkey = key;
     }
     while (it + check <= max_iter) {
-      HIPCHK(hipGraphLaunch(t->graph_exec, st));
+      HIPCHK(hipGraphLaunch(gexec, st));
       it += check;
       t->matvecs += check * mv_per_iter;
       CHK(read_active(t, nrhs, st, n_active));
@@ -2379,7 +2394,12 @@ static void orientation_S(dda_target* t, int nrhs, const double* khat, const dou
 
 // Refinement loop around the inner solves: P += D^{-1/2} u |r| where
 // (D^{-1/2} A D^{-1/2}) u = D^{-1/2} r / |r|, until the FP64 true residual
-// meets tol.  Inner precision FP64 (tol_in = tol) or FP32 (tol_in = inner_tol).
+// meets tol.  Inner precision FP64 (tol_in = tol) or FP32 (tol_in = inner_tol),
+// chosen per right-hand side: FP32 inner solves while they make progress; a
+// refinement step that cuts a right-hand side's true residual by less than 4x
+// (FP32 Krylov recurrences can stagnate, e.g. QMR_sym on point sources) moves
+// that right-hand side, and only it, to FP64 inner solves.  A step runs the
+// FP32 group and the FP64 group as two masked multi-RHS inner solves.
 static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c64* E, c64* Pv, dda_solve_info* info,
                       hipStream_t st) {
   CHK(ensure_outer(t, nrhs));
@@ -2387,13 +2407,9 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   c64* r64 = t->outer.as<c64>() + (size_t)nrhs * n3;
   c64* y64 = r64 + (size_t)nrhs * n3;
   const bool mixed = o.precision == DDA_SOLVE_MIXED;
-  // FP32 inner solves while they make progress; a refinement step that cuts
-  // the true residual of some right-hand side by less than 4x (FP32 Krylov
-  // recurrences can stagnate, e.g. QMR_sym on point sources) switches the
-  // remaining steps to FP64 inner solves.
-  bool lo = mixed;
+  std::vector<int> hi(nrhs, mixed ? 0 : 1);  // 1: FP64 inner solves for this right-hand side
   const int nslots = solver_slots(o.solver, solver_param(o));
-  if (lo) CHK(ensure_solver_ws<float>(t, nrhs, nslots));
+  if (mixed) CHK(ensure_solver_ws<float>(t, nrhs, nslots));
   else CHK(ensure_solver_ws<double>(t, nrhs, nslots));
   const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
   const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
@@ -2408,14 +2424,21 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   for (int q = 0; q < nrhs; ++q)
     if (!std::isfinite(en2[q])) return fail(DDA_EINVAL, "dda_solve: right-hand side %d is not finite", q);
   std::vector<int> iters(nrhs, 0), outer(nrhs, 0), done(nrhs, 0);
-  InnerResult ir;
-  ir.iters.resize(nrhs);
-  ir.converged.resize(nrhs);
-  ir.breakdown.resize(nrhs);
-  ir.rnorm2.resize(nrhs);
-  ir.bnorm2.resize(nrhs);
-  std::vector<int> hact(nrhs);
-  std::vector<double> hsc(nrhs), htol(nrhs);
+  auto new_result = [nrhs]() {
+    InnerResult r;
+    r.iters.assign(nrhs, 0);
+    r.converged.assign(nrhs, 0);
+    r.breakdown.assign(nrhs, 0);
+    r.rnorm2.assign(nrhs, 0.0);
+    r.bnorm2.assign(nrhs, 0.0);
+    return r;
+  };
+  InnerResult ir = new_result(), irg = new_result();
+  std::vector<int> hact(nrhs), hgrp[2] = {std::vector<int>(nrhs), std::vector<int>(nrhs)};
+  std::vector<double> hsc(nrhs), hacc(nrhs), htol(nrhs);
+  const unsigned gx = (unsigned)std::min<long>((n3 + 255) / 256, 4096);
+  const c64* a0 = t->p64.a0.as<c64>();
+  const c64* a1 = t->has_a1 ? t->p64.a1.as<c64>() : nullptr;
   for (int step = 0; step < max_outer; ++step) {
     int n_left = 0;
     for (int q = 0; q < nrhs; ++q) {
@@ -2425,47 +2448,59 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       hsc[q] = rn2[q] > 0 ? 1.0 / std::sqrt(rn2[q]) : 0.0;
       // solve only as far as the outer target needs: ||r_new|| <= tol ||E|| / 2
       const double need = rn2[q] > 0 ? 0.5 * tol * std::sqrt(en2[q] / rn2[q]) : 1.0;
-      htol[q] = std::min(0.5, std::max(lo ? tol_in : tol, need));
+      htol[q] = std::min(0.5, std::max(hi[q] ? tol : tol_in, need));
     }
     if (n_left == 0) break;
-    int budget = 0;
-    for (int q = 0; q < nrhs; ++q)
-      if (hact[q]) budget = std::max(budget, max_iter - iters[q]);
-    HIPCHK(hipMemcpyAsync(t->active.p, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(t->active_outer.p, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(t->scal.p, hsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(t->tolv.p, htol.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    const unsigned gx = (unsigned)std::min<long>((n3 + 255) / 256, 4096);
-    const c64* a0 = t->p64.a0.as<c64>();
-    const c64* a1 = t->has_a1 ? t->p64.a1.as<c64>() : nullptr;
-    if (lo) {
-      hipLaunchKernelGGL((k_scale_rhs<float>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p32.vec.as<c32>(), a0, a1,
-                         t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
-      LAUNCHCHK();
-      CHK(inner_solve<float>(t, o.solver, solver_param(o), nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
-                             ir));
-    } else {
-      hipLaunchKernelGGL((k_scale_rhs<double>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p64.vec.as<c64>(), a0, a1,
-                         t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd, o.jacobi ? 1 : 0);
-      LAUNCHCHK();
-      CHK(inner_solve<double>(t, o.solver, solver_param(o), nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0, o.check_every, o.use_graph, st,
-                              ir));
+    for (int q = 0; q < nrhs; ++q) hacc[q] = std::sqrt(rn2[q]);
+    // g = 0: the FP32 group, g = 1: the FP64 group; each an inner solve over
+    // the right-hand sides of its group, then P += |r| D^{-1/2} u for them
+    for (int g = 0; g < 2; ++g) {
+      std::vector<int>& m = hgrp[g];
+      int nm = 0, budget = 0;
+      for (int q = 0; q < nrhs; ++q) {
+        m[q] = hact[q] && hi[q] == g;
+        nm += m[q];
+        if (m[q]) budget = std::max(budget, max_iter - iters[q]);
+      }
+      if (nm == 0) continue;
+      HIPCHK(hipMemcpyAsync(t->active.p, m.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      if (g == 0) {
+        hipLaunchKernelGGL((k_scale_rhs<float>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p32.vec.as<c32>(), a0, a1,
+                           t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd,
+                           o.jacobi ? 1 : 0);
+        LAUNCHCHK();
+        CHK(inner_solve<float>(t, o.solver, solver_param(o), nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0,
+                               o.check_every, o.use_graph, st, irg));
+      } else {
+        hipLaunchKernelGGL((k_scale_rhs<double>), dim3(gx, nrhs), dim3(256), 0, st, r64, t->p64.vec.as<c64>(), a0,
+                           a1, t->S.as<double>(), t->scal.as<double>(), t->active.as<int>(), (long)t->nd,
+                           o.jacobi ? 1 : 0);
+        LAUNCHCHK();
+        CHK(inner_solve<double>(t, o.solver, solver_param(o), nrhs, t->tolv.as<double>(), budget, o.jacobi ? 1 : 0,
+                                o.check_every, o.use_graph, st, irg));
+      }
+      for (int q = 0; q < nrhs; ++q)
+        if (m[q]) ir.iters[q] = irg.iters[q];
     }
-    // P += |r| D^{-1/2} u
-    for (int q = 0; q < nrhs; ++q) hsc[q] = std::sqrt(rn2[q]);
-    HIPCHK(hipMemcpyAsync(t->scal.p, hsc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    if (lo) {
+    HIPCHK(hipMemcpyAsync(t->scal.p, hacc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    for (int g = 0; g < 2; ++g) {
+      int nm = 0;
+      for (int q = 0; q < nrhs; ++q) nm += hgrp[g][q];
+      if (nm == 0) continue;
+      HIPCHK(hipMemcpyAsync(t->active_outer.p, hgrp[g].data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
       const size_t vsz = (size_t)nrhs * n3;
-      hipLaunchKernelGGL((k_accumulate<float>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p32.vec.as<c32>() + vsz, a0,
-                         a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
-                         o.jacobi ? 1 : 0);
-    } else {
-      const size_t vsz = (size_t)nrhs * n3;
-      hipLaunchKernelGGL((k_accumulate<double>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p64.vec.as<c64>() + vsz, a0,
-                         a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
-                         o.jacobi ? 1 : 0);
+      if (g == 0)
+        hipLaunchKernelGGL((k_accumulate<float>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p32.vec.as<c32>() + vsz, a0,
+                           a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
+                           o.jacobi ? 1 : 0);
+      else
+        hipLaunchKernelGGL((k_accumulate<double>), dim3(gx, nrhs), dim3(256), 0, st, Pv, t->p64.vec.as<c64>() + vsz,
+                           a0, a1, t->S.as<double>(), t->scal.as<double>(), t->active_outer.as<int>(), (long)t->nd,
+                           o.jacobi ? 1 : 0);
+      LAUNCHCHK();
     }
-    LAUNCHCHK();
     for (int q = 0; q < nrhs; ++q)
       if (hact[q]) {
         iters[q] += ir.iters[q];
@@ -2473,13 +2508,11 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       }
     const std::vector<double> prev = rn2;
     CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
-    if (lo)
-      for (int q = 0; q < nrhs; ++q)
-        if (hact[q] && rn2[q] > tol * tol * en2[q] && rn2[q] > prev[q] / 16.0) {
-          lo = false;
-          CHK(ensure_solver_ws<double>(t, nrhs, nslots));
-          break;
-        }
+    for (int q = 0; q < nrhs; ++q)
+      if (hact[q] && !hi[q] && rn2[q] > tol * tol * en2[q] && rn2[q] > prev[q] / 16.0) {
+        hi[q] = 1;
+        CHK(ensure_solver_ws<double>(t, nrhs, nslots));
+      }
   }
   bool all = true;
   for (int q = 0; q < nrhs; ++q) {

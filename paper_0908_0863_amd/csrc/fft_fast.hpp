@@ -352,6 +352,12 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RW) k_fast_x(const cx<R>* __r
   __shared__ cx<R> lds[RW * LS];
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const long row = (long)blockIdx.x * RW + rw;
+  if (active) {  // skip the block when none of the right-hand sides its rows belong to is active
+    const long r0 = (long)blockIdx.x * RW, r1 = min(r0 + RW, nrows) - 1;
+    bool any = false;
+    for (long q = r0 / rows_per_rhs; q <= r1 / rows_per_rhs && !any; ++q) any = active[q] != 0;
+    if (!any) return;
+  }
   const bool valid = row < nrows && (!active || active[row / rows_per_rhs]);
   const cx<R>* src = in + row * lin_stride;
   cx<R> v[E];

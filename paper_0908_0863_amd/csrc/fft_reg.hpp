@@ -265,6 +265,12 @@ k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Yz,
   if (mxm && xt == gx) return;
   const int jj = mym ? a.Jpp - gy : gy;
   if (mym && (gy == 0 || jj == gy)) return;
+  const int r0 = rg * zm.RB, r1 = min(zm.nrhs, r0 + zm.RB);
+  if (active) {  // a block none of whose right-hand sides is active leaves at once
+    bool any = false;
+    for (int q = r0; q < r1 && !any; ++q) any = active[q] != 0;
+    if (!any) return;
+  }
   for (int e = threadIdx.x; e < N; e += blockDim.x) tws[e] = tw[(e % T) * (e / T)];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane % CW, t = lane / CW;
@@ -297,7 +303,6 @@ k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Yz,
   brsrc yr[6];
 #pragma unroll
   for (int u = 0; u < 6; ++u) yr[u] = make_rsrc(Yz + (size_t)u * cs, cs * SZ);
-  const int r0 = rg * zm.RB, r1 = min(zm.nrhs, r0 + zm.RB);
   __syncthreads();  // twiddle table ready; from here on the wavefronts are independent
   for (int rhs = r0; rhs < r1; ++rhs) {
     if (active && !active[rhs]) continue;
@@ -398,7 +403,8 @@ __global__ void __launch_bounds__(FastPlan<N>::T* RW) k_xb(const cx<R>* __restri
   __shared__ cx<R> lds[RW * LS];
   const int t = threadIdx.x % T, rw = threadIdx.x / T;
   const int rc = blockIdx.z, jj = blockIdx.y, k = blockIdx.x * RW + rw;
-  const bool valid = k < P && (!active || active[rc / 3]);
+  if (active && !active[rc / 3]) return;  // uniform over the block
+  const bool valid = k < P;
   const int cm = (1 << lc) - 1;
   const long g1row = (((long)rc * P + k) * Jpp + jj) * K;
   const long brow = ((long)rc * Jpp + jj) * NT * (long)P * (cm + 1) + (long)k * (cm + 1);
@@ -425,10 +431,13 @@ __global__ void __launch_bounds__(FastPlan<N>::T* RW) k_xb(const cx<R>* __restri
 
 // (T, W) of the two-level z pass per length: E = N/T a multiple of T; W
 // wavefronts per block, C = W 64/T columns per tile
+// (FP64 with E = 24 is left out: its 16-byte values make the exchange areas
+// of a block 110 KB at N = 192, one wavefront per SIMD.)
 template <typename R, int N>
 struct Z2Shape {
-  static constexpr int T = N == 16 ? 2 : N == 24 ? 2 : N == 32 ? 4 : N == 48 ? 4 : N == 64 ? 8 : N == 96 ? 4
-                           : N == 128 ? 8 : N == 192 ? 8 : N == 256 ? 16 : 0;
+  static constexpr int T0 = N == 16 ? 2 : N == 24 ? 2 : N == 32 ? 4 : N == 48 ? 4 : N == 64 ? 8 : N == 96 ? 4
+                            : N == 128 ? 8 : N == 192 ? 8 : N == 256 ? 16 : 0;
+  static constexpr int T = (sizeof(R) == 8 && T0 > 0 && N / T0 > 16) ? 0 : T0;
   static constexpr bool ok = T > 0;
   static constexpr int W = 4;
   static constexpr int C = ok ? W * 64 / T : 1;
