@@ -304,8 +304,15 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
 /* DDA_OPT_RHS_PER_BLOCK (0..8): right-hand sides each block of the two-level
  * z pass (schedules 5 and 6) runs in turn, sharing its spectrum tile; 0
  * (default) is one. */
+/* DDA_OPT_Y_TILE (-1, the default, or 0..2): the y passes of the five-pass
+ * schedules take 2^value times their default number of adjacent x positions
+ * per block (longer contiguous runs of the y-transformed array, up to 1024
+ * threads and 64 KB of LDS per block; a precision without that variant
+ * takes its widest); -1 leaves it to the autotuner, which times the wider
+ * variants after choosing the schedule.  DDA_EINVAL if even FP32 has no such
+ * variant for the lattice. */
 enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4,
-       DDA_OPT_RHS_PER_BLOCK = 5 };
+       DDA_OPT_RHS_PER_BLOCK = 5, DDA_OPT_Y_TILE = 6 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:
@@ -317,9 +324,11 @@ int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
 /* Copy the spectrum [6][P_h][J_h][K_h] (complex128 or complex64) to out_dev. */
 int dda_get_spectrum(dda_target *t, int precision, void *out_dev, void *hip_stream);
 
-/* Kernel timing for measurement: while enabled, every launch of a
- * matrix-vector pass, and every whole product, is bracketed by HIP events on
- * its own stream (and the solver does not capture graphs).  dda_profile_read
+/* Kernel timing for measurement: while enabled (enable = 1), every launch of
+ * a matrix-vector pass, and every whole product, is bracketed by HIP events on
+ * its own stream (and the solver does not capture graphs); enable = 2 records
+ * the whole products only, with no events between their passes; 0 turns it
+ * off, any other value is DDA_EINVAL.  dda_profile_read
  * fills ms[2*DDA_PROF_SLOTS] (summed milliseconds) and
  * count[2*DDA_PROF_SLOTS] (launches) for the slots y-forward, x-forward,
  * z (forward, product, inverse), x-inverse, y-inverse, fused xy-forward,

@@ -116,7 +116,7 @@ static bool z2_size(int n) {
   switch (n) {
 #define DDA_CASE(N) \
   case N:           \
-    return Z2Shape<R, N>::ok;
+    return Z2Shape<R, N, true>::ok;
     DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
     default:
@@ -124,13 +124,13 @@ static bool z2_size(int n) {
   }
 }
 
-// columns per tile of the two-level z pass (and of the blocked layout)
+// columns per tile of the tile-blocked layout (and of its two-level z pass)
 template <typename R>
 static int z2_cols(int n) {
   switch (n) {
 #define DDA_CASE(N) \
   case N:           \
-    return Z2Shape<R, N>::C;
+    return Z2Shape<R, N, true>::C;
     DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
     default:
@@ -196,7 +196,7 @@ struct dda_lib {
   std::map<std::string, int> tuned;  // schedule per (lattice, padding, nrhs, precision)
   std::mutex tune_mu;                // guards `tuned` and the tune file (batch workers)
   std::vector<hipStream_t> workers;  // streams of dda_batch_solve's workers
-  bool prof = false;
+  int prof = 0;  // 0 off, 1 every pass and product, 2 whole products only
   std::vector<hipEvent_t> ev_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (pass, start, stop)
   double prof_ms[PASS_COUNT] = {0};
@@ -220,7 +220,8 @@ struct PassTimer {
   hipStream_t st;
   bool on;
   hipEvent_t a = nullptr, b = nullptr;
-  PassTimer(dda_lib* l_, int p, hipStream_t s, bool enabled = true) : l(l_), pass(p), st(s), on(enabled && l_->prof) {
+  PassTimer(dda_lib* l_, int p, hipStream_t s, bool enabled = true)
+      : l(l_), pass(p), st(s), on(enabled && (l_->prof == 1 || (l_->prof == 2 && p % PASS_PER_PREC == PASS_MATVEC))) {
     if (on) {
       a = take_event(l);
       b = take_event(l);
@@ -274,6 +275,7 @@ struct dda_target {
   PrecBufs<float> p32;
   bool spec_ready = false;
   int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
+  int forced_ylog = -1;      // -1: tuned; L >= 0: y tile 2^L times the default
   int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
   int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
   int fuse_qmr = 1;          // QMR_sym step fused into the y-forward pass where possible
@@ -394,13 +396,17 @@ static int launch_strided_mirror(const cx<R>* in, cx<R>* out, StridedArgs a, int
 // ----------------------------------------------------------------------------
 // C ABI
 // ----------------------------------------------------------------------------
+template <typename R>
+static int ylog_max(const dda_target* t);
+
 extern "C" {
 
 const char* dda_last_error(void) { return g_err.c_str(); }
 
 int dda_profile_enable(dda_lib* lib, int enable) {
   if (!lib) return fail(DDA_EINVAL, "dda_profile_enable: NULL lib");
-  lib->prof = enable != 0;
+  if (enable < 0 || enable > 2) return fail(DDA_EINVAL, "dda_profile_enable: enable must be 0, 1 or 2");
+  lib->prof = enable;
   return DDA_OK;
 }
 
@@ -565,6 +571,12 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_FUSE_QMR_STEP:
       if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: fuse %d", value);
       t->fuse_qmr = value;
+      return DDA_OK;
+    case DDA_OPT_Y_TILE:
+      if (value < -1 || value > 2) return fail(DDA_EINVAL, "dda_target_set_option: y tile variant %d", value);
+      if (value > 0 && value > ylog_max<float>(t))
+        return fail(DDA_EINVAL, "dda_target_set_option: no y tile variant %d for this lattice", value);
+      t->forced_ylog = value;
       return DDA_OK;
     case DDA_OPT_RHS_PER_BLOCK:
       if (value < 0 || value > 8) return fail(DDA_EINVAL, "dda_target_set_option: right-hand sides per block %d", value);
@@ -964,6 +976,17 @@ constexpr int fast_txz() {
   while (tx > 2 && 3 * N * tx * (int)sizeof(cx<R>) > 48 * 1024) tx /= 2;
   return tx;
 }
+// y-pass tiles wider than fast_tx: 2^L times as many x positions per block,
+// up to 1024 threads and 64 KB of LDS (longer contiguous runs in the strided
+// rows of the y-transformed array, fewer blocks)
+template <typename R, int N>
+constexpr int ytx_max_log() {
+  int L = 0;
+  while (L < 2 && FastPlan<N>::T * (fast_tx<N>() << (L + 1)) <= 1024 &&
+         N * (fast_tx<N>() << (L + 1)) * (int)sizeof(cx<R>) <= 64 * 1024)
+    ++L;
+  return L;
+}
 template <int N>
 constexpr int fast_rw() {
   constexpr int T = FastPlan<N>::T;
@@ -997,11 +1020,16 @@ struct FastLaunch {
     dim3 grid(32 * ((zm.ngroups + 7) / 8));
     hipLaunchKernelGGL((k_zline<R, N, RL>), grid, dim3(FastPlan<N>::T * RL), 0, st, G2t, Yz, act, za, zm, tw);
   }
+  // y tile of variant ylog (clamped to the widest that exists)
   template <int N>
-  static void yfwd(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
-                   const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
-                   const QmrFuse<R>* qf) {
-    constexpr int TX = fast_tx<N>();
+  static int ytx(int ylog) {
+    return fast_tx<N>() << std::min(std::max(ylog, 0), ytx_max_log<R, N>());
+  }
+  template <int N, int L>
+  static void yfwd_L(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
+                     const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
+                     const QmrFuse<R>* qf) {
+    constexpr int TX = fast_tx<N>() << L;
     dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
     if (qf)
       hipLaunchKernelGGL((k_fast_yfwd<R, N, TX, true>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0, a1,
@@ -1010,20 +1038,44 @@ struct FastLaunch {
       hipLaunchKernelGGL((k_fast_yfwd<R, N, TX, false>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0,
                          a1, S, act, va, tw, QmrFuse<R>{});
   }
+  template <int N>
+  static void yfwd(int ylog, dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
+                   const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
+                   const QmrFuse<R>* qf) {
+    constexpr int LM = ytx_max_log<R, N>();
+    const int L = std::min(std::max(ylog, 0), LM);
+    if constexpr (LM >= 2)
+      if (L == 2) return yfwd_L<N, 2>(g0, st, x, G1, map, a0, a1, S, act, va, tw, qf);
+    if constexpr (LM >= 1)
+      if (L == 1) return yfwd_L<N, 1>(g0, st, x, G1, map, a0, a1, S, act, va, tw, qf);
+    yfwd_L<N, 0>(g0, st, x, G1, map, a0, a1, S, act, va, tw, qf);
+  }
   // y-forward blocks per right-hand side (3 components x P planes x x tiles)
   template <int N>
-  static int yfwd_blocks(const dda_target* t) {
-    constexpr int TX = fast_tx<N>();
+  static int yfwd_blocks(const dda_target* t, int ylog) {
+    const int TX = ytx<N>(ylog);
     return 3 * t->P * ((t->K + TX - 1) / TX);
   }
-  template <int N>
-  static void yinv(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
-                   const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
-                   DotArgs dot) {
-    constexpr int TX = fast_tx<N>();
+  template <int N, int L>
+  static void yinv_L(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
+                     const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va,
+                     const cx<R>* tw, DotArgs dot) {
+    constexpr int TX = fast_tx<N>() << L;
     dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
     hipLaunchKernelGGL((k_fast_yinv<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G1, x, y, map, a0, a1, S,
                        act, va, tw, dot);
+  }
+  template <int N>
+  static void yinv(int ylog, dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
+                   const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
+                   DotArgs dot) {
+    constexpr int LM = ytx_max_log<R, N>();
+    const int L = std::min(std::max(ylog, 0), LM);
+    if constexpr (LM >= 2)
+      if (L == 2) return yinv_L<N, 2>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
+    if constexpr (LM >= 1)
+      if (L == 1) return yinv_L<N, 1>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
+    yinv_L<N, 0>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
   }
   template <int N, bool INV>
   static void xpass(hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride, int lout_stride,
@@ -1052,10 +1104,21 @@ struct FastLaunch {
   // block then runs its few active ones in turn where one block each would
   // run side by side (the batched solve took 21.5 s instead of 16.7 s).
   // x passes to and from the tile-blocked layout of the two-level z pass
+  // rows per block of the x passes to and from the tile-blocked layout:
+  // enough that a block's share of a tile (RW x C values) is a run of at
+  // least 512 bytes, within 1024 threads and 64 KB of LDS
+  template <int N>
+  static constexpr int xb_rows() {
+    constexpr int C = Z2Shape<R, N, true>::C, T = FastPlan<N>::T, LS = N + N / 8 + 1;
+    int rw = fast_rw<N>();
+    while (rw * C * (int)sizeof(cx<R>) < 512 && 2 * rw * T <= 1024 && 2 * rw * LS * (int)sizeof(cx<R>) <= 65536)
+      rw *= 2;
+    return rw;
+  }
   template <int N, bool INV>
   static void xb(const dda_target* t, int nrhs, int C, hipStream_t st, const cx<R>* in, cx<R>* out, const int* act,
                  const cx<R>* tw) {
-    constexpr int RW = fast_rw<N>();
+    constexpr int RW = xb_rows<N>();
     int lc = 0;
     while ((1 << lc) < C) ++lc;
     const int NT = (t->Kpp + C - 1) / C;
@@ -1066,8 +1129,9 @@ struct FastLaunch {
   template <int N, bool BLK>
   static void z2(int nrhs, int rb, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za,
                  const cx<R>* tw) {
-    if constexpr (Z2Shape<R, N>::ok) {
-      constexpr int T = Z2Shape<R, N>::T, C = Z2Shape<R, N>::C, W = Z2Shape<R, N>::W;
+    using SH = Z2Shape<R, N, BLK>;
+    if constexpr (SH::ok) {
+      constexpr int T = SH::T, C = SH::C, W = SH::W;
       Z2Map zm;
       zm.NX = (za.Kpp + C - 1) / C;
       zm.ngx = (zm.NX + 1) / 2;
@@ -1077,7 +1141,7 @@ struct FastLaunch {
       zm.RB = rb > 0 ? std::min(rb, nrhs) : 1;
       zm.ngroups = ((nrhs + zm.RB - 1) / zm.RB) * per;
       dim3 grid(32 * ((zm.ngroups + 7) / 8));
-      hipLaunchKernelGGL((k_z2<R, N, T, W, BLK>), grid, dim3(64 * W), 0, st, G2, Y, act, za, zm, tw);
+      hipLaunchKernelGGL((k_z2<R, N, T, W, BLK, SH::WPE>), grid, dim3(64 * W), 0, st, G2, Y, act, za, zm, tw);
     }
   }
   template <int N>
@@ -1174,6 +1238,8 @@ static inline bool is_fused(int s) { return s == 2 || s == 4 || s == 8; }
 // blocks per right-hand side of the last matvec pass (fused-dot partials)
 template <typename R>
 static int schedule_of(const dda_target* t, int nrhs);
+template <typename R>
+static int ylog_of(const dda_target* t, int nrhs);
 
 template <typename R>
 static int yinv_blocks(const dda_target* t, int nrhs) {
@@ -1181,9 +1247,9 @@ static int yinv_blocks(const dda_target* t, int nrhs) {
   if (is_fused(sc)) return 3 * t->P * sc;
   int tx = 0;
   switch (t->Jpp) {
-#define DDA_CASE(N) \
-  case N:           \
-    tx = fast_tx<N>(); \
+#define DDA_CASE(N)                                           \
+  case N:                                                     \
+    tx = FastLaunch<R>::template ytx<N>(ylog_of<R>(t, nrhs)); \
     break;
     DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
@@ -1235,7 +1301,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
-  const int sched = schedule_of<R>(t, nrhs);
+  const int sched = schedule_of<R>(t, nrhs), ylog = ylog_of<R>(t, nrhs);
   const int dfwd = is_fused(sched) ? sched : 0, dinv = dfwd;
   if (dfwd && qf) return fail(DDA_EINVAL, "matvec: fused QMR step needs the register-resident y pass");
   if (dfwd) {
@@ -1296,7 +1362,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
-    FastLaunch<R>::template yfwd<N>(dim3(1, P, nrhs * 3), st, x, G1, occ_of(t), a0, a1, dS, active, va, \
+    FastLaunch<R>::template yfwd<N>(ylog, dim3(1, P, nrhs * 3), st, x, G1, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), qf);                                        \
     break;
         DDA_FAST_SIZES(DDA_CASE)
@@ -1500,7 +1566,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                             \
   case N:                                                                                                       \
-    FastLaunch<R>::template yinv<N>(dim3(1, P, nrhs * 3), st, G1, x, y, occ_of(t), a0, a1, dS, active, va, \
+    FastLaunch<R>::template yinv<N>(ylog, dim3(1, P, nrhs * 3), st, G1, x, y, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), dot);                                           \
     break;
         DDA_FAST_SIZES(DDA_CASE)
@@ -1534,20 +1600,45 @@ static std::string tune_key(const dda_target* t, int nrhs) {
   return k.str();
 }
 
+// A plan is the schedule in its low 4 bits and the y-tile variant (log2 of
+// the multiple of the default y tile) above them.
 template <typename R>
-static int schedule_of(const dda_target* t, int nrhs) {
+static int plan_of(const dda_target* t, int nrhs) {
   if (t->sched_override >= 0) return t->sched_override;
+  int v = 0;  // untuned: the strided five-pass schedule, default y tile
   if (t->forced_sched >= 0) {
     // the two-level z pass is not built for every length in FP64: the
     // five plain passes stand in for it there
-    if ((t->forced_sched == 5 || t->forced_sched == 6) && !z2_size<R>(t->Ppp)) return 0;
-    return t->forced_sched;
+    v = ((t->forced_sched == 5 || t->forced_sched == 6) && !z2_size<R>(t->Ppp)) ? 0 : t->forced_sched;
+  } else {
+    const std::string key = tune_key<R>(t, nrhs);
+    std::lock_guard<std::mutex> g(t->lib->tune_mu);
+    auto it = t->lib->tuned.find(key);
+    if (it != t->lib->tuned.end()) v = it->second;
   }
-  const std::string key = tune_key<R>(t, nrhs);
-  std::lock_guard<std::mutex> g(t->lib->tune_mu);
-  auto it = t->lib->tuned.find(key);
-  if (it != t->lib->tuned.end()) return it->second;
-  // untuned: the strided five-pass schedule
+  if (t->forced_ylog >= 0) v = (v & 15) | (t->forced_ylog << 4);
+  return v;
+}
+template <typename R>
+static int schedule_of(const dda_target* t, int nrhs) {
+  return plan_of<R>(t, nrhs) & 15;
+}
+template <typename R>
+static int ylog_of(const dda_target* t, int nrhs) {
+  return plan_of<R>(t, nrhs) >> 4;
+}
+
+// widest y-tile variant of this lattice's y length in precision R (0 where
+// the y pass is not register-resident)
+template <typename R>
+static int ylog_max(const dda_target* t) {
+  switch (t->Jpp) {
+#define DDA_CASE(N) \
+  case N:           \
+    return ytx_max_log<R, N>();
+    DDA_FAST_SIZES(DDA_CASE)
+#undef DDA_CASE
+  }
   return 0;
 }
 
@@ -1568,8 +1659,8 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {
-    const bool prof = t->lib->prof;
-    if (prof) t->lib->prof = false;  // (profiling runs single-threaded)
+    const int prof = t->lib->prof;
+    if (prof) t->lib->prof = 0;  // (profiling runs single-threaded)
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1603,8 +1694,31 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
         best_ms = best_c[ci];
         best = cand[ci];
       }
-    t->sched_override = -1;
     t->matvecs -= 11 * (int)cand.size();
+    // then wider y tiles for the chosen schedule, the same way
+    if (!is_fused(best) && t->forced_ylog < 0) {
+      const int base = best;
+      for (int L = 1; L <= ylog_max<R>(t) && rc == DDA_OK; ++L) {
+        t->sched_override = base | (L << 4);
+        float bl = 1e30f;
+        for (int w = 0; w < 2 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+        for (int round = 0; round < 3 && rc == DDA_OK; ++round) {
+          (void)hipEventRecord(e0, st);
+          for (int w = 0; w < 3 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+          (void)hipEventRecord(e1, st);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          bl = std::min(bl, ms);
+        }
+        t->matvecs -= 11;
+        if (bl < 0.97f * best_ms) {
+          best_ms = bl;
+          best = base | (L << 4);
+        }
+      }
+    }
+    t->sched_override = -1;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (prof) t->lib->prof = prof;
@@ -1780,7 +1894,7 @@ static int qmr_fused_blocks(dda_target* t, int nrhs) {
   switch (t->Jpp) {
 #define DDA_CASE(N) \
   case N:           \
-    return FastLaunch<R>::template yfwd_blocks<N>(t);
+    return FastLaunch<R>::template yfwd_blocks<N>(t, ylog_of<R>(t, nrhs));
     DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
   }

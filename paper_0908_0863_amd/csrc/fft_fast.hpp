@@ -859,6 +859,12 @@ constexpr int zline_rows() {
 // z-fastest spectrum with Table 1 signs), in place on G2t.  Blocks take RL
 // consecutive lines i'' at one j''; mirror quadruples of line tiles share
 // spectrum rows and are dealt to one XCD in consecutive slots.
+// components per 16-byte record of the z-fastest spectrum copy (k_spec_zfast)
+template <typename R>
+__host__ __device__ constexpr int yz_group() {
+  return 16 / (int)sizeof(cx<R>);
+}
+
 template <typename R, int N, int RL>
 __global__ void __launch_bounds__(FastPlan<N>::T * RL) k_zline(cx<R>* __restrict__ G2t, const cx<R>* __restrict__ Yz,
                                                               const int* __restrict__ active, ZArgs a, ZMap zm,
@@ -903,8 +909,8 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RL) k_zline(cx<R>* __restrict
     int sxy[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) sxy[c] = (mx ? c_sign[0][c] : 1) * (my ? c_sign[1][c] : 1);
-    const long cs = (long)a.Ph * a.Jh * a.Kh;
-    const cx<R>* yrow = Yz + ((long)jm * a.Kh + im) * a.Ph;
+    constexpr int V = yz_group<R>();
+    const cx<R>* yrow = Yz + ((long)jm * a.Kh + im) * a.Ph * 6;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int e = t + T * m;
@@ -914,7 +920,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RL) k_zline(cx<R>* __restrict
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         const int sg = sxy[c] * (mz ? c_sign[2][c] : 1);
-        const cx<R> w = yrow[c * cs + km];
+        const cx<R> w = yrow[((c / V) * a.Ph + km) * V + c % V];
         yv[c] = sg < 0 ? mk(-w.x, -w.y) : w;
       }
       const cx<R> x0 = v[0][m], x1 = v[1][m], x2 = v[2][m];
@@ -936,17 +942,25 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RL) k_zline(cx<R>* __restrict
   }
 }
 
-// z-fastest copy of the spectrum: Yz[c][j][i][k] = Y[c][k][j][i]
+// z-fastest copy of the spectrum: per (j, i) column the six components in
+// groups of V = 16 / sizeof(cx<R>) (two FP32, one FP64), each group's z
+// frequencies consecutive with the group's V values together:
+// Yz[j][i][c / V][k][c % V] = Y[c][k][j][i].  One 16-byte load of the T
+// lanes of a z line then reads T consecutive records.
 template <typename R>
 __global__ void k_spec_zfast(const cx<R>* __restrict__ Y, cx<R>* __restrict__ Yz, int Kh, int Jh, int Ph) {
+  constexpr int V = yz_group<R>(), G = 6 / V;
   const long n = 6L * Ph * Jh * Kh;
   for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < n; g += (long)gridDim.x * blockDim.x) {
-    const int k = (int)(g % Ph);
-    const long r = g / Ph;
+    const int v = (int)(g % V);
+    long r = g / V;
+    const int k = (int)(r % Ph);
+    r /= Ph;
+    const int grp = (int)(r % G);
+    r /= G;
     const int i = (int)(r % Kh);
-    const long r2 = r / Kh;
-    const int j = (int)(r2 % Jh);
-    const int c = (int)(r2 / Jh);
+    const int j = (int)(r / Kh);
+    const int c = grp * V + v;
     Yz[g] = Y[(((long)c * Ph + k) * Jh + j) * Kh + i];
   }
 }

@@ -201,6 +201,31 @@ __device__ __forceinline__ void bstore(brsrc r, unsigned off, cx<R> v) {
 }
 constexpr unsigned kOutOfRange = 0x80000000u;  // byte offset past every range used here
 
+// the six spectrum components of one frequency from the z-fastest copy
+// (k_spec_zfast): 16-byte records (two FP32 components, one FP64) at
+// off + g gstride, g = 0 .. 6/V - 1 (the uniform part g gstride goes in the
+// load's scalar offset, so the six loads share one address register)
+template <typename R>
+__device__ __forceinline__ void bload6(brsrc r, unsigned off, unsigned gstride, cx<R> (&y)[6]) {
+  if constexpr (sizeof(R) == 4) {
+    // the loaded vector is bit-cast whole (element access on it compiled to
+    // a one-dword load broadcast to all four)
+    struct Pair {
+      cx<float> a, b;
+    };
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+      const Pair q = __builtin_bit_cast(Pair, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)(h * gstride), 0));
+      y[2 * h] = q.a;
+      y[2 * h + 1] = q.b;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+      y[u] = __builtin_bit_cast(cx<R>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)(u * gstride), 0));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // z pass with the spectral product on the two-level transform (Sec. 3 z lines;
 // Eqs. Q0-Q2 with the mirrored octant and Table 1 signs), in place on G2.
@@ -239,11 +264,12 @@ struct Z2Map {
 // LDS exchange area of one wavefront: element (k1, s, c) at k1 RP + s CW + c.
 // The pitch RP = 64 + CW puts the CW-lane groups of a read (one k1 each) on
 // consecutive bank ranges, so neither the writes nor the reads conflict.
-// Two wavefronts per SIMD: with up to 256 registers the compiler keeps more
-// of the spectrum gathers in flight, which measured faster than three
-// wavefronts at 168 (FP32 at the 128^3 sphere: 235 against 271 us).
-template <typename R, int N, int T, int W, bool BLK>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// WPE wavefronts per SIMD (Z2Shape): two leave up to 256 registers, so more
+// of the spectrum gathers stay in flight, which measured faster than three
+// at 168 for four-wavefront blocks (FP32 at the 128^3 sphere: 235 against
+// 271 us, before the spectrum components were interleaved).
+template <typename R, int N, int T, int W, bool BLK, int WPE>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Yz,
                                               const int* __restrict__ active, ZArgs a, Z2Map zm,
                                               const cx<R>* __restrict__ tw) {
@@ -296,13 +322,13 @@ k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Yz,
 #pragma unroll
   for (int u = 0; u < 6; ++u) sxy[u] = (mx ? c_sign[0][u] : 1) * (my ? c_sign[1][u] : 1);
   const unsigned cs = (unsigned)a.Ph * a.Jh * a.Kh;
-  // the spectrum's z-fastest copy Yz[u][j_h][i_h][k_h]: the T lanes of a
-  // column gather T consecutive z frequencies, one run instead of T rows
-  // (measured 185 against 240 us for the FP32 pass at the 128^3 sphere)
-  const unsigned yl = (unsigned)(jm * a.Kh + im) * (unsigned)a.Ph;
-  brsrc yr[6];
-#pragma unroll
-  for (int u = 0; u < 6; ++u) yr[u] = make_rsrc(Yz + (size_t)u * cs, cs * SZ);
+  // the spectrum's z-fastest copy (k_spec_zfast): the T lanes of a column
+  // gather T consecutive z frequencies, one run instead of T rows (measured
+  // 185 against 240 us for the FP32 pass at the 128^3 sphere), and FP32
+  // takes two components per 16-byte load
+  const unsigned yl = (unsigned)(jm * a.Kh + im) * (unsigned)a.Ph * 6 * SZ;
+  const unsigned ygs = (unsigned)a.Ph * 16;  // one component group's run
+  const brsrc yr = make_rsrc(Yz, 6 * cs * SZ);
   __syncthreads();  // twiddle table ready; from here on the wavefronts are independent
   for (int rhs = r0; rhs < r1; ++rhs) {
     if (active && !active[rhs]) continue;
@@ -347,13 +373,12 @@ k_z2(cx<R>* __restrict__ G2, const cx<R>* __restrict__ Yz,
         const int f = t + T * q + E * k2;
         const int km = min(f, N - f);
         const bool mz = f > N - f;
-        const unsigned yo = ((unsigned)km + yl) * SZ;
         cx<R> yv[6];
+        bload6<R>(yr, yl + (unsigned)km * 16, ygs, yv);
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
-          const cx<R> w = bload<R>(yr[u], yo);
           const int sg = sxy[u] * (mz ? c_sign[2][u] : 1);
-          yv[u] = sg < 0 ? mk(-w.x, -w.y) : w;
+          if (sg < 0) yv[u] = mk(-yv[u].x, -yv[u].y);
         }
         const int p = q * T + k2;
         const cx<R> x0 = v[0][p], x1 = v[1][p], x2 = v[2][p];
@@ -429,17 +454,24 @@ __global__ void __launch_bounds__(FastPlan<N>::T* RW) k_xb(const cx<R>* __restri
   }
 }
 
-// (T, W) of the two-level z pass per length: E = N/T a multiple of T; W
-// wavefronts per block, C = W 64/T columns per tile
+// (T, W, WPE) of the two-level z pass per length and layout: E = N/T a
+// multiple of T; W wavefronts per block, C = W 64/T columns per tile, WPE
+// wavefronts per SIMD.  FP32 on the tile-blocked layout with E <= 16 runs one
+// wavefront per block at three per SIMD (the 96 data registers and the
+// spectrum gathers fit 168): 146 against 168 us for four wavefronts at two per
+// SIMD at the 128^3 sphere.  The strided layout keeps four (its rows are runs
+// of C values: 220 us with two wavefronts, 276 with one).
 // (FP64 with E = 24 is left out: its 16-byte values make the exchange areas
 // of a block 110 KB at N = 192, one wavefront per SIMD.)
-template <typename R, int N>
+template <typename R, int N, bool BLK>
 struct Z2Shape {
   static constexpr int T0 = N == 16 ? 2 : N == 24 ? 2 : N == 32 ? 4 : N == 48 ? 4 : N == 64 ? 8 : N == 96 ? 4
                             : N == 128 ? 8 : N == 192 ? 8 : N == 256 ? 16 : 0;
   static constexpr int T = (sizeof(R) == 8 && T0 > 0 && N / T0 > 16) ? 0 : T0;
   static constexpr bool ok = T > 0;
-  static constexpr int W = 4;
+  static constexpr bool narrow = BLK && sizeof(R) == 4 && ok && N / T <= 16;
+  static constexpr int W = narrow ? 1 : 4;
+  static constexpr int WPE = narrow ? 3 : 2;
   static constexpr int C = ok ? W * 64 / T : 1;
 };
 

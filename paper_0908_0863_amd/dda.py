@@ -76,6 +76,7 @@ EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "
 PASS_NAMES = ["y_forward", "x_forward", "z_product", "x_inverse", "y_inverse", "xy_forward", "xy_inverse", "matvec"]
 DDA_PROF_SLOTS = len(PASS_NAMES)
 DDA_OPT_SCHEDULE, DDA_OPT_INJECT_BREAKDOWN, DDA_OPT_CANARY, DDA_OPT_FUSE_QMR_STEP, DDA_OPT_RHS_PER_BLOCK = 1, 2, 3, 4, 5
+DDA_OPT_Y_TILE = 6
 
 _lib = None
 
@@ -177,8 +178,10 @@ class Library:
             load().dda_close(self.h)
             self.h = None
 
-    def profile(self, enable: bool = True):
-        _check(load().dda_profile_enable(self.h, int(bool(enable))))
+    def profile(self, enable=True):
+        """True/1: time every pass and every whole product; 2: whole products
+        only (no events between the passes); False/0: off."""
+        _check(load().dda_profile_enable(self.h, int(enable)))
 
     def profile_reset(self):
         _check(load().dda_profile_reset(self.h))

@@ -499,7 +499,7 @@ def test_direct_polarizability_matvec_and_solve(lib):
 
 def test_profiling_counts_and_tune_file(tmp_path):
     """dda_profile_*: every pass of a product is timed once per launch in its
-    precision's slot, reset clears the record; dda_open's tune file records
+    precision's slot (level 2: only the whole product), reset clears the record; dda_open's tune file records
     the autotuner's choice and a second library reads it back."""
     from paper_0908_0863_amd import dda
     path = str(tmp_path / "tune.txt")
@@ -526,8 +526,21 @@ def test_profiling_counts_and_tune_file(tmp_path):
         assert n == 3 and ms > 0.0, (p, ms, n)
         assert rec[(p, "fp32")][1] == 0
     assert rec[("xy_forward", "fp64")][1] == 0
+    assert rec[("matvec", "fp64")][1] == 3
     lib1.profile_reset()
     assert all(n == 0 for _, n in lib1.profile_read().values())
+    # level 2: the whole products only
+    lib1.profile(2)
+    for _ in range(2):
+        t.matvec(x)
+    rec = lib1.profile_read()
+    lib1.profile(False)
+    assert rec[("matvec", "fp64")][1] == 2 and rec[("matvec", "fp64")][0] > 0.0
+    assert all(n == 0 for (p, _), (_, n) in rec.items() if p != "matvec")
+    lib1.profile_reset()
+    with pytest.raises(dda.DDAError) as e:
+        lib1.profile(3)
+    assert e.value.code == dda.DDA_EINVAL
     # a second library opened on the same file uses the recorded choice
     lib2 = dda.Library(0, tune_cache=path)
     t2 = dda.Target(lib2, 16, 16, 16, w["kd"])
