@@ -323,6 +323,47 @@ def test_matvec_two_level_z_pass(lib, shape, rb, sched):
         _close(y32[r], yo, 2e-6, (shape, r))
 
 
+@pytest.mark.parametrize("ylog", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 16, 5), (13, 24, 7), (5, 12, 9)])
+def test_y_tile_variants(lib, shape, ylog):
+    """DDA_OPT_Y_TILE: the y passes with 2^ylog times the default tile
+    (ragged last tiles where K is not a multiple of it) against the dense
+    oracle element by element in FP64 and FP32; a QMR_sym solve whose step
+    is fused into the widened y-forward pass (its partial counts follow the
+    tile) against the oracle's LU.  A width FP32 lacks is DDA_EINVAL."""
+    from paper_0908_0863_amd import dda
+    K, J, P = shape
+    occ = np.ones((P, J, K), np.uint8)  # a filled lattice keeps the QMR step fused
+    kd, eps = 0.37, 1.9 + 0.08j
+    t, nd = _target(lib, occ, kd, eps)
+    t.set_option(dda.DDA_OPT_SCHEDULE, 0)
+    try:
+        t.set_option(dda.DDA_OPT_Y_TILE, ylog)
+    except dda.DDAError as e:
+        assert e.code == dda.DDA_EINVAL and ylog > 0
+        pytest.skip(f"no y tile variant {ylog} for {shape}")
+    sites = ora.sites_of(occ)
+    x = inputs.complex_gaussian(71, (2, 3, nd))
+    S = [0.0, 0.2]
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=True).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=True).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", S[r])
+        s = 1.0 / np.sqrt(ainv)
+        yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
+        _close(y[r], yo, 1e-12, (shape, ylog, r))
+        _close(y32[r], yo, 2e-6, (shape, ylog, r))
+    if nd <= 2000:
+        khat = np.array([[0.0, 0.0, 1.0]])
+        ehat = np.array([[1.0, 0.0, 0.0]])
+        for prec in ("fp64", "mixed"):
+            P_, info = t.solve(khat=khat, ehat=ehat, solver="qmr_sym", precision=prec, tol=1e-10)
+            assert info[0]["converged"], (prec, info)
+            ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0)
+            Pl = ora.solve_dense(sites, kd, ainv, ora.einc(sites, kd, khat[0], ehat[0]))
+            _close(P_.cpu().numpy()[0], Pl, 1e-8, (shape, ylog, prec))
+
+
 @pytest.mark.parametrize("shape", FUSED_SHAPES)
 @pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 8, -1])
 @pytest.mark.parametrize("jacobi", [False, True])
