@@ -60,14 +60,6 @@ def pass_bytes(K, J, P, Kpp, Jpp, Kh, Jh, Ph, nd, b, jacobi):
     }
 
 
-KERNEL_OF_PASS = {  # (pass, precision) -> kernel template name in the rocprofv3 summaries
-    ("y_forward", "fp32"): "dda::k_fast_yfwd<float", ("x_forward", "fp32"): "dda::k_fast_x<float, false",
-    ("z_product", "fp32"): "dda::k_fast_zmul<float", ("x_inverse", "fp32"): "dda::k_fast_x<float, true",
-    ("y_inverse", "fp32"): "dda::k_fast_yinv<float", ("xy_forward", "fp32"): "dda::k_xy_fwd<float",
-    ("xy_inverse", "fp32"): "dda::k_xy_inv<float",
-}
-
-
 def kernel_source_sha1():
     import hashlib
     h = hashlib.sha1()
@@ -77,21 +69,34 @@ def kernel_source_sha1():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(pass_name, prec, workload):
-    """HBM bytes per launch of a pass from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    summary is missing or the kernel sources changed since it was taken."""
+def measured_traffic(pass_name, workload, schedule):
+    """HBM bytes per launch of an FP32 pass ("matvec": the whole product) from
+    the committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or None when the summary is missing, was taken with
+    another schedule, or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_matvec_fp32_{workload}.txt")
-    # "matvec_total": the summary's sum over the kernels of one product
-    key = "matvec_total" if pass_name == "matvec" else KERNEL_OF_PASS.get((pass_name, prec))
-    if key is None or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
-    sha = None
+    key = "pass matvec_total" if pass_name == "matvec" else f"pass {pass_name}"
+    sha = sched = None
     for line in open(path):
         if line.startswith("source_sha1:"):
             sha = line.split(":", 1)[1].strip()
-        elif line.startswith(key) and sha == kernel_source_sha1():
-            return int(float(line.split()[-2]))
+        elif line.startswith("schedule:"):
+            sched = int(line.split(":", 1)[1])
+        elif line.startswith(key + " ") and sha == kernel_source_sha1() and sched == schedule:
+            return int(line.split()[-1])
+    return None
+
+
+def tuned_schedule(tune_file, K, J, P, prec):
+    """The schedule the autotuner recorded for a single-RHS product of this
+    lattice in this precision (the low 4 bits of the plan), or None."""
+    if not os.path.exists(tune_file):
+        return None
+    for ln in open(tune_file):
+        if ln.startswith(f"mv {K}x{J}x{P} ") and f" nrhs 1 {prec} = " in ln:
+            return int(ln.rsplit("=", 1)[1]) & 15
     return None
 
 
@@ -575,10 +580,14 @@ def main():
     mv_s = mv_ms / mv_n / 1e3
     b3 = b3_bytes(K, J, P, info["Jpp"], info["Kh"], info["Jh"], info["Ph"], nd, 8)
     achieved = b3 / mv_s / 1e9
+    sched32 = tuned_schedule(tune_file, K, J, P, "fp32")
     pass_sum_s = sum(prof[(p, "fp32")][0] / prof[(p, "fp32")][1] for p in dda.PASS_NAMES
                      if p != "matvec" and prof[(p, "fp32")][1]) / 1e3
-    # the dominant kernel of the product (longest FP32 pass) on its own bytes
-    zname, zms, zn = max(((p, *prof[(p, "fp32")]) for p in dda.PASS_NAMES
+    # the z pass (z DFT, product, inverse z DFT) on its own bytes, and the
+    # longest FP32 pass of the product
+    zname = "z_product"
+    zms, zn = prof[(zname, "fp32")]
+    lname, lms, ln = max(((p, *prof[(p, "fp32")]) for p in dda.PASS_NAMES
                           if p != "matvec" and prof[(p, "fp32")][1]), key=lambda a: a[1] / a[2])
     z_s = zms / zn / 1e3
     z_ach = bpe["fp32"][zname] / z_s / 1e9
@@ -604,7 +613,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "FP32 matrix-vector product (all passes)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": measured_traffic("matvec", "fp32", args.workload),
+                     "traffic": measured_traffic("matvec", args.workload, sched32),
+                     "schedule": sched32,
                      "bytes": "B3 = 8 [9 N_d + 12 K J'' P + 6 K_h J_h P_h] per product (3-pass model)",
                      "bytes_per_launch": b3, "avg_launch_us": round(mv_s * 1e6, 2), "launches": mv_n,
                      "pass_kernels_sum_us": round(pass_sum_s * 1e6, 2),
@@ -614,7 +624,8 @@ def main():
                      "z_kernel": {"pass": zname, "achieved": round(z_ach, 1),
                                   "frac": round(z_ach / HBM_PEAK_GBPS, 4), "avg_launch_us": round(z_s * 1e6, 2),
                                   "bytes_per_launch": bpe["fp32"][zname],
-                                  "traffic": measured_traffic(zname, "fp32", args.workload)}},
+                                  "traffic": measured_traffic(zname, args.workload, sched32)},
+                     "longest_pass": {"pass": lname, "avg_launch_us": round(lms / ln * 1e3, 2)}},
         "solve": {"iterations": infm[0]["iterations"], "outer_iterations": infm[0]["outer_iterations"],
                   "matvecs": infm[0]["matvecs"], "rel_residual": infm[0]["rel_residual"],
                   "cross_sections": {"cext": cm[0], "cabs": cm[1], "csca": cm[2]},

@@ -1030,7 +1030,7 @@ struct FastLaunch {
                      const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
                      const QmrFuse<R>* qf) {
     constexpr int TX = fast_tx<N>() << L;
-    dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
+    dim3 grid((unsigned)ytile_blocks((long)((va.K + TX - 1) / TX) * va.P * va.nrhs));
     if (qf)
       hipLaunchKernelGGL((k_fast_yfwd<R, N, TX, true>), grid, dim3(FastPlan<N>::T * TX), 0, st, x, G1, map, a0, a1,
                          S, act, va, tw, *qf);
@@ -1061,7 +1061,7 @@ struct FastLaunch {
                      const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va,
                      const cx<R>* tw, DotArgs dot) {
     constexpr int TX = fast_tx<N>() << L;
-    dim3 grid((va.K + TX - 1) / TX, g0.y, g0.z);
+    dim3 grid((unsigned)ytile_blocks((long)((va.K + TX - 1) / TX) * va.P * va.nrhs));
     hipLaunchKernelGGL((k_fast_yinv<R, N, TX>), grid, dim3(FastPlan<N>::T * TX), 0, st, G1, x, y, map, a0, a1, S,
                        act, va, tw, dot);
   }
@@ -1284,6 +1284,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   const cx<R>* a0 = b.a0.template as<cx<R>>();
   const cx<R>* a1 = t->has_a1 ? b.a1.template as<cx<R>>() : nullptr;
   VecArgs va;
+  va.nrhs = nrhs;
   va.K = K;
   va.J = J;
   va.P = P;
@@ -2483,8 +2484,10 @@ static int true_residual(dda_target* t, int nrhs, const c64* E, const c64* Pv, c
   return DDA_OK;
 }
 
+// FP64 outer buffers, five slots of [nrhs][3][N_d]: (caller's), residual,
+// product scratch, and the P and residual of the last accepted step
 static int ensure_outer(dda_target* t, int nrhs) {
-  return t->outer.ensure((size_t)3 * nrhs * 3 * t->nd * sizeof(c64));
+  return t->outer.ensure((size_t)5 * nrhs * 3 * t->nd * sizeof(c64));
 }
 
 static void orientation_S(dda_target* t, int nrhs, const double* khat, const double* ehat, const double* S,
@@ -2520,6 +2523,8 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   const long n3 = 3 * t->nd;
   c64* r64 = t->outer.as<c64>() + (size_t)nrhs * n3;
   c64* y64 = r64 + (size_t)nrhs * n3;
+  c64* pkeep = y64 + (size_t)nrhs * n3;
+  c64* rkeep = pkeep + (size_t)nrhs * n3;
   const bool mixed = o.precision == DDA_SOLVE_MIXED;
   std::vector<int> hi(nrhs, mixed ? 0 : 1);  // 1: FP64 inner solves for this right-hand side
   const int nslots = solver_slots(o.solver, solver_param(o));
@@ -2599,6 +2604,9 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
         if (m[q]) ir.iters[q] = irg.iters[q];
     }
     HIPCHK(hipMemcpyAsync(t->scal.p, hacc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    // keep P and the residual of this step's start, to take the step back
+    HIPCHK(hipMemcpyAsync(pkeep, Pv, (size_t)nrhs * n3 * sizeof(c64), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(rkeep, r64, (size_t)nrhs * n3 * sizeof(c64), hipMemcpyDeviceToDevice, st));
     for (int g = 0; g < 2; ++g) {
       int nm = 0;
       for (int q = 0; q < nrhs; ++q) nm += hgrp[g][q];
@@ -2622,6 +2630,16 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       }
     const std::vector<double> prev = rn2;
     CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
+    for (int q = 0; q < nrhs; ++q)
+      if (hact[q] && !(rn2[q] <= prev[q])) {
+        // the correction made this right-hand side's true residual worse, or
+        // not finite (an FP32 inner solve that overflowed): take the step
+        // back; the rule below then moves it to FP64 inner solves
+        const size_t off = (size_t)q * n3, bytes = (size_t)n3 * sizeof(c64);
+        HIPCHK(hipMemcpyAsync(Pv + off, pkeep + off, bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(r64 + off, rkeep + off, bytes, hipMemcpyDeviceToDevice, st));
+        rn2[q] = prev[q];
+      }
     for (int q = 0; q < nrhs; ++q)
       if (hact[q] && !hi[q] && rn2[q] > tol * tol * en2[q] && rn2[q] > prev[q] / 16.0) {
         hi[q] = 1;

@@ -204,9 +204,35 @@ struct FastStages3 {
 };
 
 // ---------------------------------------------------------------------------
-// y forward with expansion (Sec. 3 and 4): grid (ceil(K/TX), P, nrhs*3),
-// block T*TX threads; lane = t*TX + l (l fastest: coalesced rows).
+// y forward with expansion (Sec. 3 and 4): one block per (x tile of TX
+// columns, z plane, right-hand side, component), block T*TX threads; lane =
+// t*TX + l (l fastest: coalesced rows).
 // ---------------------------------------------------------------------------
+// The y passes' 1D grid: blocks are dealt to the 8 XCDs round-robin, and the
+// three component blocks of one (tile, plane, right-hand side) group take
+// consecutive slots of one XCD, so the dipoles' occupancy words and diagonal
+// entries that all three read come from that XCD's L2 after the first
+// (measured at the 128^3 sphere with the components as a grid dimension:
+// the y-forward pass fetched 177 MB for 45 MB of such reads).
+struct YTile {
+  int tile, k, c, rhs;
+  bool ok;
+};
+__device__ __forceinline__ YTile ytile_of(int b, int ntile, int P, int nrhs) {
+  const int xcd = b & 7, slot = b >> 3;
+  const int g = (slot / 3) * 8 + xcd;
+  YTile y;
+  y.c = slot - (slot / 3) * 3;
+  y.ok = g < ntile * P * nrhs;
+  y.tile = g % ntile;
+  const int r = g / ntile;
+  y.k = r % P;
+  y.rhs = r / P;
+  return y;
+}
+// blocks of that grid for ngroups = tiles x planes x right-hand sides
+__host__ __device__ constexpr long ytile_blocks(long ngroups) { return 24 * ((ngroups + 7) / 8); }
+
 // QF: a whole QMR_sym step runs here (QmrFuse): the block reduces the
 // previous partials and runs the scalar recurrence (as every block of
 // k_qmr_step does), then forms vt_{n+1} for the dipoles it expands, which
@@ -218,13 +244,15 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
     const cx<R>* __restrict__ tw, QmrFuse<R> qf) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
   __shared__ cx<R> lds[N * TX];
-  const int rc = blockIdx.z, rhs = rc / 3;
+  const int ntile = (a.K + TX - 1) / TX;
+  const YTile yt = ytile_of(blockIdx.x, ntile, a.P, a.nrhs);
+  if (!yt.ok) return;
+  const int rhs = yt.rhs, cc = yt.c, rc = 3 * rhs + cc;  // cc: this component's diagonal entries
   if (active && !active[rhs]) return;
   const int l = threadIdx.x % TX, t = threadIdx.x / TX;
-  const int i = blockIdx.x * TX + l, k = blockIdx.y;
+  const int i = yt.tile * TX + l, k = yt.k;
   const R Sr = S ? (R)S[rhs] : (R)0;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const int cc = rc % 3;  // this component's diagonal entries
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   cx<R> v[E];
   QmrCoef qd{};
@@ -253,7 +281,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
         q.stop = s0.converged;
       }
       cq = q;
-      if (blockIdx.x == 0 && blockIdx.y == 0 && rc % 3 == 0) {
+      if (yt.tile == 0 && k == 0 && cc == 0) {
         s0.ver += 1;
         qf.sout[rhs] = s0;
         if (q.stop) qf.active[rhs] = 0;
@@ -289,7 +317,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yfwd(
   if constexpr (QF) {
     block_sum2_any(acc[0], acc[1]);
     if (threadIdx.x == 0) {
-      const long bid = ((long)(rc % 3) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      const long bid = ((long)cc * a.P + k) * ntile + yt.tile;
       c64* po = qf.pnorm_out + ((long)rhs * qf.nblk_out + bid) * 2;
       po[0] = acc[0];
       po[1] = acc[1];
@@ -306,10 +334,13 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
     const int* __restrict__ active, VecArgs a, const cx<R>* __restrict__ tw, DotArgs dt) {
   constexpr int E = FastPlan<N>::E, T = FastPlan<N>::T;
   __shared__ cx<R> lds[N * TX];
-  const int rc = blockIdx.z, rhs = rc / 3;
+  const int ntile = (a.K + TX - 1) / TX;
+  const YTile yt = ytile_of(blockIdx.x, ntile, a.P, a.nrhs);
+  if (!yt.ok) return;
+  const int rhs = yt.rhs, cc = yt.c, rc = 3 * rhs + cc;  // cc: this component's diagonal entries
   if (active && !active[rhs]) return;
   const int l = threadIdx.x % TX, t = threadIdx.x / TX;
-  const int i = blockIdx.x * TX + l, k = blockIdx.y;
+  const int i = yt.tile * TX + l, k = yt.k;
   const cx<R>* src = G1 + ((long)rc * a.P + k) * N * a.K + i;
   cx<R> v[E];
 #pragma unroll
@@ -318,7 +349,6 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
   const R Sr = S ? (R)S[rhs] : (R)0;
   const R sc = (R)a.scale;
   const cx<R>* xv = x + (long)rc * a.nd;
-  const int cc = rc % 3;  // this component's diagonal entries
   cx<R>* yv = y + (long)rc * a.nd;
   c64 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
   if (i < a.K) {
@@ -336,7 +366,7 @@ __global__ void __launch_bounds__(FastPlan<N>::T * TX) k_fast_yinv(
       dot_term(dt, xn, yn, (long)rc * a.nd + n, d0, d1);
     }
   }
-  dot_flush(dt, rhs, rc - 3 * rhs, d0, d1);
+  dot_flush_at(dt, rhs, ((long)cc * a.P + k) * ntile + yt.tile, 3L * a.P * ntile, d0, d1);
 }
 
 // x direction on rows: RW rows per block, lane = row*T + t (t fastest).

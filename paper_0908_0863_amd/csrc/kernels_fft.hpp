@@ -203,6 +203,7 @@ __device__ __forceinline__ int site_index(const OccBits& o, long row, int i) {
 
 struct VecArgs {
   int K, J, P, Jpp, Kpp, Ppp;
+  int nrhs = 1;  // right-hand sides of the launch
   long nd;
   long dstride;  // distance between the components' diagonals: N_d, or 0 when isotropic (shared entries)
   int TX;
@@ -290,16 +291,20 @@ __device__ __forceinline__ void dot_term(const DotArgs& dt, cx<R> xv, cx<R> yv, 
   }
 }
 
-// Write the block's fused inner-product partials (all threads must call).
-__device__ __forceinline__ void dot_flush(const DotArgs& dt, int rhs, int c, c64 d0, c64 d1) {
+// Write the block's fused inner-product partials as block blk of nblk per
+// right-hand side (all threads must call).
+__device__ __forceinline__ void dot_flush_at(const DotArgs& dt, int rhs, long blk, long nblk, c64 d0, c64 d1) {
   if (dt.mode == DOT_NONE) return;
   block_sum2_any(d0, d1);
   if (threadIdx.x == 0) {
-    const long nblk = 3L * gridDim.y * gridDim.x;
-    const long blk = ((long)c * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     dt.part[((long)rhs * nblk + blk) * 2] = d0;
     dt.part[((long)rhs * nblk + blk) * 2 + 1] = d1;
   }
+}
+// ... for a grid (tiles, planes, 3 nrhs): component c of right-hand side rhs
+__device__ __forceinline__ void dot_flush(const DotArgs& dt, int rhs, int c, c64 d0, c64 d1) {
+  dot_flush_at(dt, rhs, ((long)c * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, 3L * gridDim.y * gridDim.x,
+               d0, d1);
 }
 
 template <typename R>

@@ -105,6 +105,14 @@ __device__ __forceinline__ void reduce_all(const c64* __restrict__ part, int nbl
 }
 
 __device__ __forceinline__ bool tiny(c64 a, double scale) { return !(abs2(a) > 1e-300 * scale); }
+// a scalar coefficient that the vector precision R can hold (finite, both parts
+// at most R's largest value): an FP32 inner solve overflows far above the
+// FP64 breakdown thresholds
+template <typename R>
+__device__ __forceinline__ bool holds(c64 a) {
+  constexpr double big = sizeof(R) == 4 ? 3.0e38 : 1.0e300;
+  return fabs(a.x) <= big && fabs(a.y) <= big;
+}
 
 // ============================================================================
 // BiCGSTAB (van der Vorst 1992), complex, Hermitian inner products
@@ -786,6 +794,12 @@ __global__ void __launch_bounds__(kRedThreads) k_tfq_a(const cx<R>* __restrict__
     } else {
       s.alpha = cdiv(s.rho, s.sigma);
       dcoef = (s.theta * s.theta) * cdiv(s.eta, s.alpha);
+      // alpha and the d coefficient must be usable in the vectors' precision
+      // (a vanishing alpha makes eta / alpha 0/0 and x += eta d NaN)
+      if (tiny(s.alpha, 1.0) || !holds<R>(s.alpha) || !holds<R>(dcoef)) {
+        s.breakdown = 1;
+        stop = 1;
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -832,16 +846,28 @@ __global__ void __launch_bounds__(kRedThreads) k_tfq_b(cx<R>* __restrict__ x, co
   reduce_all<2>(pw, dm.nblk, rhs, rw);
   reduce_all<2>(puo, nblk_mv, rhs, ru);
   TfqState s = sin[rhs];
-  if (s.converged || s.breakdown) return;
-  const bool conv = tfq_close(s, rw[0].x);
+  if (s.converged || s.breakdown) {
+    // carry a stopped state into this kernel's output buffer: the state
+    // buffers swap roles every iteration, so a state left behind here would
+    // be read back stale two kernels later
+    if (blockIdx.x == 0 && threadIdx.x == 0) sout[rhs] = s;
+    return;
+  }
+  bool conv = tfq_close(s, rw[0].x);
   s.s_uo = ru[0];
   if (conv) s.converged = 1;
   const c64 dcoef = (s.theta * s.theta) * cdiv(s.eta, s.alpha);
+  if (!conv && (!holds<R>(s.eta) || !holds<R>(dcoef))) {
+    // x is still updated with this half-step's eta when it is usable; the
+    // second half-step is not opened
+    s.breakdown = 1;
+    conv = true;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s.ver += 1;
     sout[rhs] = s;
   }
-  const cx<R> et = cvt<R>(s.eta), al = cvt<R>(s.alpha), dc = cvt<R>(dcoef);
+  const cx<R> et = holds<R>(s.eta) ? cvt<R>(s.eta) : mk((R)0, (R)0), al = cvt<R>(s.alpha), dc = cvt<R>(dcoef);
   c64 acc[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
   const long o = (long)rhs * dm.n3;
   DDA_RANGE(dm, i) {
@@ -871,24 +897,36 @@ __global__ void __launch_bounds__(kRedThreads) k_tfq_c(cx<R>* __restrict__ x, co
                                                        const cx<R>* __restrict__ w, const cx<R>* __restrict__ uo,
                                                        cx<R>* __restrict__ ue, const c64* __restrict__ pw,
                                                        const TfqState* __restrict__ sin, TfqState* __restrict__ sout,
-                                                       const int* __restrict__ active, SolverDims dm) {
+                                                       int* __restrict__ active, SolverDims dm) {
   const int rhs = blockIdx.y;
   if (!active[rhs]) return;
   c64 rw[2];
   reduce_all<2>(pw, dm.nblk, rhs, rw);
   TfqState s = sin[rhs];
-  if (s.converged || s.breakdown) return;
+  if (s.converged || s.breakdown) {
+    // stopped at the first half-step (k_tfq_b): pass the state on (the next
+    // iteration reads this kernel's output buffer) and stop the right-hand side
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sout[rhs] = s;
+      active[rhs] = 0;
+    }
+    return;
+  }
   const bool conv = tfq_close(s, rw[0].x);
   bool upd = !conv;
   if (conv) {
     s.converged = 1;
   } else {
     const c64 rho_new = rw[1];
-    if (tiny(s.rho, s.bnorm2 * s.bnorm2 * 1e-32) || !isfinite(rho_new.x)) {
+    // rho' = rt^H w vanishing (or not finite) is a breakdown now, before the
+    // next half-step divides by alpha = rho' / sigma
+    const c64 beta = cdiv(rho_new, s.rho);
+    if (tiny(rho_new, s.bnorm2 * s.bnorm2 * 1e-32) || !isfinite(rho_new.x) || !isfinite(rho_new.y) ||
+        !holds<R>(beta)) {
       s.breakdown = 1;
       upd = false;
     } else {
-      s.beta = cdiv(rho_new, s.rho);
+      s.beta = beta;
       s.rho = rho_new;
     }
     if (s.rnorm2 < 0.98 * s.best2) {

@@ -194,6 +194,44 @@ def test_solve_mixed_sphere16(lib, solver, param):
     assert _rel(P[0].cpu().numpy(), Po) < 1e-8
 
 
+@pytest.mark.parametrize("plans", [(6, 2), (5, 2), (0, 0)])
+def test_tfqmr_stops_where_its_bound_is_met(tmp_path, plans):
+    """TFQMR that meets its residual bound at the first half-step of an
+    iteration stops there: its state reaches the buffer the next iteration
+    reads (a looser tolerance once took 90 iterations against 8 for 1e-9, and
+    the mixed solve ended in NaN for one pair of FP32/FP64 schedules).  Both
+    FP64 runs and the mixed solve (schedules seeded per precision through the
+    tune file) are checked against the oracle's LU."""
+    from paper_0908_0863_amd import dda
+    p32, p64 = plans
+    path = tmp_path / "tune.txt"
+    path.write_text(f"mv 16x16x16 pad 32x32x32 nrhs 2 fp32 = {p32}\n"
+                    f"mv 16x16x16 pad 32x32x32 nrhs 2 fp64 = {p64}\n"
+                    f"mv 16x16x16 pad 32x32x32 nrhs 1 fp64 = {p64}\n")
+    lib = dda.Library(0, tune_cache=str(path))
+    w = inputs.workload("sphere16")
+    eps = w["m"] ** 2
+    t, nd = _target(lib, w["occ"], w["kd"], eps)
+    its = {}
+    for tol in (1e-4, 1e-9):
+        P, info = t.solve(khat=[[0, 0, 1]], ehat=[[1, 0, 0]], solver="tfqmr", precision="fp64", tol=tol,
+                          use_graph=False)
+        assert info[0]["converged"] and info[0]["rel_residual"] <= tol
+        its[tol] = info[0]["iterations"]
+    assert its[1e-4] <= its[1e-9], its
+    kw = dict(khat=[[0, 0, 1], [0, 0, 1]], ehat=[[1, 0, 0], [0, 1, 0]], solver="tfqmr", precision="mixed",
+              tol=1e-9, inner_tol=1e-4, check_every=4)
+    for graph in (False, True):
+        P, info = t.solve(use_graph=graph, **kw)
+        P = P.cpu().numpy()
+        for r in range(2):
+            assert info[r]["converged"] and np.isfinite(P[r]).all()
+            Po = _sphere16_lu(w["kd"], eps, kw["khat"][r], kw["ehat"][r], 0.0)
+            assert _rel(P[r], Po) < 1e-7
+    t.close()
+    lib.close()
+
+
 _BOX_LU = {}
 
 
