@@ -311,8 +311,13 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * takes its widest); -1 leaves it to the autotuner, which times the wider
  * variants after choosing the schedule.  DDA_EINVAL if even FP32 has no such
  * variant for the lattice. */
+/* DDA_OPT_INJECT_BAD_STEP (fault injection for tests of the recovery path):
+ * the next `value` refinement steps of dda_solve add their correction with the
+ * wrong sign, so the true residual grows and the step must be taken back (P
+ * and the residual of the step's start restored, the right-hand side moved to
+ * FP64 inner solves).  DDA_EINVAL for a negative value. */
 enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4,
-       DDA_OPT_RHS_PER_BLOCK = 5, DDA_OPT_Y_TILE = 6 };
+       DDA_OPT_RHS_PER_BLOCK = 5, DDA_OPT_Y_TILE = 6, DDA_OPT_INJECT_BAD_STEP = 7 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:

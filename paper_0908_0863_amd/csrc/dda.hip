@@ -276,6 +276,7 @@ struct dda_target {
   bool spec_ready = false;
   int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
   int forced_ylog = -1;      // -1: tuned; L >= 0: y tile 2^L times the default
+  int inject_bad_step = 0;   // fault injection: refinement steps applied with the wrong sign
   int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
   int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
   int fuse_qmr = 1;          // QMR_sym step fused into the y-forward pass where possible
@@ -571,6 +572,10 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_FUSE_QMR_STEP:
       if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: fuse %d", value);
       t->fuse_qmr = value;
+      return DDA_OK;
+    case DDA_OPT_INJECT_BAD_STEP:
+      if (value < 0) return fail(DDA_EINVAL, "dda_target_set_option: inject count %d", value);
+      t->inject_bad_step = value;
       return DDA_OK;
     case DDA_OPT_Y_TILE:
       if (value < -1 || value > 2) return fail(DDA_EINVAL, "dda_target_set_option: y tile variant %d", value);
@@ -2602,6 +2607,11 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
       }
       for (int q = 0; q < nrhs; ++q)
         if (m[q]) ir.iters[q] = irg.iters[q];
+    }
+    if (t->inject_bad_step > 0) {
+      // fault injection: this step's correction goes the wrong way
+      --t->inject_bad_step;
+      for (int q = 0; q < nrhs; ++q) hacc[q] = -hacc[q];
     }
     HIPCHK(hipMemcpyAsync(t->scal.p, hacc.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     // keep P and the residual of this step's start, to take the step back

@@ -138,3 +138,30 @@ def test_injected_breakdown_restarts_from_true_residual(dda, lib, precision):
     assert (torch.linalg.norm(P1 - P0) / torch.linalg.norm(P0)).item() < 1e-8
     P2, i2 = t.solve(**kw)  # the injections are used up
     assert i2[0]["outer_iterations"] == i0[0]["outer_iterations"]
+
+
+@pytest.mark.parametrize("solver", ["qmr_sym", "tfqmr"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_step_that_worsens_the_residual_is_taken_back(dda, lib, solver, precision):
+    """A refinement step applied with the wrong sign (fault injection from the
+    host) leaves the true residual larger than before: the loop restores P and
+    the residual of that step's start, and the solve still ends at the answer
+    of the undisturbed one (in mixed precision on FP64 inner solves).  Two
+    right-hand sides, both disturbed."""
+    t, w = _sphere16(dda, lib)
+    kw = dict(khat=w["khat"], ehat=w["ehat"], solver=solver, precision=precision, tol=1e-10, inner_tol=1e-4)
+    P0, i0 = t.solve(**kw)
+    with pytest.raises(dda.DDAError) as e:
+        t.set_option(dda.DDA_OPT_INJECT_BAD_STEP, -1)
+    assert _code(e) == dda.DDA_EINVAL
+    t.set_option(dda.DDA_OPT_INJECT_BAD_STEP, 1)
+    P1, i1 = t.solve(**kw)
+    for r in range(len(i0)):
+        assert i0[r]["converged"] and i1[r]["converged"]
+        # the taken-back step counts; in mixed precision the FP64 inner solves
+        # that follow it can need fewer steps than the undisturbed solve
+        assert i1[r]["outer_iterations"] >= 2
+        if precision == "fp64":
+            assert i1[r]["outer_iterations"] == i0[r]["outer_iterations"] + 1
+        assert torch.isfinite(torch.view_as_real(P1[r])).all()
+        assert (torch.linalg.norm(P1[r] - P0[r]) / torch.linalg.norm(P0[r])).item() < 1e-8
