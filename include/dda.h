@@ -316,8 +316,13 @@ int dda_grad_cabs_eps(dda_target *t, const dda_solve_opts *opts, int nrhs, const
  * wrong sign, so the true residual grows and the step must be taken back (P
  * and the residual of the step's start restored, the right-hand side moved to
  * FP64 inner solves).  DDA_EINVAL for a negative value. */
+/* DDA_OPT_X_ROWS (-1, the default, or 0..2): the x passes of the register-
+ * resident schedules take their default number of rows per block (0), half
+ * of it (1) or twice it (2), within 1024 threads and 64 KB of LDS (a variant
+ * that does not fit runs the default); -1 leaves it to the autotuner, which
+ * times 1 and 2 after the y tiles.  DDA_EINVAL outside -1..2. */
 enum { DDA_OPT_SCHEDULE = 1, DDA_OPT_INJECT_BREAKDOWN = 2, DDA_OPT_CANARY = 3, DDA_OPT_FUSE_QMR_STEP = 4,
-       DDA_OPT_RHS_PER_BLOCK = 5, DDA_OPT_Y_TILE = 6, DDA_OPT_INJECT_BAD_STEP = 7 };
+       DDA_OPT_RHS_PER_BLOCK = 5, DDA_OPT_Y_TILE = 6, DDA_OPT_INJECT_BAD_STEP = 7, DDA_OPT_X_ROWS = 8 };
 int dda_target_set_option(dda_target *t, int option, int value);
 
 /* Sizes of the embedding, for inspection:

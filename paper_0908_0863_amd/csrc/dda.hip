@@ -276,6 +276,7 @@ struct dda_target {
   bool spec_ready = false;
   int forced_sched = -1;     // -1: tuned; 0: five passes; D > 0: fused xy passes with split D
   int forced_ylog = -1;      // -1: tuned; L >= 0: y tile 2^L times the default
+  int forced_xsel = -1;      // -1: tuned; 0, 1, 2: x-pass rows per block default, half, twice
   int inject_bad_step = 0;   // fault injection: refinement steps applied with the wrong sign
   int inject_breakdown = 0;  // BiCGSTAB inner solves still to start from a zero shadow vector
   int canary = 0;            // dda_matvec fills its workspaces with NaN first (debug)
@@ -572,6 +573,10 @@ int dda_target_set_option(dda_target* t, int option, int value) {
     case DDA_OPT_FUSE_QMR_STEP:
       if (value != 0 && value != 1) return fail(DDA_EINVAL, "dda_target_set_option: fuse %d", value);
       t->fuse_qmr = value;
+      return DDA_OK;
+    case DDA_OPT_X_ROWS:
+      if (value < -1 || value > 2) return fail(DDA_EINVAL, "dda_target_set_option: x rows variant %d", value);
+      t->forced_xsel = value;
       return DDA_OK;
     case DDA_OPT_INJECT_BAD_STEP:
       if (value < 0) return fail(DDA_EINVAL, "dda_target_set_option: inject count %d", value);
@@ -999,6 +1004,17 @@ constexpr int fast_rw() {
   return rw < 1 ? 1 : (rw > 64 ? 64 : rw);
 }
 
+// Rows per block of an x pass for variant xsel: 0 the base count, 1 half of
+// it, 2 twice it (within 1024 threads and 64 KB of LDS; a variant that does
+// not fit is the base count)
+template <typename R, int N>
+constexpr int xrows_variant(int base, int xsel) {
+  constexpr int T = FastPlan<N>::T, LS = N + N / 8 + 1;
+  const int rw = xsel == 1 ? base / 2 : xsel == 2 ? base * 2 : base;
+  if (rw < 1 || rw * T > 1024 || rw * LS * (int)sizeof(cx<R>) > 65536) return base;
+  return rw;
+}
+
 template <typename R>
 struct FastLaunch {
   template <int N>
@@ -1082,13 +1098,22 @@ struct FastLaunch {
       if (L == 1) return yinv_L<N, 1>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
     yinv_L<N, 0>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
   }
-  template <int N, bool INV>
-  static void xpass(hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride, int lout_stride,
-                    int Lin, int Lout, long rows_per_rhs, const int* act, const cx<R>* tw) {
-    constexpr int RW = fast_rw<N>();
+  template <int N, bool INV, int RW>
+  static void xpass_rw(hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride, int lout_stride,
+                       int Lin, int Lout, long rows_per_rhs, const int* act, const cx<R>* tw) {
     dim3 grid((unsigned)((nrows + RW - 1) / RW));
     hipLaunchKernelGGL((k_fast_x<R, INV, N, RW>), grid, dim3(FastPlan<N>::T * RW), 0, st, in, out, nrows, lin_stride,
                        lout_stride, Lin, Lout, rows_per_rhs, act, tw);
+  }
+  template <int N, bool INV>
+  static void xpass(int xsel, hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride,
+                    int lout_stride, int Lin, int Lout, long rows_per_rhs, const int* act, const cx<R>* tw) {
+    constexpr int B = fast_rw<N>(), R1 = xrows_variant<R, N>(B, 1), R2 = xrows_variant<R, N>(B, 2);
+    if (xsel == 1 && R1 != B)
+      return xpass_rw<N, INV, R1>(st, in, out, nrows, lin_stride, lout_stride, Lin, Lout, rows_per_rhs, act, tw);
+    if (xsel == 2 && R2 != B)
+      return xpass_rw<N, INV, R2>(st, in, out, nrows, lin_stride, lout_stride, Lin, Lout, rows_per_rhs, act, tw);
+    xpass_rw<N, INV, B>(st, in, out, nrows, lin_stride, lout_stride, Lin, Lout, rows_per_rhs, act, tw);
   }
   template <int N>
   static void zsplit(int nrhs, hipStream_t st, cx<R>* G2, const cx<R>* Y, const int* act, ZArgs za,
@@ -1121,9 +1146,16 @@ struct FastLaunch {
     return rw;
   }
   template <int N, bool INV>
-  static void xb(const dda_target* t, int nrhs, int C, hipStream_t st, const cx<R>* in, cx<R>* out, const int* act,
-                 const cx<R>* tw) {
-    constexpr int RW = xb_rows<N>();
+  static void xb(int xsel, const dda_target* t, int nrhs, int C, hipStream_t st, const cx<R>* in, cx<R>* out,
+                 const int* act, const cx<R>* tw) {
+    constexpr int B = xb_rows<N>(), R1 = xrows_variant<R, N>(B, 1), R2 = xrows_variant<R, N>(B, 2);
+    if (xsel == 1 && R1 != B) return xb_rw<N, INV, R1>(t, nrhs, C, st, in, out, act, tw);
+    if (xsel == 2 && R2 != B) return xb_rw<N, INV, R2>(t, nrhs, C, st, in, out, act, tw);
+    xb_rw<N, INV, B>(t, nrhs, C, st, in, out, act, tw);
+  }
+  template <int N, bool INV, int RW>
+  static void xb_rw(const dda_target* t, int nrhs, int C, hipStream_t st, const cx<R>* in, cx<R>* out,
+                    const int* act, const cx<R>* tw) {
     int lc = 0;
     while ((1 << lc) < C) ++lc;
     const int NT = (t->Kpp + C - 1) / C;
@@ -1245,6 +1277,8 @@ template <typename R>
 static int schedule_of(const dda_target* t, int nrhs);
 template <typename R>
 static int ylog_of(const dda_target* t, int nrhs);
+template <typename R>
+static int xsel_of(const dda_target* t, int nrhs);
 
 template <typename R>
 static int yinv_blocks(const dda_target* t, int nrhs) {
@@ -1307,7 +1341,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   va.jacobi = jacobi;
   va.scale = 1.0 / ((double)Kpp * Jpp * Ppp);
   va.TX = tile_width<R>(K, Jpp, 2);
-  const int sched = schedule_of<R>(t, nrhs), ylog = ylog_of<R>(t, nrhs);
+  const int sched = schedule_of<R>(t, nrhs), ylog = ylog_of<R>(t, nrhs), xsel = xsel_of<R>(t, nrhs);
   const int dfwd = is_fused(sched) ? sched : 0, dinv = dfwd;
   if (dfwd && qf) return fail(DDA_EINVAL, "matvec: fused QMR step needs the register-resident y pass");
   if (dfwd) {
@@ -1400,7 +1434,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Kpp) {
 #define DDA_CASE(N)                                                                                          \
   case N:                                                                                                    \
-    FastLaunch<R>::template xb<N, false>(t, nrhs, C, st, G1, G2, active, b.tw[0].template as<cx<R>>());    \
+    FastLaunch<R>::template xb<N, false>(xsel, t, nrhs, C, st, G1, G2, active, b.tw[0].template as<cx<R>>());    \
     break;
         DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
@@ -1425,7 +1459,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Kpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
-    FastLaunch<R>::template xb<N, true>(t, nrhs, C, st, G2, G1, active, b.tw[0].template as<cx<R>>());     \
+    FastLaunch<R>::template xb<N, true>(xsel, t, nrhs, C, st, G2, G1, active, b.tw[0].template as<cx<R>>());     \
     break;
         DDA_FAST_SIZES(DDA_CASE)
 #undef DDA_CASE
@@ -1486,7 +1520,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     switch (Kpp) {
 #define DDA_CASE(N)                                                                                          \
   case N:                                                                                                    \
-    FastLaunch<R>::template xpass<N, false>(st, G1, G2, rows, K, Kpp, K, Kpp, 3L * P * Jpp, active,           \
+    FastLaunch<R>::template xpass<N, false>(xsel, st, G1, G2, rows, K, Kpp, K, Kpp, 3L * P * Jpp, active,           \
                                             b.tw[0].template as<cx<R>>());                                   \
     break;
       DDA_FAST_SIZES(DDA_CASE)
@@ -1553,7 +1587,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
     switch (Kpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
-    FastLaunch<R>::template xpass<N, true>(st, G2, G1, rows, Kpp, K, Kpp, K, 3L * P * Jpp, active,           \
+    FastLaunch<R>::template xpass<N, true>(xsel, st, G2, G1, rows, Kpp, K, Kpp, K, 3L * P * Jpp, active,           \
                                            b.tw[0].template as<cx<R>>());                                   \
     break;
       DDA_FAST_SIZES(DDA_CASE)
@@ -1606,8 +1640,9 @@ static std::string tune_key(const dda_target* t, int nrhs) {
   return k.str();
 }
 
-// A plan is the schedule in its low 4 bits and the y-tile variant (log2 of
-// the multiple of the default y tile) above them.
+// A plan is the schedule in its low 4 bits, the y-tile variant (log2 of the
+// multiple of the default y tile) in bits 4-5 and the x-pass rows variant
+// (0 the default rows per block, 1 half, 2 twice) in bits 6-7.
 template <typename R>
 static int plan_of(const dda_target* t, int nrhs) {
   if (t->sched_override >= 0) return t->sched_override;
@@ -1622,7 +1657,8 @@ static int plan_of(const dda_target* t, int nrhs) {
     auto it = t->lib->tuned.find(key);
     if (it != t->lib->tuned.end()) v = it->second;
   }
-  if (t->forced_ylog >= 0) v = (v & 15) | (t->forced_ylog << 4);
+  if (t->forced_ylog >= 0) v = (v & ~(3 << 4)) | (t->forced_ylog << 4);
+  if (t->forced_xsel >= 0) v = (v & ~(3 << 6)) | (t->forced_xsel << 6);
   return v;
 }
 template <typename R>
@@ -1631,7 +1667,11 @@ static int schedule_of(const dda_target* t, int nrhs) {
 }
 template <typename R>
 static int ylog_of(const dda_target* t, int nrhs) {
-  return plan_of<R>(t, nrhs) >> 4;
+  return (plan_of<R>(t, nrhs) >> 4) & 3;
+}
+template <typename R>
+static int xsel_of(const dda_target* t, int nrhs) {
+  return (plan_of<R>(t, nrhs) >> 6) & 3;
 }
 
 // widest y-tile variant of this lattice's y length in precision R (0 where
@@ -1701,26 +1741,41 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
         best = cand[ci];
       }
     t->matvecs -= 11 * (int)cand.size();
-    // then wider y tiles for the chosen schedule, the same way
+    // then the variants of the chosen schedule's y tiles and x-pass rows,
+    // the same way, one dimension after the other
+    auto time_plan = [&](int plan) -> float {
+      t->sched_override = plan;
+      float bl = 1e30f;
+      for (int w = 0; w < 2 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+      for (int round = 0; round < 3 && rc == DDA_OK; ++round) {
+        (void)hipEventRecord(e0, st);
+        for (int w = 0; w < 3 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        bl = std::min(bl, ms);
+      }
+      t->matvecs -= 11;
+      return bl;
+    };
     if (!is_fused(best) && t->forced_ylog < 0) {
       const int base = best;
       for (int L = 1; L <= ylog_max<R>(t) && rc == DDA_OK; ++L) {
-        t->sched_override = base | (L << 4);
-        float bl = 1e30f;
-        for (int w = 0; w < 2 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
-        for (int round = 0; round < 3 && rc == DDA_OK; ++round) {
-          (void)hipEventRecord(e0, st);
-          for (int w = 0; w < 3 && rc == DDA_OK; ++w) rc = matvec_T<R>(t, nrhs, dS, jacobi, x, y, nullptr, st);
-          (void)hipEventRecord(e1, st);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          bl = std::min(bl, ms);
-        }
-        t->matvecs -= 11;
+        const float bl = time_plan(base | (L << 4));
         if (bl < 0.97f * best_ms) {
           best_ms = bl;
           best = base | (L << 4);
+        }
+      }
+    }
+    if (!is_fused(best) && fast_size(t->Kpp) && t->forced_xsel < 0) {
+      const int base = best;
+      for (int xs = 1; xs <= 2 && rc == DDA_OK; ++xs) {
+        const float bl = time_plan(base | (xs << 6));
+        if (bl < 0.97f * best_ms) {
+          best_ms = bl;
+          best = base | (xs << 6);
         }
       }
     }

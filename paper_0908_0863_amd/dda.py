@@ -78,6 +78,7 @@ DDA_PROF_SLOTS = len(PASS_NAMES)
 DDA_OPT_SCHEDULE, DDA_OPT_INJECT_BREAKDOWN, DDA_OPT_CANARY, DDA_OPT_FUSE_QMR_STEP, DDA_OPT_RHS_PER_BLOCK = 1, 2, 3, 4, 5
 DDA_OPT_Y_TILE = 6
 DDA_OPT_INJECT_BAD_STEP = 7
+DDA_OPT_X_ROWS = 8
 
 _lib = None
 

@@ -194,6 +194,39 @@ def test_solve_mixed_sphere16(lib, solver, param):
     assert _rel(P[0].cpu().numpy(), Po) < 1e-8
 
 
+@pytest.mark.parametrize("xsel", [0, 1, 2])
+@pytest.mark.parametrize("sched", [0, 5, 6])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 9, 33), (7, 20, 12)])
+def test_x_rows_variants(lib, shape, sched, xsel):
+    """DDA_OPT_X_ROWS: the x passes (strided and tile-blocked) with half and
+    twice their default rows per block, ragged last blocks included, against
+    the dense oracle element by element in FP64 and FP32."""
+    from paper_0908_0863_amd import dda
+    K, J, P = shape
+    occ = _rand_occ((P, J, K), 81)
+    kd, eps = 0.33, 2.4 + 0.2j
+    t, nd = _target(lib, occ, kd, eps)
+    try:
+        t.set_option(dda.DDA_OPT_SCHEDULE, sched)
+    except dda.DDAError:
+        pytest.skip(f"no schedule {sched} for {shape}")
+    t.set_option(dda.DDA_OPT_X_ROWS, xsel)
+    sites = ora.sites_of(occ)
+    x = inputs.complex_gaussian(82, (2, 3, nd))
+    S = [0.15, 0.0]
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=True).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=True).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", S[r])
+        sc = 1.0 / np.sqrt(ainv)
+        yo = sc * ora.dense_matvec(sites, kd, ainv, sc * x[r])
+        _close(y[r], yo, 1e-12, (shape, sched, xsel, r))
+        _close(y32[r], yo, 2e-6, (shape, sched, xsel, r))
+    with pytest.raises(dda.DDAError) as e:
+        t.set_option(dda.DDA_OPT_X_ROWS, 3)
+    assert e.value.code == dda.DDA_EINVAL
+
+
 @pytest.mark.parametrize("plans", [(6, 2), (5, 2), (0, 0)])
 def test_tfqmr_stops_where_its_bound_is_met(tmp_path, plans):
     """TFQMR that meets its residual bound at the first half-step of an
