@@ -1047,7 +1047,7 @@ struct FastLaunch {
     return fast_tx<N>() << std::min(std::max(ylog, 0), ytx_max_log<R, N>());
   }
   template <int N, int L>
-  static void yfwd_L(dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
+  static void yfwd_L(hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
                      const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
                      const QmrFuse<R>* qf) {
     constexpr int TX = fast_tx<N>() << L;
@@ -1060,16 +1060,16 @@ struct FastLaunch {
                          a1, S, act, va, tw, QmrFuse<R>{});
   }
   template <int N>
-  static void yfwd(int ylog, dim3 g0, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
+  static void yfwd(int ylog, hipStream_t st, const cx<R>* x, cx<R>* G1, OccBits map, const cx<R>* a0,
                    const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
                    const QmrFuse<R>* qf) {
     constexpr int LM = ytx_max_log<R, N>();
     const int L = std::min(std::max(ylog, 0), LM);
     if constexpr (LM >= 2)
-      if (L == 2) return yfwd_L<N, 2>(g0, st, x, G1, map, a0, a1, S, act, va, tw, qf);
+      if (L == 2) return yfwd_L<N, 2>(st, x, G1, map, a0, a1, S, act, va, tw, qf);
     if constexpr (LM >= 1)
-      if (L == 1) return yfwd_L<N, 1>(g0, st, x, G1, map, a0, a1, S, act, va, tw, qf);
-    yfwd_L<N, 0>(g0, st, x, G1, map, a0, a1, S, act, va, tw, qf);
+      if (L == 1) return yfwd_L<N, 1>(st, x, G1, map, a0, a1, S, act, va, tw, qf);
+    yfwd_L<N, 0>(st, x, G1, map, a0, a1, S, act, va, tw, qf);
   }
   // y-forward blocks per right-hand side (3 components x P planes x x tiles)
   template <int N>
@@ -1078,7 +1078,7 @@ struct FastLaunch {
     return 3 * t->P * ((t->K + TX - 1) / TX);
   }
   template <int N, int L>
-  static void yinv_L(dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
+  static void yinv_L(hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
                      const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va,
                      const cx<R>* tw, DotArgs dot) {
     constexpr int TX = fast_tx<N>() << L;
@@ -1087,16 +1087,16 @@ struct FastLaunch {
                        act, va, tw, dot);
   }
   template <int N>
-  static void yinv(int ylog, dim3 g0, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
+  static void yinv(int ylog, hipStream_t st, const cx<R>* G1, const cx<R>* x, cx<R>* y, OccBits map,
                    const cx<R>* a0, const cx<R>* a1, const double* S, const int* act, VecArgs va, const cx<R>* tw,
                    DotArgs dot) {
     constexpr int LM = ytx_max_log<R, N>();
     const int L = std::min(std::max(ylog, 0), LM);
     if constexpr (LM >= 2)
-      if (L == 2) return yinv_L<N, 2>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
+      if (L == 2) return yinv_L<N, 2>(st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
     if constexpr (LM >= 1)
-      if (L == 1) return yinv_L<N, 1>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
-    yinv_L<N, 0>(g0, st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
+      if (L == 1) return yinv_L<N, 1>(st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
+    yinv_L<N, 0>(st, G1, x, y, map, a0, a1, S, act, va, tw, dot);
   }
   template <int N, bool INV, int RW>
   static void xpass_rw(hipStream_t st, const cx<R>* in, cx<R>* out, long nrows, int lin_stride, int lout_stride,
@@ -1402,7 +1402,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
-    FastLaunch<R>::template yfwd<N>(ylog, dim3(1, P, nrhs * 3), st, x, G1, occ_of(t), a0, a1, dS, active, va, \
+    FastLaunch<R>::template yfwd<N>(ylog, st, x, G1, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), qf);                                        \
     break;
         DDA_FAST_SIZES(DDA_CASE)
@@ -1606,7 +1606,7 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                             \
   case N:                                                                                                       \
-    FastLaunch<R>::template yinv<N>(ylog, dim3(1, P, nrhs * 3), st, G1, x, y, occ_of(t), a0, a1, dS, active, va, \
+    FastLaunch<R>::template yinv<N>(ylog, st, G1, x, y, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), dot);                                           \
     break;
         DDA_FAST_SIZES(DDA_CASE)
