@@ -137,6 +137,48 @@ def test_batched_128_rhs_mixed_solve_sampled_residual(lib):
         assert rel < 1e-5
 
 
+@pytest.mark.timeout(600)
+def test_batched_mixed_cross_sections_against_fp64(lib):
+    """Cross sections of the batched mixed-precision solve of the 96^3
+    ellipsoid (16 of its 128 orientations in one solve, QMR_sym to 2e-7)
+    against those of an FP64 solve of the same batch to 1e-12, both
+    evaluated by the oracle's formulas (C_ext = 4 pi k sum Im(E* . P), C_abs
+    from |P|^2 and alpha^{-1}): within 1e-6 relative for every right-hand
+    side, and the library's own cross sections of the mixed solve agree with
+    the oracle's evaluation of the same P."""
+    w = inputs.workload("ellipsoid96")
+    t, nd = _target(lib, w)
+    sites = ora.sites_of(w["occ"])
+    sel = list(range(0, 128, 8))
+    kh = [w["khat"][r] for r in sel]
+    eh = [w["ehat"][r] for r in sel]
+    Pm, im = t.solve(khat=kh, ehat=eh, solver="qmr_sym", precision="mixed", tol=2e-7, inner_tol=1e-4,
+                     check_every=16, use_graph=True)
+    ce_m, ca_m, cs_m = t.cross_sections(t.incident_field(kh, eh), Pm)
+    Pd, idd = t.solve(khat=kh, ehat=eh, solver="qmr_sym", precision="fp64", tol=1e-12, check_every=16,
+                      use_graph=True)
+    assert all(i["converged"] for i in im) and all(i["converged"] for i in idd)
+    eps = np.full(nd, w["m"] ** 2)
+    worst = [0.0, 0.0, 0.0]
+    for q, r in enumerate(sel):
+        S = ora.ldr_S(w["khat"][r], w["ehat"][r])
+        ainv = ora.alpha_inv(eps, w["kd"], "ldr", S)
+        E = ora.einc(sites, w["kd"], w["khat"][r], w["ehat"][r])
+        got, ref = [], []
+        for P_, dst in ((Pm[q].cpu().numpy(), got), (Pd[q].cpu().numpy(), ref)):
+            cext = ora.c_ext(w["kd"], E, P_)
+            cabs = ora.c_abs(w["kd"], ainv, P_)
+            dst += [cext, cabs, cext - cabs]
+        for c in range(3):
+            worst[c] = max(worst[c], abs(got[c] - ref[c]) / abs(ref[c]))
+        lib_vals = (ce_m[q], ca_m[q], cs_m[q])
+        for c in range(3):
+            assert abs(lib_vals[c] - got[c]) <= 1e-9 * abs(got[c]), (r, c, lib_vals[c], got[c])
+    print(f"ellipsoid96 batch of 16, mixed to 2e-7 vs FP64 to 1e-12: max rel err C_ext {worst[0]:.2e}, "
+          f"C_abs {worst[1]:.2e}, C_sca {worst[2]:.2e}", flush=True)
+    assert max(worst) <= 1e-6, worst
+
+
 def test_validation_cube100_efficiencies(lib):
     w = inputs.workload("cube100")
     t, nd = _target(lib, w)
