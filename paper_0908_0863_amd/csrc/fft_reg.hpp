@@ -456,12 +456,13 @@ __global__ void __launch_bounds__(FastPlan<N>::T* RW) k_xb(const cx<R>* __restri
 
 // (T, W, WPE) of the two-level z pass per length and layout: E = N/T a
 // multiple of T; W wavefronts per block, C = W 64/T columns per tile, WPE
-// wavefronts per SIMD.  The tile-blocked layout with E <= 16 runs one
-// wavefront per block: FP32 at three per SIMD (the 96 data registers and the
+// wavefronts per SIMD.  The tile-blocked layout runs one wavefront per
+// block: FP32 with E <= 16 at three per SIMD (the 96 data registers and the
 // spectrum gathers fit 168; 146 against 168 us for four wavefronts at two per
-// SIMD at the 128^3 sphere), FP64 at two (312 against 322 us).  The strided
-// layout keeps four (its rows are runs of C values: 220 us with two
-// wavefronts, 276 with one).
+// SIMD at the 128^3 sphere), FP64 and E = 24 at two (FP64 312 against 322 us
+// at the 128^3 sphere; FP32 length 192, 128 right-hand sides of the 96^3
+// ellipsoid, 7.5 against 8.0 ms).  The strided layout keeps four (its rows
+// are runs of C values: 220 us with two wavefronts, 276 with one).
 // (FP64 with E = 24 is left out: its 16-byte values make the exchange areas
 // of a block 110 KB at N = 192, one wavefront per SIMD.)
 template <typename R, int N, bool BLK>
@@ -470,9 +471,9 @@ struct Z2Shape {
                             : N == 128 ? 8 : N == 192 ? 8 : N == 256 ? 16 : 0;
   static constexpr int T = (sizeof(R) == 8 && T0 > 0 && N / T0 > 16) ? 0 : T0;
   static constexpr bool ok = T > 0;
-  static constexpr bool narrow = BLK && ok && N / T <= 16;
+  static constexpr bool narrow = BLK && ok;
   static constexpr int W = narrow ? 1 : 4;
-  static constexpr int WPE = narrow && sizeof(R) == 4 ? 3 : 2;
+  static constexpr int WPE = narrow && sizeof(R) == 4 && N / T <= 16 ? 3 : 2;
   static constexpr int C = ok ? W * 64 / T : 1;
 };
 
