@@ -414,6 +414,9 @@ def main():
                     help="FP32 inner-solve tolerance (default: 5e-5 for the single-RHS line, 1e-4 for the batch modes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--tune-file", default=None,
+                    help="autotuner record to read and extend (default: a fresh one per run); a profiled run "
+                         "given the file of an earlier run uses the same plans")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the 128^3 / 96^3 x 128 keys (matvec_rates, batched_orientations)")
     ap.add_argument("--fp64", action="store_true", help="--profile-matvec: FP64 vectors")
@@ -467,7 +470,7 @@ def main():
     w = inputs.workload(args.workload)
     K, J, P = w["K"], w["J"], w["P"]
     import tempfile
-    tune_file = os.path.join(tempfile.mkdtemp(prefix="dda_tune_"), "tune.txt")
+    tune_file = args.tune_file or os.path.join(tempfile.mkdtemp(prefix="dda_tune_"), "tune.txt")
     lib = dda.Library(0, tune_cache=tune_file)
     t = dda.Target(lib, K, J, P, w["kd"])
     nd = t.set_occupancy(w["occ"])
