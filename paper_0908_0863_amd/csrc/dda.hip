@@ -267,6 +267,7 @@ struct dda_target {
   // c N_d + n at 2^mlb bits each; the matrix-vector passes read these and the
   // materials' table instead of per-dipole diagonals
   bool comp_bits = false;
+  bool uniform_diag = false;  // one permittivity for every dipole: the passes read a one-entry table
   int mlb = 0;
   DevBuf mbits;
   int prescription = -1;
@@ -649,6 +650,7 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   t->nd = (int64_t)sites.size();
   t->have_alpha = t->have_eps = false;
   t->comp_bits = false;
+  t->uniform_diag = false;
   // everything sized or captured for the previous N_d goes: solver vectors
   // (ensure_solver_ws grows them by count, not bytes), the captured
   // iteration (its launches bake in N_d, block counts and slot offsets) and
@@ -758,6 +760,24 @@ int dda_set_permittivity(dda_target* t, const double* eps, int prescription) {
     CHK(t->d1.ensure(nd * sizeof(c64)));
     HIPCHK(hipMemcpy(t->d1.p, d1.data(), nd * sizeof(c64), hipMemcpyHostToDevice));
   }
+  // one permittivity for all dipoles (a homogeneous target): the
+  // matrix-vector passes take alpha^{-1} from a one-entry table instead of
+  // gathering the per-dipole arrays (the solver's outer kernels keep those)
+  bool uniform = true;
+  for (size_t n = 1; n < nd && uniform; ++n) uniform = eps[2 * n] == eps[0] && eps[2 * n + 1] == eps[1];
+  t->uniform_diag = false;
+  if (uniform) {
+    const c32 f0 = mk((float)a0[0].x, (float)a0[0].y), f1 = mk((float)a1[0].x, (float)a1[0].y);
+    CHK(t->p64.mt0.ensure(sizeof(c64)));
+    CHK(t->p64.mt1.ensure(sizeof(c64)));
+    CHK(t->p32.mt0.ensure(sizeof(c32)));
+    CHK(t->p32.mt1.ensure(sizeof(c32)));
+    HIPCHK(hipMemcpy(t->p64.mt0.p, &a0[0], sizeof(c64), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(t->p64.mt1.p, &a1[0], sizeof(c64), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(t->p32.mt0.p, &f0, sizeof(c32), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(t->p32.mt1.p, &f1, sizeof(c32), hipMemcpyHostToDevice));
+    t->uniform_diag = true;
+  }
   t->prescription = prescription;
   t->have_alpha = t->have_eps = true;
   t->aniso = false;
@@ -784,6 +804,7 @@ int dda_set_polarizability(dda_target* t, const double* alpha) {
   t->have_eps = false;
   t->aniso = false;
   t->comp_bits = false;
+  t->uniform_diag = false;
   return DDA_OK;
 }
 
@@ -840,6 +861,7 @@ int dda_set_composition(dda_target* t, int nmat, const double* eps, const uint8_
   HIPCHK(hipMemcpy(t->p32.mt1.p, mf1.data(), nmat * sizeof(c32), hipMemcpyHostToDevice));
   t->mlb = mlb;
   t->comp_bits = true;
+  t->uniform_diag = false;
   t->prescription = prescription;
   t->have_alpha = true;
   t->have_eps = false;  // the permittivity gradient is defined per isotropic dipole
@@ -1335,6 +1357,10 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   if (t->comp_bits) {
     va.mbits = t->mbits.as<uint32_t>();
     va.mlb = t->mlb;
+    va.mt0 = b.mt0.p;
+    va.mt1 = t->has_a1 ? b.mt1.p : nullptr;
+  } else if (t->uniform_diag) {
+    va.uniform = 1;
     va.mt0 = b.mt0.p;
     va.mt1 = t->has_a1 ? b.mt1.p : nullptr;
   }
@@ -2433,6 +2459,7 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
                                   (uintptr_t)t->occ.p,
                                   (uintptr_t)t->fuse_qmr,
                                   (uintptr_t)t->comp_bits,
+                                  (uintptr_t)t->uniform_diag,
                                   (uintptr_t)t->mbits.p,
                                   (uintptr_t)B.mt0.p,
                                   (uintptr_t)B.mt1.p};

@@ -218,12 +218,16 @@ struct VecArgs {
   int mlb = 0;
   const void* mt0 = nullptr;
   const void* mt1 = nullptr;
+  // a homogeneous target (one permittivity for every dipole): alpha^{-1} =
+  // mt0[0] + S mt1[0] for all of them, no per-dipole gathers
+  int uniform = 0;
 };
 
 // alpha^{-1} of component c of dipole n for orientation factor S
 template <typename R>
 __device__ __forceinline__ cx<R> diag_at(const cx<R>* __restrict__ a0, const cx<R>* __restrict__ a1,
                                          const VecArgs& a, int c, long n, R S) {
+  if (a.uniform) return diag_of((const cx<R>*)a.mt0, (const cx<R>*)a.mt1, S, 0);
   if (a.mbits) {
     const long bit = ((long)c * a.nd + n) << a.mlb;
     const uint32_t w = a.mbits[bit >> 5];
