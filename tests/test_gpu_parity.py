@@ -194,6 +194,37 @@ def test_solve_mixed_sphere16(lib, solver, param):
     assert _rel(P[0].cpu().numpy(), Po) < 1e-8
 
 
+@pytest.mark.parametrize("sched", [0, 2, 5, 6])
+def test_matvec_per_dipole_and_homogeneous_permittivity(lib, sched):
+    """The passes' two diagonal paths: per-dipole permittivities (gathered
+    alpha^{-1} arrays) and a homogeneous target (the one-entry table), each
+    against the dense oracle element by element in FP64 and FP32, in the
+    Jacobi form with an LDR S per right-hand side; then the homogeneous
+    target is given per-dipole values again and follows them."""
+    from paper_0908_0863_amd import dda
+    occ = inputs.sphere(16)
+    kd = 0.41
+    t, nd = _target(lib, occ, kd, 2.1 + 0.2j)
+    try:
+        t.set_option(dda.DDA_OPT_SCHEDULE, sched)
+    except dda.DDAError:
+        pytest.skip(f"no schedule {sched}")
+    sites = ora.sites_of(occ)
+    rng = np.random.default_rng(91)
+    x = inputs.complex_gaussian(92, (2, 3, nd))
+    S = [0.0, 0.27]
+    for eps in (np.full(nd, 2.1 + 0.2j), 2.0 + rng.random(nd) + 1j * (0.05 + 0.3 * rng.random(nd))):
+        t.set_permittivity(eps, "ldr")
+        y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=True).cpu().numpy()
+        y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=True).cpu().numpy()
+        for r in range(2):
+            ainv = ora.alpha_inv(eps, kd, "ldr", S[r])
+            sc = 1.0 / np.sqrt(ainv)
+            yo = sc * ora.dense_matvec(sites, kd, ainv, sc * x[r])
+            _close(y[r], yo, 1e-12, (sched, r))
+            _close(y32[r], yo, 2e-6, (sched, r))
+
+
 @pytest.mark.parametrize("xsel", [0, 1, 2])
 @pytest.mark.parametrize("sched", [0, 5, 6])
 @pytest.mark.parametrize("shape", [(16, 16, 16), (70, 9, 33), (7, 20, 12)])
