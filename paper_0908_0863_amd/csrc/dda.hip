@@ -1726,8 +1726,10 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   std::vector<int> cand = {0};
   if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
   if (fast_size(t->Ppp)) cand.push_back(3);
-  if (z2_size<R>(t->Ppp)) cand.push_back(5);
+  // the tile-blocked schedule before the strided one: it measured as fast or
+  // faster on every workload here, so near-ties keep it
   if (z2_size<R>(t->Ppp) && fast_size(t->Kpp)) cand.push_back(6);
+  if (z2_size<R>(t->Ppp)) cand.push_back(5);
   for (int d : xy_candidates<R>(t)) cand.push_back(d);
   int best = 0;
   if (cand.size() > 1) {
