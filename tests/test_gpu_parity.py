@@ -426,13 +426,14 @@ def test_matvec_two_level_z_pass(lib, shape, rb, sched):
 
 
 @pytest.mark.parametrize("ylog", [0, 1, 2])
-@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 16, 5), (13, 24, 7), (5, 12, 9)])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 16, 5), (13, 24, 7), (5, 12, 9), (9, 64, 6), (5, 128, 4)])
 def test_y_tile_variants(lib, shape, ylog):
     """DDA_OPT_Y_TILE: the y passes with 2^ylog times the default tile
-    (ragged last tiles where K is not a multiple of it) against the dense
-    oracle element by element in FP64 and FP32; a QMR_sym solve whose step
-    is fused into the widened y-forward pass (its partial counts follow the
-    tile) against the oracle's LU.  A width FP32 lacks is DDA_EINVAL."""
+    (ragged last tiles where K is not a multiple of it; padded y lengths 24
+    to 256) against the dense oracle element by element in FP64 and FP32; a
+    QMR_sym solve whose step is fused into the widened y-forward pass (its
+    partial counts follow the tile) against the oracle's LU.  A width FP32
+    lacks is DDA_EINVAL."""
     from paper_0908_0863_amd import dda
     K, J, P = shape
     occ = np.ones((P, J, K), np.uint8)  # a filled lattice keeps the QMR step fused
