@@ -331,6 +331,35 @@ int dda_target_set_option(dda_target *t, int option, int value);
  * the spectrum build (Table 2). */
 int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
 
+/* The padded FFT lengths K'', J'', P'' of the circulant embedding (Sec. 3:
+ * every length n'' >= 2n - 1 embeds the Toeplitz blocks, so the product does
+ * not depend on the choice, up to rounding).  0 for an axis takes the default
+ * rule (the smallest 2^a 3^b 5^c length >= 2n - 1, or the smallest one with
+ * register-resident kernels when that is at most 30% longer).  Each nonzero
+ * length must be >= 2n - 1, of the form 2^a 3^b 5^c and at most
+ * max(16, 4 (2n - 1)); DDA_EINVAL otherwise, and when a schedule forced with
+ * DDA_OPT_SCHEDULE does not exist at the new lengths (nothing changes then).
+ * New lengths drop the spectrum (dda_build_spectrum must run again before a
+ * product or solve: DDA_ESTATE until then), the product workspaces and the
+ * captured iterations; the lengths already in use change nothing. */
+int dda_target_set_padding(dda_target *t, int Kpp, int Jpp, int Ppp);
+
+/* Padded lengths chosen by measurement, the analogue of planning an FFT by
+ * measuring (Sec. 3).  Per axis the candidates are the default rule's length,
+ * the smallest 2^a 3^b 5^c length >= 2n - 1 and the smallest length >= 2n - 1
+ * with register-resident kernels when it is at most twice that; for every
+ * combination (those with a forced schedule only) the spectrum is built, the
+ * schedule tuned and `nrhs` products in `precision` timed on hip_stream with
+ * HIP events (Jacobi form, S = 0, a fixed input pattern).  A combination
+ * must beat the default rule's by more than 3%.  The target keeps the
+ * fastest lengths with their spectrum built, and lengths[0..2] (may be NULL)
+ * receives them.  The choice is kept in the library handle per (lattice,
+ * nrhs, precision) and appended to the tune-cache file, so a later call only
+ * sets the lengths and builds the spectrum.  Needs the occupancy and the
+ * polarisability (DDA_ESTATE otherwise); DDA_EINVAL for nrhs < 1 or an
+ * unknown precision.  Allocates and frees two vectors of nrhs x 3 x N_d. */
+int dda_tune_padding(dda_target *t, int nrhs, int precision, int *lengths /* 3, or NULL */, void *hip_stream);
+
 /* Copy the spectrum [6][P_h][J_h][K_h] (complex128 or complex64) to out_dev. */
 int dda_get_spectrum(dda_target *t, int precision, void *out_dev, void *hip_stream);
 

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -402,6 +403,60 @@ static int launch_strided_mirror(const cx<R>* in, cx<R>* out, StridedArgs a, int
 template <typename R>
 static int ylog_max(const dda_target* t);
 
+static const char* schedule_missing(int value, int K, int J, int Kpp, int Jpp, int Ppp);
+
+// the captured inner iterations (their launches bake in sizes and addresses)
+static void drop_graphs(dda_target* t) {
+  for (int g = 0; g < 2; ++g) {
+    if (t->graph_exec[g]) (void)hipGraphExecDestroy(t->graph_exec[g]);
+    t->graph_exec[g] = nullptr;
+    t->graph_key[g].clear();
+  }
+}
+
+// Padded lengths K'', J'', P'' and what follows from them: half lengths,
+// radix plans and the twiddle tables exp(-2 pi i m / n) (host libm in FP64,
+// FP32 by rounding).  What was built or captured for other lengths goes: the
+// spectrum, the product workspaces and the captured iterations.
+static int set_lengths(dda_target* t, int Kpp, int Jpp, int Ppp) {
+  const int ns[3] = {Kpp, Jpp, Ppp};
+  for (int a = 0; a < 3; ++a) {
+    const int n = ns[a];
+    std::vector<c64> w(n);
+    std::vector<c32> wf(n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = 2.0 * M_PI * (double)m / (double)n;
+      w[m] = mk(std::cos(ang), -std::sin(ang));
+      wf[m] = mk((float)w[m].x, (float)w[m].y);
+    }
+    CHK(t->p64.tw[a].ensure(n * sizeof(c64)));
+    CHK(t->p32.tw[a].ensure(n * sizeof(c32)));
+    if (hipMemcpy(t->p64.tw[a].p, w.data(), n * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->p32.tw[a].p, wf.data(), n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(DDA_EDEVICE, "twiddle upload failed");
+  }
+  t->Kpp = Kpp;
+  t->Jpp = Jpp;
+  t->Ppp = Ppp;
+  t->Kh = Kpp / 2 + 1;
+  t->Jh = Jpp / 2 + 1;
+  t->Ph = Ppp / 2 + 1;
+  t->fx = make_desc(Kpp);
+  t->fy = make_desc(Jpp);
+  t->fz = make_desc(Ppp);
+  t->spec_ready = false;
+  t->p32.cap = t->p64.cap = 0;
+  drop_graphs(t);
+  return DDA_OK;
+}
+
+// a padded length the transforms take for lattice extent n: at least 2n - 1
+// (Sec. 3), of the form 2^a 3^b 5^c, and at most max(16, 4 (2n - 1))
+static bool padding_ok(int n, int npp) {
+  const long m = 2L * n - 1;
+  return npp >= m && smooth235(npp) && npp <= std::max(16L, 4 * m);
+}
+
 extern "C" {
 
 const char* dda_last_error(void) { return g_err.c_str(); }
@@ -503,37 +558,11 @@ int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target**
   t->J = J;
   t->P = P;
   t->kd = kd;
-  t->Kpp = fft_size_at_least(2 * K - 1);
-  t->Jpp = fft_size_at_least(2 * J - 1);
-  t->Ppp = fft_size_at_least(2 * P - 1);
-  t->Kh = t->Kpp / 2 + 1;
-  t->Jh = t->Jpp / 2 + 1;
-  t->Ph = t->Ppp / 2 + 1;
-  t->fx = make_desc(t->Kpp);
-  t->fy = make_desc(t->Jpp);
-  t->fz = make_desc(t->Ppp);
-  // twiddle tables exp(-2 pi i m / n), from host libm in FP64; FP32 by rounding
-  const int ns[3] = {t->Kpp, t->Jpp, t->Ppp};
-  for (int a = 0; a < 3; ++a) {
-    const int n = ns[a];
-    std::vector<c64> w(n);
-    std::vector<c32> wf(n);
-    for (int m = 0; m < n; ++m) {
-      const double ang = 2.0 * M_PI * (double)m / (double)n;
-      w[m] = mk(std::cos(ang), -std::sin(ang));
-      wf[m] = mk((float)w[m].x, (float)w[m].y);
-    }
-    int rc = t->p64.tw[a].ensure(n * sizeof(c64));
-    if (rc == DDA_OK) rc = t->p32.tw[a].ensure(n * sizeof(c32));
-    if (rc != DDA_OK) {
-      delete t;
-      return rc;
-    }
-    if (hipMemcpy(t->p64.tw[a].p, w.data(), n * sizeof(c64), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t->p32.tw[a].p, wf.data(), n * sizeof(c32), hipMemcpyHostToDevice) != hipSuccess) {
-      delete t;
-      return fail(DDA_EDEVICE, "dda_target_create: twiddle upload failed");
-    }
+  const int rc = set_lengths(t, fft_size_at_least(2 * K - 1), fft_size_at_least(2 * J - 1),
+                             fft_size_at_least(2 * P - 1));
+  if (rc != DDA_OK) {
+    delete t;
+    return rc;
   }
   *out = t;
   return DDA_OK;
@@ -550,20 +579,9 @@ int dda_target_set_option(dda_target* t, int option, int value) {
   if (!t) return fail(DDA_EINVAL, "dda_target_set_option: NULL target");
   switch (option) {
     case DDA_OPT_SCHEDULE: {
-      if (value == 1 && !(fast_size(t->Kpp) && fast_size(t->Ppp)))
-        return fail(DDA_EINVAL, "dda_target_set_option: no z-contiguous schedule for this lattice");
-      if (value == 3 && !fast_size(t->Ppp))
-        return fail(DDA_EINVAL, "dda_target_set_option: no component-split z pass for this lattice");
-      if (value == 5 && !z2_size(t->Ppp))
-        return fail(DDA_EINVAL, "dda_target_set_option: no two-level z pass for this lattice");
-      if (value == 6 && !(z2_size(t->Ppp) && fast_size(t->Kpp)))
-        return fail(DDA_EINVAL, "dda_target_set_option: no tile-blocked schedule for this lattice");
-      if (value >= 2 && value != 3 && value != 5 && value != 6) {
-        const std::vector<int> c64c = xy_candidates<double>(t), c32c = xy_candidates<float>(t);
-        if (std::find(c64c.begin(), c64c.end(), value) == c64c.end() ||
-            std::find(c32c.begin(), c32c.end(), value) == c32c.end())
-          return fail(DDA_EINVAL, "dda_target_set_option: no fused schedule with split %d for this lattice", value);
-      }
+      if (value > 0)
+        if (const char* why = schedule_missing(value, t->K, t->J, t->Kpp, t->Jpp, t->Ppp))
+          return fail(DDA_EINVAL, "dda_target_set_option: schedule %d: %s for this lattice", value, why);
       t->forced_sched = value < 0 ? -1 : value;
       return DDA_OK;
     }
@@ -620,6 +638,25 @@ int dda_target_info(const dda_target* t, int64_t* dims) {
   return DDA_OK;
 }
 
+int dda_target_set_padding(dda_target* t, int Kpp, int Jpp, int Ppp) {
+  if (!t) return fail(DDA_EINVAL, "dda_target_set_padding: NULL target");
+  const int n[3] = {t->K, t->J, t->P};
+  int v[3] = {Kpp, Jpp, Ppp};
+  for (int a = 0; a < 3; ++a) {
+    if (v[a] == 0) v[a] = fft_size_at_least(2 * n[a] - 1);
+    if (!padding_ok(n[a], v[a]))
+      return fail(DDA_EINVAL, "dda_target_set_padding: length %d for extent %d (needs >= %d, 2^a 3^b 5^c, <= %ld)",
+                  v[a], n[a], 2 * n[a] - 1, std::max(16L, 4 * (2L * n[a] - 1)));
+  }
+  if (t->forced_sched > 0)
+    if (const char* why = schedule_missing(t->forced_sched, t->K, t->J, v[0], v[1], v[2]))
+      return fail(DDA_EINVAL, "dda_target_set_padding: forced schedule %d: %s at %dx%dx%d", t->forced_sched, why,
+                  v[0], v[1], v[2]);
+  if (v[0] == t->Kpp && v[1] == t->Jpp && v[2] == t->Ppp) return DDA_OK;
+  HIPCHK(hipSetDevice(t->lib->device));
+  return set_lengths(t, v[0], v[1], v[2]);
+}
+
 int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   if (!t || !occ) return fail(DDA_EINVAL, "dda_set_occupancy: NULL argument");
   HIPCHK(hipSetDevice(t->lib->device));
@@ -660,11 +697,7 @@ int dda_set_occupancy(dda_target* t, const uint8_t* occ, int64_t* nd_out) {
   t->p32.vec_cap = t->p32.vec_slots = 0;
   t->p64.vec_cap = t->p64.vec_slots = 0;
   t->p32.vec_nd = t->p64.vec_nd = 0;
-  for (int g = 0; g < 2; ++g) {
-    if (t->graph_exec[g]) (void)hipGraphExecDestroy(t->graph_exec[g]);
-    t->graph_exec[g] = nullptr;
-    t->graph_key[g].clear();
-  }
+  drop_graphs(t);
   t->solve_S.clear();
   {
     int lo[3] = {t->K, t->J, t->P}, hi[3] = {-1, -1, -1};
@@ -1242,15 +1275,36 @@ static size_t xy_inv_lds(int K) {
 // Residue splits D of the fused xy-plane passes that exist for this lattice
 // and fit the LDS budget (both directions).
 template <typename R>
-static std::vector<int> xy_candidates(const dda_target* t) {
+static std::vector<int> xy_candidates_of(int K, int J, int Kpp, int Jpp) {
   std::vector<int> out;
-  if (t->Kpp != t->Jpp || 2 * t->K > t->Kpp || 2 * t->J > t->Jpp) return out;
-#define DDA_CASE(NN, D)                                                                              \
-  if (t->Kpp == NN && xy_fwd_lds<R, NN, D>(t->K) <= kXYLds && xy_inv_lds<R, NN, D>(t->K) <= kXYLds) \
+  if (Kpp != Jpp || 2 * K > Kpp || 2 * J > Jpp) return out;
+#define DDA_CASE(NN, D)                                                                      \
+  if (Kpp == NN && xy_fwd_lds<R, NN, D>(K) <= kXYLds && xy_inv_lds<R, NN, D>(K) <= kXYLds) \
     out.push_back(D);
   DDA_XY_SIZES(DDA_CASE)
 #undef DDA_CASE
   return out;
+}
+template <typename R>
+static std::vector<int> xy_candidates(const dda_target* t) {
+  return xy_candidates_of<R>(t->K, t->J, t->Kpp, t->Jpp);
+}
+
+// why schedule `value` does not exist for a lattice padded to Kpp x Jpp x
+// Ppp (nullptr: it exists in both precisions)
+static const char* schedule_missing(int value, int K, int J, int Kpp, int Jpp, int Ppp) {
+  if (value == 1 && !(fast_size(Kpp) && fast_size(Ppp))) return "no z-contiguous schedule";
+  if (value == 3 && !fast_size(Ppp)) return "no component-split z pass";
+  if (value == 5 && !z2_size(Ppp)) return "no two-level z pass";
+  if (value == 6 && !(z2_size(Ppp) && fast_size(Kpp))) return "no tile-blocked schedule";
+  if (value >= 2 && value != 3 && value != 5 && value != 6) {
+    const std::vector<int> c64c = xy_candidates_of<double>(K, J, Kpp, Jpp),
+                           c32c = xy_candidates_of<float>(K, J, Kpp, Jpp);
+    if (std::find(c64c.begin(), c64c.end(), value) == c64c.end() ||
+        std::find(c32c.begin(), c32c.end(), value) == c32c.end())
+      return "no fused schedule with this split";
+  }
+  return nullptr;
 }
 
 template <typename R, int NN, int D>
@@ -1819,6 +1873,138 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
   if (!t->lib->tune_path.empty()) {
     std::ofstream f(t->lib->tune_path, std::ios::app);
     if (f) f << key << " = " << best << "\n";
+  }
+  return DDA_OK;
+}
+
+// Padded lengths tried for lattice extent n: the smallest 2^a 3^b 5^c length
+// >= 2n - 1, and the smallest length with register-resident kernels when it
+// is at most twice that; the default rule's choice first.
+static std::vector<int> padding_candidates(int n) {
+  const int m = 2 * n - 1;
+  std::vector<int> c = {fft_size_at_least(m)};
+  int sm = m;
+  while (!smooth235(sm)) ++sm;
+  int f = m;
+  while (!fast_size(f) && f <= 2 * sm) ++f;
+  for (int v : {sm, f})
+    if (padding_ok(n, v) && (v == sm || fast_size(v)) && std::find(c.begin(), c.end(), v) == c.end())
+      c.push_back(v);
+  return c;
+}
+
+static std::string padding_key(const dda_target* t, int nrhs, int precision) {
+  std::ostringstream k;
+  k << "pad " << t->K << "x" << t->J << "x" << t->P << " nrhs " << nrhs << " "
+    << (precision == DDA_FP32 ? "fp32" : "fp64");
+  return k.str();
+}
+
+// One padding's product time: spectrum built for it, schedule tuned for it,
+// then the fastest of three rounds of three products (after two warm-ups).
+template <typename R>
+static int time_padding(dda_target* t, int nrhs, const cx<R>* x, cx<R>* y, hipStream_t st, hipEvent_t e0,
+                        hipEvent_t e1, float* out_ms) {
+  CHK(dda_build_spectrum(t, st));
+  CHK(ensure_matvec_ws<R>(t, nrhs));
+  const double* dS = t->S.as<double>();
+  CHK(autotune<R>(t, nrhs, dS, 1, x, y, st));
+  for (int w = 0; w < 2; ++w) CHK(matvec_T<R>(t, nrhs, dS, 1, x, y, nullptr, st));
+  float best = 1e30f;
+  for (int round = 0; round < 3; ++round) {
+    HIPCHK(hipEventRecord(e0, st));
+    for (int w = 0; w < 3; ++w) CHK(matvec_T<R>(t, nrhs, dS, 1, x, y, nullptr, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    best = std::min(best, ms);
+  }
+  *out_ms = best;
+  return DDA_OK;
+}
+
+template <typename R>
+static int tune_padding_T(dda_target* t, int nrhs, int precision, hipStream_t st) {
+  const std::vector<int> ck = padding_candidates(t->K), cj = padding_candidates(t->J), cp = padding_candidates(t->P);
+  std::vector<std::array<int, 3>> combos;
+  for (int a : ck)
+    for (int b : cj)
+      for (int c : cp)
+        if (!(t->forced_sched > 0 && schedule_missing(t->forced_sched, t->K, t->J, a, b, c)))
+          combos.push_back({a, b, c});
+  if (combos.empty()) return DDA_OK;  // no candidate carries the forced schedule: the lengths stay
+  const std::string key = padding_key(t, nrhs, precision);
+  int pick = -1;
+  {
+    std::lock_guard<std::mutex> g(t->lib->tune_mu);
+    auto it = t->lib->tuned.find(key);
+    if (it != t->lib->tuned.end() && it->second >= 0 && it->second < (int)combos.size()) pick = it->second;
+  }
+  if (pick < 0 && combos.size() == 1) pick = 0;
+  if (pick < 0) {
+    // product inputs: a fixed finite byte pattern (timing only), S = 0
+    DevBuf xb, yb;
+    const size_t vb = (size_t)nrhs * 3 * t->nd * sizeof(cx<R>);
+    CHK(xb.ensure(vb));
+    CHK(yb.ensure(vb));
+    HIPCHK(hipMemsetAsync(xb.p, 0x3F, vb, st));
+    CHK(ensure_scratch(t, nrhs));
+    HIPCHK(hipMemsetAsync(t->S.p, 0, nrhs * sizeof(double), st));
+    const int prof = t->lib->prof, mv = t->matvecs;
+    t->lib->prof = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = DDA_OK;
+    float best_ms = 1e30f;
+    for (size_t i = 0; i < combos.size() && rc == DDA_OK; ++i) {
+      rc = set_lengths(t, combos[i][0], combos[i][1], combos[i][2]);
+      float ms = 1e30f;
+      if (rc == DDA_OK) rc = time_padding<R>(t, nrhs, xb.as<cx<R>>(), yb.as<cx<R>>(), st, e0, e1, &ms);
+      // a later padding must win by more than 3% (near-ties keep the
+      // default rule's lengths, so that repeated tunings agree)
+      if (rc == DDA_OK && (pick < 0 || ms < 0.97f * best_ms)) {
+        best_ms = ms;
+        pick = (int)i;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    t->lib->prof = prof;
+    t->matvecs = mv;
+    HIPCHK(hipStreamSynchronize(st));  // the timing buffers are freed on return
+    CHK(rc);
+    std::lock_guard<std::mutex> g(t->lib->tune_mu);
+    if (!t->lib->tuned.count(key)) {
+      t->lib->tuned[key] = pick;
+      if (!t->lib->tune_path.empty()) {
+        std::ofstream f(t->lib->tune_path, std::ios::app);
+        if (f) f << key << " = " << pick << "\n";
+      }
+    }
+  }
+  const std::array<int, 3>& v = combos[pick];
+  if (v[0] != t->Kpp || v[1] != t->Jpp || v[2] != t->Ppp) CHK(set_lengths(t, v[0], v[1], v[2]));
+  if (!t->spec_ready) CHK(dda_build_spectrum(t, st));
+  return DDA_OK;
+}
+
+extern "C" int dda_tune_padding(dda_target* t, int nrhs, int precision, int* lengths, void* hip_stream) {
+  if (!t) return fail(DDA_EINVAL, "dda_tune_padding: NULL target");
+  if (nrhs < 1) return fail(DDA_EINVAL, "dda_tune_padding: nrhs = %d", nrhs);
+  if (precision != DDA_FP64 && precision != DDA_FP32)
+    return fail(DDA_EINVAL, "dda_tune_padding: precision %d", precision);
+  if (t->nd <= 0) return fail(DDA_ESTATE, "dda_tune_padding: occupancy not set");
+  if (!t->have_alpha) return fail(DDA_ESTATE, "dda_tune_padding: polarisability not set");
+  HIPCHK(hipSetDevice(t->lib->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  CHK(precision == DDA_FP64 ? tune_padding_T<double>(t, nrhs, precision, st)
+                            : tune_padding_T<float>(t, nrhs, precision, st));
+  if (lengths) {
+    lengths[0] = t->Kpp;
+    lengths[1] = t->Jpp;
+    lengths[2] = t->Ppp;
   }
   return DDA_OK;
 }

@@ -69,7 +69,7 @@ EXPORTS = ["dda_open", "dda_close", "dda_target_create", "dda_target_destroy", "
            "dda_matvec_noalloc", "dda_solve", "dda_solve_orientation_factors", "dda_batch_solve",
            "dda_incident_field", "dda_cross_sections", "dda_far_field", "dda_csca_quadrature", "dda_mueller",
            "dda_grad_cabs_eps", "dda_target_set_option",
-           "dda_target_info",
+           "dda_target_info", "dda_target_set_padding", "dda_tune_padding",
            "dda_get_spectrum", "dda_profile_enable", "dda_profile_read", "dda_profile_reset",
            "dda_last_error"]
 
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "dda_grad_cabs_eps": (i, [vp, P(dda_solve_opts), i, vp, vp, vp, vp]),
         "dda_target_set_option": (i, [vp, i, i]),
         "dda_target_info": (i, [vp, vp]),
+        "dda_target_set_padding": (i, [vp, i, i, i]),
+        "dda_tune_padding": (i, [vp, i, i, vp, vp]),
         "dda_get_spectrum": (i, [vp, i, vp, vp]),
         "dda_profile_enable": (i, [vp, i]),
         "dda_profile_read": (i, [vp, vp, vp]),
@@ -297,6 +299,18 @@ class Target:
 
     def set_option(self, option: int, value: int):
         _check(load().dda_target_set_option(self.h, int(option), int(value)))
+
+    def set_padding(self, Kpp: int = 0, Jpp: int = 0, Ppp: int = 0):
+        """Padded FFT lengths (0: the default rule); the spectrum must be
+        built again afterwards."""
+        _check(load().dda_target_set_padding(self.h, int(Kpp), int(Jpp), int(Ppp)))
+
+    def tune_padding(self, nrhs: int = 1, precision: str = "fp32") -> tuple:
+        """Padded lengths chosen by timing products (spectrum built for them)."""
+        out = np.zeros(3, np.int32)
+        prec = DDA_FP32 if precision == "fp32" else DDA_FP64
+        _check(load().dda_tune_padding(self.h, int(nrhs), prec, _np_ptr(out), _stream()))
+        return tuple(int(v) for v in out)
 
     def info(self) -> dict:
         dims = np.zeros(9, np.int64)

@@ -1,0 +1,187 @@
+"""Padded FFT lengths (dda_target_set_padding, dda_tune_padding).
+
+Any padded length n'' >= 2n - 1 embeds the Toeplitz blocks of the
+interaction matrix in a circulant (Sec. 3), so the spectrum at every allowed
+padding must equal the oracle's circulant DFT at that padding, and the
+product and the solution must not depend on the choice: both are checked
+element by element against the dense oracle and its LU.
+"""
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_0908_0863_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_0863_amd import dda as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def lib(dda):
+    return dda.Library(0)
+
+
+def _occ(shape, seed, frac=0.7):
+    rng = np.random.default_rng(seed)
+    occ = (rng.random(shape) < frac).astype(np.uint8)
+    occ.flat[0] = 1
+    return occ
+
+
+def _close(a, b, tol, ctx=None):
+    a, b = np.ravel(a), np.ravel(b)
+    rel = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    assert rel < tol, ("2-norm", ctx, rel)
+    emax = float(np.abs(a - b).max())
+    assert emax <= tol * float(np.abs(b).max()), ("max element", ctx, emax / float(np.abs(b).max()))
+
+
+def _target(dda, lib, occ, kd, eps):
+    P, J, K = occ.shape
+    t = dda.Target(lib, K, J, P, kd)
+    nd = t.set_occupancy(occ)
+    t.set_permittivity(np.full(nd, eps), "ldr")
+    return t, nd
+
+
+# (K, J, P) lattice and the padded lengths to force: minimal 2^a 3^b 5^c
+# lengths (generic kernels), register-resident lengths, over-padding, mixed
+PADDINGS = [
+    ((7, 5, 9), (15, 9, 18)),
+    ((7, 5, 9), (16, 16, 32)),
+    ((7, 5, 9), (20, 12, 24)),
+    ((12, 12, 12), (25, 24, 27)),
+    ((12, 12, 12), (32, 32, 32)),
+    ((16, 8, 10), (32, 16, 20)),
+    ((16, 8, 10), (45, 15, 24)),
+]
+
+
+@pytest.mark.parametrize("shape,pads", PADDINGS)
+def test_forced_padding_matches_oracle(dda, lib, shape, pads):
+    """dda_target_set_padding: the spectrum equals the oracle's circulant DFT
+    at that padding, and the tuned product (FP64 to 1e-12, FP32 to 2e-6)
+    equals the dense product, element by element."""
+    K, J, P = shape
+    occ = _occ((P, J, K), 11)
+    kd, eps = 0.41, 2.2 + 0.15j
+    t, nd = _target(dda, lib, occ, kd, eps)
+    t.set_padding(*pads)
+    t.build_spectrum()
+    i = t.info()
+    assert (i["Kpp"], i["Jpp"], i["Ppp"]) == pads
+    Yg = t.spectrum().cpu().numpy()
+    Yo = ora.circulant_spectrum(K, J, P, *pads, kd)
+    assert Yg.shape == Yo.shape
+    assert np.abs(Yg - Yo).max() <= 1e-13 * np.abs(Yo).max() + 1e-15
+    sites = ora.sites_of(occ)
+    S = [0.0, 0.25]
+    x = inputs.complex_gaussian(13, (2, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=True).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=True).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", S[r])
+        s = 1.0 / np.sqrt(ainv)
+        yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
+        _close(y[r], yo, 1e-12, (shape, pads, r))
+        _close(y32[r], yo, 2e-6, (shape, pads, r))
+
+
+def test_set_padding_rejects_bad_lengths_and_drops_the_spectrum(dda, lib):
+    """Lengths below 2n - 1, with a prime factor above 5 or above
+    max(16, 4 (2n - 1)) are DDA_EINVAL and change nothing; a forced schedule
+    the new lengths lack is DDA_EINVAL; new lengths need a new spectrum
+    (DDA_ESTATE until then); the current lengths change nothing."""
+    occ = _occ((9, 5, 7), 12)
+    t, nd = _target(dda, lib, occ, 0.4, 1.9 + 0.1j)
+    t.build_spectrum()
+    before = t.info()
+    x = torch.from_numpy(inputs.complex_gaussian(14, (1, 3, nd))).cuda()
+    y0 = t.matvec(x).cpu().numpy()
+    for pads in [(12, 0, 0), (0, 14, 0), (0, 0, 7 * 4), (64, 0, 0), (0, 0, 17)]:
+        with pytest.raises(dda.DDAError) as e:
+            t.set_padding(*pads)
+        assert e.value.code == dda.DDA_EINVAL, pads
+    assert t.info() == before
+    assert np.array_equal(t.matvec(x).cpu().numpy(), y0)  # spectrum still there
+    t.set_padding(before["Kpp"], before["Jpp"], before["Ppp"])  # the same lengths: nothing dropped
+    assert np.array_equal(t.matvec(x).cpu().numpy(), y0)
+    # a forced register-resident schedule pins the lengths that carry it
+    t.set_padding(16, 16, 32)
+    t.build_spectrum()
+    t.set_option(dda.DDA_OPT_SCHEDULE, 6)
+    with pytest.raises(dda.DDAError) as e:
+        t.set_padding(15, 9, 18)
+    assert e.value.code == dda.DDA_EINVAL
+    assert (t.info()["Kpp"], t.info()["Jpp"], t.info()["Ppp"]) == (16, 16, 32)
+    t.set_option(dda.DDA_OPT_SCHEDULE, -1)
+    t.set_padding(15, 9, 18)
+    with pytest.raises(dda.DDAError) as e:
+        t.matvec(x)
+    assert e.value.code == dda.DDA_ESTATE
+    t.build_spectrum()
+    _close(t.matvec(x).cpu().numpy(), y0, 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_after_padding_change_matches_lu(dda, lib, precision):
+    """A solve (its iteration captured as a graph) before and after new
+    lengths: both agree with the oracle's LU to 1e-10 (no launch captured for
+    the old lengths is replayed)."""
+    occ = _occ((6, 7, 8), 15)
+    kd, eps = 0.5, 2.0 + 0.2j
+    t, nd = _target(dda, lib, occ, kd, eps)
+    sites = ora.sites_of(occ)
+    khat = np.array([[0.0, 0.0, 1.0]])
+    ehat = np.array([[1.0, 0.0, 0.0]])
+    Pl = ora.solve_dense(sites, kd, ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0),
+                         ora.einc(sites, kd, khat[0], ehat[0]))
+    for pads in [(0, 0, 0), (20, 15, 12), (16, 16, 16), (0, 0, 0)]:
+        t.set_padding(*pads)
+        t.build_spectrum()
+        for solver in ("qmr_sym", "bicgstab"):
+            P_, info = t.solve(khat=khat, ehat=ehat, solver=solver, precision=precision, tol=1e-12)
+            assert info[0]["converged"], (pads, solver, info)
+            _close(P_.cpu().numpy()[0], Pl, 1e-10, (pads, solver))
+
+
+def test_tune_padding_picks_a_candidate_and_records_it(dda, tmp_path):
+    """dda_tune_padding: the chosen lengths are among the candidates, the
+    spectrum is built for them and the product equals the dense one; the
+    choice goes to the tune file, and a second library reads it back."""
+    path = str(tmp_path / "tune.txt")
+    lib1 = dda.Library(0, tune_cache=path)
+    occ = _occ((5, 6, 5), 16)
+    kd, eps = 0.45, 1.8 + 0.05j
+    t, nd = _target(dda, lib1, occ, kd, eps)
+    with pytest.raises(dda.DDAError) as e:
+        t.tune_padding(0, "fp32")
+    assert e.value.code == dda.DDA_EINVAL
+    pads = t.tune_padding(2, "fp32")
+    # candidates per axis: the minimal 2^a 3^b 5^c length and the smallest
+    # register-resident one (K = P = 5: 9 or 16; J = 6: 12 or 16)
+    assert pads[0] in (9, 16) and pads[1] in (12, 16) and pads[2] in (9, 16), pads
+    i = t.info()
+    assert (i["Kpp"], i["Jpp"], i["Ppp"]) == pads
+    lines = [l for l in open(path).read().splitlines() if l.startswith("pad ")]
+    assert lines == ["pad 5x6x5 nrhs 2 fp32 = " + lines[0].split(" = ")[1]], lines
+    sites = ora.sites_of(occ)
+    x = inputs.complex_gaussian(17, (1, 3, nd))
+    ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0)
+    yo = ora.dense_matvec(sites, kd, ainv, x[0])
+    _close(t.matvec(torch.from_numpy(x).cuda()).cpu().numpy()[0], yo, 1e-12)
+    assert t.tune_padding(2, "fp32") == pads  # recorded: same lengths
+    lib2 = dda.Library(0, tune_cache=path)
+    t2, _ = _target(dda, lib2, occ, kd, eps)
+    assert t2.tune_padding(2, "fp32") == pads
+    _close(t2.matvec(torch.from_numpy(x).cuda()).cpu().numpy()[0], yo, 1e-12)
+    assert [l for l in open(path).read().splitlines() if l.startswith("pad ")] == lines
