@@ -335,7 +335,8 @@ int dda_target_info(const dda_target *t, int64_t *dims /* 9 */);
  * every length n'' >= 2n - 1 embeds the Toeplitz blocks, so the product does
  * not depend on the choice, up to rounding).  0 for an axis takes the default
  * rule (the smallest 2^a 3^b 5^c length >= 2n - 1, or the smallest one with
- * register-resident kernels when that is at most 30% longer).  Each nonzero
+ * register-resident kernels when that is at most 30% longer: 2^k and 3 2^k,
+ * and for J'' also 5 2^k and 25 2^k).  Each nonzero
  * length must be >= 2n - 1, of the form 2^a 3^b 5^c and at most
  * max(16, 4 (2n - 1)); DDA_EINVAL otherwise, and when a schedule forced with
  * DDA_OPT_SCHEDULE does not exist at the new lengths (nothing changes then).

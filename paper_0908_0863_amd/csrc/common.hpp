@@ -64,16 +64,22 @@ using c32 = cx<float>;
 
 constexpr int kMaxStages = 16;
 
-// Sum of two complex values over a block of any size <= 1024 (a multiple of
-// the 64-lane wavefront), in a fixed order; result valid in thread 0.
+// Sum of two complex values over a block of any size up to 1024 threads, in
+// a fixed order; result valid in thread 0.
 __device__ __forceinline__ void block_sum2_any(cx<double>& v0, cx<double>& v1) {
   __shared__ cx<double> sh[2][16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  // lanes of this wavefront that exist (a last, partial wavefront adds no
+  // value from the lanes it lacks)
+  const int nact = min(64, (int)blockDim.x - (wv << 6));
   double a[4] = {v0.x, v0.y, v1.x, v1.y};
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_down(a[q], off, 64);
+      if (lane + off < nact) a[q] += o;
+    }
   if (lane == 0) {
     sh[0][wv] = mk(a[0], a[1]);
     sh[1][wv] = mk(a[2], a[3]);

@@ -110,6 +110,18 @@ static bool fast_size(int n) {
       return false;
   }
 }
+// ... and those with register-resident y passes: the above and 5 2^k, 25 2^k
+#define DDA_FAST_Y_SIZES(X) DDA_FAST_SIZES(X) X(80) X(160) X(320) X(100) X(200) X(400)
+static bool fast_y_size(int n) {
+  switch (n) {
+#define DDA_CASE(N) case N:
+    DDA_FAST_Y_SIZES(DDA_CASE)
+#undef DDA_CASE
+    return true;
+    default:
+      return false;
+  }
+}
 
 // lengths with a two-level z pass (fft_reg.hpp) in precision R
 template <typename R = float>
@@ -142,13 +154,14 @@ static int z2_cols(int n) {
 // Padded FFT length for a lattice extent: any n'' >= 2n - 1 embeds the
 // Toeplitz matrix in a circulant (Sec. 3).  Take the smallest 2^a 3^b 5^c
 // length, or the smallest length with a register-resident kernel when it is
-// at most 30% longer.
-static int fft_size_at_least(int m) {
+// at most 30% longer (for y, `yax`: a register-resident y pass).
+static int fft_size_at_least(int m, bool yax = false) {
+  auto fast = [yax](int v) { return yax ? fast_y_size(v) : fast_size(v); };
   int n = std::max(1, m);
   while (!smooth235(n)) ++n;
   int f = std::max(1, m);
-  while (!fast_size(f) && f < 4 * n) ++f;
-  if (fast_size(f) && 10 * f <= 13 * n) return f;  // register-resident kernels beat generic ones up to +30%
+  while (!fast(f) && f < 4 * n) ++f;
+  if (fast(f) && 10 * f <= 13 * n) return f;  // register-resident kernels beat generic ones up to +30%
   return n;
 }
 
@@ -558,7 +571,7 @@ int dda_target_create(dda_lib* lib, int K, int J, int P, double kd, dda_target**
   t->J = J;
   t->P = P;
   t->kd = kd;
-  const int rc = set_lengths(t, fft_size_at_least(2 * K - 1), fft_size_at_least(2 * J - 1),
+  const int rc = set_lengths(t, fft_size_at_least(2 * K - 1), fft_size_at_least(2 * J - 1, true),
                              fft_size_at_least(2 * P - 1));
   if (rc != DDA_OK) {
     delete t;
@@ -643,7 +656,7 @@ int dda_target_set_padding(dda_target* t, int Kpp, int Jpp, int Ppp) {
   const int n[3] = {t->K, t->J, t->P};
   int v[3] = {Kpp, Jpp, Ppp};
   for (int a = 0; a < 3; ++a) {
-    if (v[a] == 0) v[a] = fft_size_at_least(2 * n[a] - 1);
+    if (v[a] == 0) v[a] = fft_size_at_least(2 * n[a] - 1, a == 1);
     if (!padding_ok(n[a], v[a]))
       return fail(DDA_EINVAL, "dda_target_set_padding: length %d for extent %d (needs >= %d, 2^a 3^b 5^c, <= %ld)",
                   v[a], n[a], 2 * n[a] - 1, std::max(16L, 4 * (2L * n[a] - 1)));
@@ -1031,6 +1044,13 @@ static int ensure_matvec_ws(dda_target* t, int nrhs) {
 template <int N>
 constexpr int fast_tx() {
   constexpr int T = FastPlan<N>::T;
+  if (FastPlan<N>::five) {
+    // (y passes only) a power-of-two tile of at least 128 threads, within
+    // 64 KB of FP64 LDS
+    int tx = 1;
+    while (T * tx < 128 && N * (2 * tx) * 16 <= 64 * 1024) tx *= 2;
+    return tx;
+  }
   int tx = 256 / T;
   if (tx < 16) tx = 512 / T < 16 ? 512 / T : 16;  // rows of >= 128 B where a 512-thread block allows
   return tx < 8 ? 8 : (tx > 64 ? 64 : tx);
@@ -1366,7 +1386,7 @@ static int yinv_blocks(const dda_target* t, int nrhs) {
   case N:                                                     \
     tx = FastLaunch<R>::template ytx<N>(ylog_of<R>(t, nrhs)); \
     break;
-    DDA_FAST_SIZES(DDA_CASE)
+    DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
     default:
       tx = tile_width<R>(t->K, t->Jpp, 2);
@@ -1478,14 +1498,14 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   }
   {
     PassTimer pt(t->lib, PASS_YFWD + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
-    if (fast_size(Jpp)) {
+    if (fast_y_size(Jpp)) {
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                         \
   case N:                                                                                                   \
     FastLaunch<R>::template yfwd<N>(ylog, st, x, G1, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), qf);                                        \
     break;
-        DDA_FAST_SIZES(DDA_CASE)
+        DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
       }
     } else {
@@ -1682,14 +1702,14 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   }
   {
     PassTimer pt(t->lib, PASS_YINV + (sizeof(R) == 4 ? PASS_PER_PREC : 0), st, own_ws);
-    if (fast_size(Jpp)) {
+    if (fast_y_size(Jpp)) {
       switch (Jpp) {
 #define DDA_CASE(N)                                                                                             \
   case N:                                                                                                       \
     FastLaunch<R>::template yinv<N>(ylog, st, G1, x, y, occ_of(t), a0, a1, dS, active, va, \
                                     b.tw[1].template as<cx<R>>(), dot);                                           \
     break;
-        DDA_FAST_SIZES(DDA_CASE)
+        DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
       }
     } else {
@@ -1762,7 +1782,7 @@ static int ylog_max(const dda_target* t) {
 #define DDA_CASE(N) \
   case N:           \
     return ytx_max_log<R, N>();
-    DDA_FAST_SIZES(DDA_CASE)
+    DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
   }
   return 0;
@@ -1878,11 +1898,12 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
 }
 
 // Padded lengths tried for lattice extent n: the smallest 2^a 3^b 5^c length
-// >= 2n - 1, and the smallest length with register-resident kernels when it
-// is at most twice that; the default rule's choice first.
-static std::vector<int> padding_candidates(int n) {
+// >= 2n - 1, and the smallest length with register-resident kernels for
+// every pass when it is at most twice that; the default rule's choice (for
+// y, `yax`, counting the register-resident y passes) first.
+static std::vector<int> padding_candidates(int n, bool yax) {
   const int m = 2 * n - 1;
-  std::vector<int> c = {fft_size_at_least(m)};
+  std::vector<int> c = {fft_size_at_least(m, yax)};
   int sm = m;
   while (!smooth235(sm)) ++sm;
   int f = m;
@@ -1926,7 +1947,8 @@ static int time_padding(dda_target* t, int nrhs, const cx<R>* x, cx<R>* y, hipSt
 
 template <typename R>
 static int tune_padding_T(dda_target* t, int nrhs, int precision, hipStream_t st) {
-  const std::vector<int> ck = padding_candidates(t->K), cj = padding_candidates(t->J), cp = padding_candidates(t->P);
+  const std::vector<int> ck = padding_candidates(t->K, false), cj = padding_candidates(t->J, true),
+                         cp = padding_candidates(t->P, false);
   std::vector<std::array<int, 3>> combos;
   for (int a : ck)
     for (int b : cj)
@@ -2164,13 +2186,13 @@ static int read_active(dda_target* t, int nrhs, hipStream_t st, int& n_active) {
 // right-hand side, or 0 if the step stays separate.
 template <typename R>
 static int qmr_fused_blocks(dda_target* t, int nrhs) {
-  if (is_fused(schedule_of<R>(t, nrhs)) || !fast_size(t->Jpp)) return 0;
+  if (is_fused(schedule_of<R>(t, nrhs)) || !fast_y_size(t->Jpp)) return 0;
   if ((double)t->nd < 0.9 * (double)t->K * t->J * t->P) return 0;
   switch (t->Jpp) {
 #define DDA_CASE(N) \
   case N:           \
     return FastLaunch<R>::template yfwd_blocks<N>(t, ylog_of<R>(t, nrhs));
-    DDA_FAST_SIZES(DDA_CASE)
+    DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
   }
   return 0;

@@ -21,23 +21,40 @@
 
 namespace dda {
 
+// odd part of n (n with every factor 2 divided out)
+constexpr int odd_part(int n) {
+  while (n % 2 == 0) n /= 2;
+  return n;
+}
+
+// Compile-time plan of a register-resident length: E values per thread, T
+// threads per line, the radix of every Stockham stage.  Lengths 2^k (radix
+// 8, then the remainder), 3 2^k (radix 4, then 2 where needed, then 3) and,
+// for the y passes only, 5 2^k and 25 2^k with 4 | N (radix 4, then 2 where
+// needed, then one or two radix-5 stages; 20 values per thread).
 template <int N>
 struct FastPlan {
   static constexpr bool pow2 = N >= 16 && (N & (N - 1)) == 0;
   static constexpr bool three = N >= 24 && N % 3 == 0 && ((N / 3) & (N / 3 - 1)) == 0;
-  static constexpr bool ok = pow2 || three;
-  static constexpr int E = pow2 ? 8 : 12;
+  static constexpr bool five = N >= 20 && N % 4 == 0 && (odd_part(N) == 5 || odd_part(N) == 25);
+  static constexpr bool ok = pow2 || three || five;
+  static constexpr int E = pow2 ? 8 : three ? 12 : 20;
   static constexpr int T = N / E;
   static constexpr int nst_calc() {
     int n = N, s = 0;
     if (pow2) {
-      while (n >= 8) { n /= 8; ++s; }
+      while (n >= E) { n /= E; ++s; }
       if (n > 1) ++s;
-    } else {
+    } else if (three) {
       n /= 3;
       while (n >= 4) { n /= 4; ++s; }
       if (n > 1) ++s;
       ++s;
+    } else {
+      n /= odd_part(N);
+      while (n >= 4) { n /= 4; ++s; }
+      if (n > 1) ++s;
+      s += odd_part(N) == 25 ? 2 : 1;
     }
     return s;
   }
@@ -45,14 +62,14 @@ struct FastPlan {
   static constexpr int radix(int s) {
     int n = N, i = 0;
     if (pow2) {
-      while (n >= 8) {
-        if (i == s) return 8;
-        n /= 8;
+      while (n >= E) {
+        if (i == s) return E;
+        n /= E;
         ++i;
       }
       return n;
     }
-    n /= 3;
+    n /= three ? 3 : odd_part(N);
     while (n >= 4) {
       if (i == s) return 4;
       n /= 4;
@@ -62,7 +79,7 @@ struct FastPlan {
       if (i == s) return n;
       ++i;
     }
-    return 3;
+    return three ? 3 : 5;
   }
   static constexpr int pbefore(int s) {
     int p = 1;

@@ -1269,19 +1269,23 @@ struct QmrFuse {
   int* active;
 };
 
-// Sum of ND complex values over a block of any multiple-of-64 size; fixed
+// Sum of ND complex values over a block of any size up to 1024 threads; fixed
 // order, result valid in thread 0.
 template <int ND>
 __device__ __forceinline__ void block_sum_n(c64 (&v)[ND]) {
   __shared__ c64 shn[ND][16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const int nact = min(64, (int)blockDim.x - (wv << 6));  // lanes of a last, partial wavefront
 #pragma unroll
   for (int q = 0; q < ND; ++q) {
     double a = v[q].x, b = v[q].y;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-      a += __shfl_down(a, off, 64);
-      b += __shfl_down(b, off, 64);
+      const double oa = __shfl_down(a, off, 64), ob = __shfl_down(b, off, 64);
+      if (lane + off < nact) {
+        a += oa;
+        b += ob;
+      }
     }
     if (lane == 0) shn[q][wv] = mk(a, b);
   }

@@ -63,6 +63,13 @@ PADDINGS = [
     ((12, 12, 12), (32, 32, 32)),
     ((16, 8, 10), (32, 16, 20)),
     ((16, 8, 10), (45, 15, 24)),
+    # register-resident y passes of lengths 5 2^k and 25 2^k (radix-5 stages)
+    ((7, 40, 5), (16, 80, 12)),
+    ((5, 50, 4), (12, 100, 8)),
+    ((4, 80, 3), (8, 160, 6)),
+    ((3, 100, 3), (6, 200, 5)),
+    ((3, 160, 2), (6, 320, 4)),
+    ((2, 200, 2), (4, 400, 4)),
 ]
 
 
@@ -185,3 +192,17 @@ def test_tune_padding_picks_a_candidate_and_records_it(dda, tmp_path):
     assert t2.tune_padding(2, "fp32") == pads
     _close(t2.matvec(torch.from_numpy(x).cuda()).cpu().numpy()[0], yo, 1e-12)
     assert [l for l in open(path).read().splitlines() if l.startswith("pad ")] == lines
+
+
+def test_default_rule_counts_the_radix5_y_lengths(dda, lib):
+    """The default padded lengths: J'' takes 5 2^k or 25 2^k where a
+    register-resident y pass exists for it (J = 40, 100, 200 -> 80, 200,
+    400), K'' and P'' the lengths with register-resident passes in every
+    direction within 30% (100 -> 256, 200 -> 512, 7 -> 16), and the smallest
+    2^a 3^b 5^c length otherwise (9 -> 18)."""
+    cases = {(100, 40, 200): (256, 80, 512), (200, 100, 7): (512, 200, 16), (9, 200, 100): (18, 400, 256)}
+    for (K, J, P), want in cases.items():
+        t = dda.Target(lib, K, J, P, 0.3)
+        i = t.info()
+        assert (i["Kpp"], i["Jpp"], i["Ppp"]) == want, ((K, J, P), i)
+        t.close()

@@ -426,14 +426,16 @@ def test_matvec_two_level_z_pass(lib, shape, rb, sched):
 
 
 @pytest.mark.parametrize("ylog", [0, 1, 2])
-@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 16, 5), (13, 24, 7), (5, 12, 9), (9, 64, 6), (5, 128, 4)])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 16, 5), (13, 24, 7), (5, 12, 9), (9, 64, 6), (5, 128, 4),
+                                   (3, 40, 4), (4, 50, 3), (3, 80, 3), (2, 100, 4), (2, 160, 2), (2, 200, 3)])
 def test_y_tile_variants(lib, shape, ylog):
     """DDA_OPT_Y_TILE: the y passes with 2^ylog times the default tile
     (ragged last tiles where K is not a multiple of it; padded y lengths 24
-    to 256) against the dense oracle element by element in FP64 and FP32; a
-    QMR_sym solve whose step is fused into the widened y-forward pass (its
-    partial counts follow the tile) against the oracle's LU.  A width FP32
-    lacks is DDA_EINVAL."""
+    to 256, and 80, 100, 160, 200, 320, 400 of the radix-5 kernels, whose
+    blocks of 160 threads end in a partial wavefront) against the dense
+    oracle element by element in FP64 and FP32; a QMR_sym solve whose step
+    is fused into the widened y-forward pass (its partial counts follow the
+    tile) against the oracle's LU.  A width FP32 lacks is DDA_EINVAL."""
     from paper_0908_0863_amd import dda
     K, J, P = shape
     occ = np.ones((P, J, K), np.uint8)  # a filled lattice keeps the QMR step fused
