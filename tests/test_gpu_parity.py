@@ -387,6 +387,16 @@ def test_graph_replay_matches_eager(lib, solver, param, precision):
 
 # padded x = padded y: fused xy-plane passes apply; the last two have P'' = 64 and 128
 FUSED_SHAPES = [(16, 16, 16), (32, 30, 5), (45, 40, 3), (10, 10, 32), (12, 12, 64)]
+
+
+def _square_xy(t):
+    """The fused xy schedules need K'' = J'': where the default rule pads y
+    to a shorter register-resident length (J = 40: 80 against K'' = 96), pad
+    it to K'' instead."""
+    i = t.info()
+    if i["Kpp"] != i["Jpp"]:
+        t.set_padding(i["Kpp"], i["Kpp"], i["Ppp"])
+        t.build_spectrum()
 # every z length of the two-level z pass (P'' = 16, 24, 48, 96, 192, 256), with
 # ragged column tiles (K'' not a multiple of the tile) and odd x, y extents
 Z2_SHAPES = [(5, 3, 8), (7, 9, 12), (3, 4, 24), (9, 5, 48), (6, 7, 96), (5, 3, 128)]
@@ -478,6 +488,7 @@ def test_matvec_fused_and_five_pass_schedules(lib, shape, sched, jacobi):
     occ = inputs.sphere(16) if shape == (16, 16, 16) else _rand_occ((P, J, K), 12)
     kd, eps = 0.42, 2.2 + 0.15j
     t, nd = _target(lib, occ, kd, eps)
+    _square_xy(t)
     i = t.info()
     assert i["Kpp"] == i["Jpp"]
     try:
@@ -509,6 +520,8 @@ def test_pruned_passes_never_read_unwritten_workspace(lib, shape, sched):
     occ = inputs.sphere(16) if shape == (16, 16, 16) else _rand_occ((P, J, K), 12)
     kd, eps = 0.42, 2.2 + 0.15j
     t, nd = _target(lib, occ, kd, eps)
+    if shape in FUSED_SHAPES:
+        _square_xy(t)
     try:
         t.set_option(dda.DDA_OPT_SCHEDULE, sched)
     except dda.DDAError:
