@@ -355,10 +355,12 @@ int dda_target_set_padding(dda_target *t, int Kpp, int Jpp, int Ppp);
  * must beat the default rule's by more than 3%.  The target keeps the
  * fastest lengths with their spectrum built, and lengths[0..2] (may be NULL)
  * receives them.  The choice is kept in the library handle per (lattice,
- * nrhs, precision) and appended to the tune-cache file, so a later call only
- * sets the lengths and builds the spectrum.  Needs the occupancy and the
- * polarisability (DDA_ESTATE otherwise); DDA_EINVAL for nrhs < 1 or an
- * unknown precision.  Allocates and frees two vectors of nrhs x 3 x N_d. */
+ * nrhs, precision, forced schedule) and appended to the tune-cache file, so a
+ * later call only sets the lengths and builds the spectrum.  Needs the
+ * occupancy and the polarisability (DDA_ESTATE otherwise); DDA_EINVAL for
+ * nrhs < 1 or an unknown precision.  If a measurement fails, the target
+ * is back at the lengths it had, without a spectrum (build it again), and the
+ * error is returned.  Allocates and frees two vectors of nrhs x 3 x N_d. */
 int dda_tune_padding(dda_target *t, int nrhs, int precision, int *lengths /* 3, or NULL */, void *hip_stream);
 
 /* Copy the spectrum [6][P_h][J_h][K_h] (complex128 or complex64) to out_dev. */

@@ -1914,10 +1914,13 @@ static std::vector<int> padding_candidates(int n, bool yax) {
   return c;
 }
 
+// (a forced schedule narrows the candidate list, so it is part of the key:
+// the recorded value is an index into that list)
 static std::string padding_key(const dda_target* t, int nrhs, int precision) {
   std::ostringstream k;
   k << "pad " << t->K << "x" << t->J << "x" << t->P << " nrhs " << nrhs << " "
     << (precision == DDA_FP32 ? "fp32" : "fp64");
+  if (t->forced_sched > 0) k << " schedule " << t->forced_sched;
   return k.str();
 }
 
@@ -1965,6 +1968,7 @@ static int tune_padding_T(dda_target* t, int nrhs, int precision, hipStream_t st
   }
   if (pick < 0 && combos.size() == 1) pick = 0;
   if (pick < 0) {
+    const int k0 = t->Kpp, j0 = t->Jpp, p0 = t->Ppp;
     // product inputs: a fixed finite byte pattern (timing only), S = 0
     DevBuf xb, yb;
     const size_t vb = (size_t)nrhs * 3 * t->nd * sizeof(cx<R>);
@@ -1995,8 +1999,14 @@ static int tune_padding_T(dda_target* t, int nrhs, int precision, hipStream_t st
     (void)hipEventDestroy(e1);
     t->lib->prof = prof;
     t->matvecs = mv;
+    if (rc != DDA_OK) {  // back to the lengths the target had (its spectrum dropped)
+      (void)hipStreamSynchronize(st);
+      const std::string err = g_err;
+      (void)set_lengths(t, k0, j0, p0);
+      g_err = err;
+      return rc;
+    }
     HIPCHK(hipStreamSynchronize(st));  // the timing buffers are freed on return
-    CHK(rc);
     std::lock_guard<std::mutex> g(t->lib->tune_mu);
     if (!t->lib->tuned.count(key)) {
       t->lib->tuned[key] = pick;
