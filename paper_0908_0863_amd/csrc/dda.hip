@@ -110,7 +110,8 @@ static bool fast_size(int n) {
       return false;
   }
 }
-// ... and those with register-resident y passes: the above and 5 2^k, 25 2^k
+// ... and those with register-resident y passes and transposing x passes
+// (the z-contiguous schedule): the above and 5 2^k, 25 2^k
 #define DDA_FAST_Y_SIZES(X) DDA_FAST_SIZES(X) X(80) X(160) X(320) X(100) X(200) X(400)
 static bool fast_y_size(int n) {
   switch (n) {
@@ -1313,7 +1314,7 @@ static std::vector<int> xy_candidates(const dda_target* t) {
 // why schedule `value` does not exist for a lattice padded to Kpp x Jpp x
 // Ppp (nullptr: it exists in both precisions)
 static const char* schedule_missing(int value, int K, int J, int Kpp, int Jpp, int Ppp) {
-  if (value == 1 && !(fast_size(Kpp) && fast_size(Ppp))) return "no z-contiguous schedule";
+  if (value == 1 && !(fast_y_size(Kpp) && fast_size(Ppp))) return "no z-contiguous schedule";
   if (value == 3 && !fast_size(Ppp)) return "no component-split z pass";
   if (value == 5 && !z2_size(Ppp)) return "no two-level z pass";
   if (value == 6 && !(z2_size(Ppp) && fast_size(Kpp))) return "no tile-blocked schedule";
@@ -1575,8 +1576,10 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   case N:                                                                                         \
     FastLaunch<R>::template xT<N>(false, nrhs, st, G1, G2, t, active, b.tw[0].template as<cx<R>>()); \
     break;
-        DDA_FAST_SIZES(DDA_CASE)
+        DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
+        default:
+          return fail(DDA_EINVAL, "matvec: no transposing x pass of length %d", Kpp);
       }
       LAUNCHCHK();
     }
@@ -1608,8 +1611,10 @@ static int matvec_passes(dda_target* t, int nrhs, const double* dS, int jacobi, 
   case N:                                                                                        \
     FastLaunch<R>::template xT<N>(true, nrhs, st, G2, G1, t, active, b.tw[0].template as<cx<R>>()); \
     break;
-        DDA_FAST_SIZES(DDA_CASE)
+        DDA_FAST_Y_SIZES(DDA_CASE)
 #undef DDA_CASE
+        default:
+          return fail(DDA_EINVAL, "matvec: no transposing x pass of length %d", Kpp);
       }
       LAUNCHCHK();
     }
@@ -1798,7 +1803,7 @@ static int autotune(dda_target* t, int nrhs, const double* dS, int jacobi, const
     if (t->lib->tuned.count(key)) return DDA_OK;
   }
   std::vector<int> cand = {0};
-  if (fast_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
+  if (fast_y_size(t->Kpp) && fast_size(t->Ppp)) cand.push_back(1);
   if (fast_size(t->Ppp)) cand.push_back(3);
   // the tile-blocked schedule before the strided one: it measured as fast or
   // faster on every workload here, so near-ties keep it

@@ -854,9 +854,18 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RK) k_xT_fwd(const cx<R>* __r
   for (int m = 0; m < E; ++m) lds[(t + T * m) * RKP + rw] = v[m];
   __syncthreads();
   cx<R>* dst = G2t + (((long)rc * Jpp + jj) * N) * P + k0;
-  for (int idx = threadIdx.x; idx < N * RK; idx += blockDim.x) {
+  // E values per thread: every LDS read first, then the E stores
+  cx<R> st[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = threadIdx.x + q * (T * RK);
+    st[q] = lds[(idx / RK) * RKP + idx % RK];
+  }
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = threadIdx.x + q * (T * RK);
     const int r = idx % RK, i = idx / RK;
-    if (k0 + r < P) dst[(long)i * P + r] = lds[i * RKP + r];
+    if (k0 + r < P) dst[(long)i * P + r] = st[q];
   }
 }
 
@@ -872,9 +881,19 @@ __global__ void __launch_bounds__(FastPlan<N>::T * RK) k_xT_inv(const cx<R>* __r
   const int rc = blockIdx.z, jj = blockIdx.y, k0 = blockIdx.x * RK;
   if (active && !active[rc / 3]) return;
   const cx<R>* src = G2t + (((long)rc * Jpp + jj) * N) * P + k0;
-  for (int idx = threadIdx.x; idx < N * RK; idx += blockDim.x) {
+  // the block's N x RK values are E per thread: all E loads are issued
+  // before the first LDS store, so they are in flight together
+  cx<R> ld[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = threadIdx.x + q * (T * RK);
     const int r = idx % RK, i = idx / RK;
-    lds[i * RKP + r] = (k0 + r < P) ? src[(long)i * P + r] : mk((R)0, (R)0);
+    ld[q] = (k0 + r < P) ? src[(long)i * P + r] : mk((R)0, (R)0);
+  }
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = threadIdx.x + q * (T * RK);
+    lds[(idx / RK) * RKP + idx % RK] = ld[q];
   }
   __syncthreads();
   const int rw = threadIdx.x / T, t = threadIdx.x % T;

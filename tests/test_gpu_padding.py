@@ -194,6 +194,33 @@ def test_tune_padding_picks_a_candidate_and_records_it(dda, tmp_path):
     assert [l for l in open(path).read().splitlines() if l.startswith("pad ")] == lines
 
 
+@pytest.mark.parametrize("shape,pads", [((40, 3, 5), (80, 6, 16)), ((50, 4, 3), (100, 8, 16)),
+                                        ((80, 2, 4), (160, 4, 16)), ((100, 2, 3), (200, 4, 16)),
+                                        ((160, 2, 2), (320, 4, 16)), ((200, 2, 2), (400, 4, 16))])
+def test_z_contiguous_schedule_at_radix5_x_lengths(dda, lib, shape, pads):
+    """Schedule 1 (transposing x passes, z lines contiguous) at K'' = 5 2^k
+    and 25 2^k (radix-5 stages in the x passes, blocks ending in a partial
+    wavefront): the product equals the dense one element by element."""
+    K, J, P = shape
+    occ = _occ((P, J, K), 18)
+    kd, eps = 0.38, 1.7 + 0.12j
+    t, nd = _target(dda, lib, occ, kd, eps)
+    t.set_padding(*pads)
+    t.build_spectrum()
+    t.set_option(dda.DDA_OPT_SCHEDULE, 1)
+    sites = ora.sites_of(occ)
+    S = [0.0, 0.3]
+    x = inputs.complex_gaussian(19, (2, 3, nd))
+    y = t.matvec(torch.from_numpy(x).cuda(), S=S, jacobi=True).cpu().numpy()
+    y32 = t.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), S=S, jacobi=True).cpu().numpy()
+    for r in range(2):
+        ainv = ora.alpha_inv(np.full(nd, eps), kd, "ldr", S[r])
+        s = 1.0 / np.sqrt(ainv)
+        yo = s * ora.dense_matvec(sites, kd, ainv, s * x[r])
+        _close(y[r], yo, 1e-12, (shape, pads, r))
+        _close(y32[r], yo, 2e-6, (shape, pads, r))
+
+
 def test_default_rule_counts_the_radix5_y_lengths(dda, lib):
     """The default padded lengths: J'' takes 5 2^k or 25 2^k where a
     register-resident y pass exists for it (J = 40, 100, 200 -> 80, 200,
