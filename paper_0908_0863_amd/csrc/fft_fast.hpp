@@ -30,8 +30,9 @@ constexpr int odd_part(int n) {
 // Compile-time plan of a register-resident length: E values per thread, T
 // threads per line, the radix of every Stockham stage.  Lengths 2^k (radix
 // 8, then the remainder), 3 2^k (radix 4, then 2 where needed, then 3) and,
-// for the y passes only, 5 2^k and 25 2^k with 4 | N (radix 4, then 2 where
-// needed, then one or two radix-5 stages; 20 values per thread).
+// for the y passes and the transposing x passes only, 5 2^k and 25 2^k with
+// 4 | N (radix 4, then 2 where needed, then one or two radix-5 stages; 20
+// values per thread, T not always a power of two).
 template <int N>
 struct FastPlan {
   static constexpr bool pow2 = N >= 16 && (N & (N - 1)) == 0;
