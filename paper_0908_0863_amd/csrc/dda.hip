@@ -2773,10 +2773,13 @@ static int inner_solve(dda_target* t, int solver, int param, int nrhs, const dou
 // FP64 true residual r = E - A P for all right-hand sides; returns |r|^2 and
 // |E|^2 per right-hand side on the host.
 static int true_residual(dda_target* t, int nrhs, const c64* E, const c64* Pv, c64* r, c64* y, hipStream_t st,
-                         std::vector<double>& rn2, std::vector<double>& en2) {
+                         std::vector<double>& rn2, std::vector<double>& en2, bool p_zero = false) {
   CHK(ensure_matvec_ws<double>(t, nrhs));
   CHK(autotune<double>(t, nrhs, t->S.as<double>(), 0, Pv, y, st));
-  CHK(matvec_T<double>(t, nrhs, t->S.as<double>(), 0, Pv, y, nullptr, st));
+  if (p_zero)  // A 0 = 0 (the product of a zero vector is exactly zero)
+    HIPCHK(hipMemsetAsync(y, 0, (size_t)nrhs * 3 * t->nd * sizeof(c64), st));
+  else
+    CHK(matvec_T<double>(t, nrhs, t->S.as<double>(), 0, Pv, y, nullptr, st));
   SolverDims dm;
   dm.n3 = 3 * t->nd;
   dm.nblk = nblocks_for(dm.n3);
@@ -2849,9 +2852,8 @@ static int solve_core(dda_target* t, const dda_solve_opts& o, int nrhs, const c6
   const int mv0 = t->matvecs;
   HIPCHK(hipMemsetAsync(Pv, 0, (size_t)nrhs * n3 * sizeof(c64), st));
   std::vector<double> rn2, en2;
-  // P = 0: the residual is E
-  HIPCHK(hipMemcpyAsync(r64, E, (size_t)nrhs * n3 * sizeof(c64), hipMemcpyDeviceToDevice, st));
-  CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2));
+  // P = 0: the residual is E (and no product is needed for it)
+  CHK(true_residual(t, nrhs, E, Pv, r64, y64, st, rn2, en2, true));
   for (int q = 0; q < nrhs; ++q)
     if (!std::isfinite(en2[q])) return fail(DDA_EINVAL, "dda_solve: right-hand side %d is not finite", q);
   std::vector<int> iters(nrhs, 0), outer(nrhs, 0), done(nrhs, 0);
