@@ -233,3 +233,26 @@ def test_default_rule_counts_the_radix5_y_lengths(dda, lib):
         i = t.info()
         assert (i["Kpp"], i["Jpp"], i["Ppp"]) == want, ((K, J, P), i)
         t.close()
+
+
+def test_tune_padding_keeps_a_forced_schedule(dda, tmp_path):
+    """With schedule 6 forced (tile-blocked array: K'' register-resident and a
+    two-level z length), only the candidates that carry it are timed, the
+    product still equals the dense one, and the record's key names the
+    schedule."""
+    path = str(tmp_path / "tune.txt")
+    lib1 = dda.Library(0, tune_cache=path)
+    occ = _occ((5, 6, 5), 21)
+    kd, eps = 0.45, 1.8 + 0.05j
+    t, nd = _target(dda, lib1, occ, kd, eps)
+    t.set_padding(16, 16, 16)
+    t.build_spectrum()
+    t.set_option(dda.DDA_OPT_SCHEDULE, 6)
+    pads = t.tune_padding(1, "fp32")
+    assert pads[0] == 16 and pads[2] == 16 and pads[1] in (12, 16), pads
+    lines = [l for l in open(path).read().splitlines() if l.startswith("pad ")]
+    assert len(lines) == 1 and lines[0].startswith("pad 5x6x5 nrhs 1 fp32 schedule 6 = "), lines
+    sites = ora.sites_of(occ)
+    x = inputs.complex_gaussian(22, (1, 3, nd))
+    yo = ora.dense_matvec(sites, kd, ora.alpha_inv(np.full(nd, eps), kd, "ldr", 0.0), x[0])
+    _close(t.matvec(torch.from_numpy(x).cuda()).cpu().numpy()[0], yo, 1e-12)
